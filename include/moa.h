@@ -1,0 +1,238 @@
+/*
+ * moa.h -- C ABI of the MoA ONF matrix-product library for AMD Instinct
+ * MI355X (gfx950 / CDNA4).
+ *
+ * The operation (Mullin, "From array algebra to energy efficiency on GPUs",
+ * section "MoA Matrix Multiplication", Eq. 1-3): with shapes
+ *     rho A = <m, n>,  rho B = <n, p>,  rho C = <m, p>
+ * and all three arrays stored row-major and contiguous from their base
+ * addresses (the address form that follows Eq. 3; no strides, no padding),
+ *     C[i*p + j] := sum_{k=0}^{n-1} A[i*n + k] * B[k*p + j]
+ * for 0 <= i < m, 0 <= j < p (index bounds of Eq. 2). The paper's generic C
+ * program adds into C instead of assigning; `accumulate != 0` selects that
+ * form (C += A.B), `accumulate == 0` the assignment of Eq. 3.
+ *
+ * Conventions for every call below:
+ *  - Sizes are int64_t and may exceed 2^31 elements. m, n or p may be 0:
+ *    n == 0 is the empty sum (C := 0, or C unchanged when accumulating);
+ *    m == 0 or p == 0 writes nothing.
+ *  - Matrix pointers are DEVICE pointers on the current HIP device, owned by
+ *    the caller, aligned to at least the element size; 16-byte alignment is
+ *    recommended (other alignments are accepted). The library never frees
+ *    them; they must stay valid until the work on `stream` has completed.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Calls are asynchronous on it unless stated otherwise.
+ *  - Argument errors are returned synchronously and nothing is launched.
+ *    A failed launch returns MOA_ERR_DEVICE. No C++ exception crosses the
+ *    ABI. moa_last_error() gives a thread-local message for the last error.
+ *  - Calls on different streams may run concurrently; each call uses only
+ *    its own arguments and, where it needs scratch space, memory taken from
+ *    the stream-ordered allocator on the same stream.
+ */
+#ifndef MOA_H
+#define MOA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum moa_status {
+    MOA_OK = 0,
+    MOA_ERR_INVALID = 1,      /* null pointer, bad enum, aliasing, bad count */
+    MOA_ERR_SHAPE = 2,        /* negative size or size overflow */
+    MOA_ERR_UNSUPPORTED = 3,  /* dtype/path combination not provided */
+    MOA_ERR_NOMEM = 4,        /* scratch allocation failed / over budget */
+    MOA_ERR_DEVICE = 5,       /* HIP error from a launch or runtime call */
+    MOA_NOT_READY = 6         /* serving: request not finished yet */
+} moa_status;
+
+typedef enum moa_dtype {
+    MOA_F64 = 0,              /* double A, B, C */
+    MOA_F32 = 1               /* float A, B, C */
+} moa_dtype;
+
+/* How the contraction is carried out. Every path computes Eq. 3; they
+ * differ in arithmetic:
+ *  ONF          -- scalar fused multiply-add, k ascending for every element
+ *                  (the paper's loop order); FP64 or FP32. Bitwise equal to
+ *                  the same loop with one fma per step.
+ *  MFMA_F32     -- FP32 matrix-core tiles (v_mfma_f32_32x32x2_f32), FP32
+ *                  accumulation. F32 only.
+ *  SPLIT_BF16   -- each FP32 input x is split into hi = RNE_bf16(x) and
+ *                  lo = RNE_bf16(x - hi); C = hi.hi + hi.lo + lo.hi on BF16
+ *                  matrix cores with FP32 accumulation. F32 only.
+ *  FP8_SCALED   -- row i of A is scaled by 2^e_i and column j of B by 2^f_j
+ *                  (e the largest integer with amax * 2^e <= 448), rounded
+ *                  to OCP E4M3, multiplied on FP8 matrix cores with FP32
+ *                  accumulation and descaled exactly by 2^-(e_i+f_j).
+ *                  With MOA_FLAG_FP8_TWO_TERM the rounding residual is kept
+ *                  as a second E4M3 term (stored times 2^4) and
+ *                  C = 2^-(e_i+f_j) (h.h + 2^-4 (h.l + l.h)). F32 only.
+ *  AUTO         -- ONF for F64, SPLIT_BF16 for F32.
+ * The split and FP8 paths require finite inputs. */
+typedef enum moa_path {
+    MOA_PATH_AUTO = 0,
+    MOA_PATH_ONF = 1,
+    MOA_PATH_MFMA_F32 = 2,
+    MOA_PATH_SPLIT_BF16 = 3,
+    MOA_PATH_FP8_SCALED = 4
+} moa_path;
+
+#define MOA_FLAG_FP8_TWO_TERM 0x1u
+/* Forces instantiation `v` (0-based) of the path's kernel table instead of
+ * the planner's choice: the block sizes of the dimension lift, for block-size
+ * sweeps and autotuning (moa_plan_query reports the resulting shape). An
+ * index beyond the table is MOA_ERR_INVALID. Occupies flag bits 8..15. */
+#define MOA_FLAG_VARIANT(v) ((uint32_t)((v) + 1) << 8)
+#define MOA_FLAG_VARIANT_MASK 0xFF00u
+
+/* One matrix product. Field names follow Eq. 1: m rows of A and C, n the
+ * shared extent (rho B[0]), p columns of B and C. */
+typedef struct moa_gemm_desc {
+    int64_t m, n, p;
+    int32_t dtype;            /* moa_dtype */
+    int32_t path;             /* moa_path */
+    const void *A;            /* device, m*n elements, row-major */
+    const void *B;            /* device, n*p elements, row-major */
+    void *C;                  /* device, m*p elements, row-major; must not
+                                 overlap A or B */
+    int32_t accumulate;       /* 0: C := A.B (Eq. 3); else C += A.B */
+    uint32_t flags;           /* MOA_FLAG_* */
+} moa_gemm_desc;
+
+/* The dimension lift chosen for a product: how i, j and k are split over
+ * workgroups, waves, lanes and LDS slabs (section "Dimension Lifting to
+ * Machine Coordinates"), plus the paper's static block size for the type. */
+typedef struct moa_plan_info {
+    int32_t path;             /* resolved moa_path */
+    int32_t kernel;           /* internal kernel id (for reports) */
+    int32_t tile_m, tile_n;   /* C block per workgroup (rows x cols) */
+    int32_t tile_k;           /* k slab staged in LDS per step */
+    int32_t wave_m, wave_n;   /* C block per wavefront */
+    int32_t lane_m, lane_n;   /* C block per lane (ONF) or 0 (matrix cores) */
+    int32_t threads;          /* threads per workgroup */
+    int32_t lds_bytes;        /* LDS per workgroup */
+    int64_t workgroups;       /* grid size */
+    int64_t workspace_bytes;  /* scratch taken from the stream allocator */
+    int64_t static_components;/* static block size rule result (components) */
+} moa_plan_info;
+
+/* Eq. 3 on the device. Asynchronous on `stream`.
+ * Errors: MOA_ERR_INVALID (null desc/pointers with non-empty sizes, C
+ * overlapping A or B, unknown enum or flag), MOA_ERR_SHAPE (negative size,
+ * element count overflow), MOA_ERR_UNSUPPORTED (F64 with a matrix-core path),
+ * MOA_ERR_NOMEM (scratch), MOA_ERR_DEVICE (launch failure). */
+moa_status moa_gemm(const moa_gemm_desc *desc, void *stream);
+
+/* `count` independent products in one persistent launch per path (all
+ * members with the same resolved path share one launch). Members must not
+ * write overlapping C. No ordering among members. Each result is bitwise the
+ * result moa_gemm gives for the same descriptor. Descriptors are read on the
+ * host during the call; the array may be reused when the call returns.
+ * Errors: as moa_gemm, checked for every member before anything launches;
+ * MOA_ERR_INVALID for count < 0 or a null array with count > 0. */
+moa_status moa_gemm_grouped(const moa_gemm_desc *descs, int64_t count,
+                            void *stream);
+
+/* The plan moa_gemm would use for `desc` (no launch; pointers may be null).
+ * Returns the same argument errors as moa_gemm. */
+moa_status moa_plan_query(const moa_gemm_desc *desc, moa_plan_info *out);
+
+/* Block-size rule of section "Technical Details": the largest power of two b
+ * with nblocks * b * elem_bytes <= budget_bytes (one block each of A, B and C
+ * per processor memory: nblocks = 3). Returns 0 if none fits or an argument
+ * is not positive. Pure host function. */
+int64_t moa_static_block_components(int64_t budget_bytes, int64_t elem_bytes,
+                                    int64_t nblocks);
+
+/* Operand conditioning of the split-BF16 path, exposed so that it can be
+ * checked on its own: X is rows x cols FP32 row-major (device);
+ * hi[t] = RNE_bf16(X[t]), lo[t] = RNE_bf16(X[t] - hi[t]) as raw BF16 bit
+ * patterns (uint16), written row-major with the same shape. Asynchronous.
+ * Errors: MOA_ERR_INVALID for null pointers with rows*cols > 0. */
+moa_status moa_split_bf16(const float *X, int64_t rows, int64_t cols,
+                          uint16_t *hi, uint16_t *lo, void *stream);
+
+/* Operand conditioning of the FP8 path, exposed for checking: for A (m x n)
+ * writes e[i] (int32, per row) and qA (m x n E4M3 codes, row-major); for B
+ * (n x p) writes f[j] (per column) and qB (n x p codes, row-major). With
+ * two_term != 0 also writes the residual codes lA, lB (else they may be
+ * null). Device pointers; asynchronous. */
+moa_status moa_quantise_fp8(const float *A, int64_t m, int64_t n,
+                            const float *B, int64_t p, int32_t two_term,
+                            int32_t *e, uint8_t *qA, uint8_t *lA,
+                            int32_t *f, uint8_t *qB, uint8_t *lB,
+                            void *stream);
+
+/* Error norm in FP64 on the device: out[0] = sum_t (X[t] - R[t])^2 and
+ * out[1] = sum_t R[t]^2 over `count` elements, X of type `x_dtype`
+ * (moa_dtype), R double. `out` is a device array of 2 doubles. The
+ * normwise relative error is sqrt(out[0] / out[1]). Deterministic order.
+ * Asynchronous. */
+moa_status moa_error_norm(int64_t count, int32_t x_dtype, const void *X,
+                          const double *R, double *out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Serving: a request loop that admits products of mixed shapes under an HBM
+ * budget and batches them into grouped launches on several streams
+ * (continuous batching: requests that arrive while others run are admitted
+ * as slots and memory free up).
+ * ---------------------------------------------------------------------- */
+typedef struct moa_server moa_server;
+
+typedef struct moa_serve_cfg {
+    int64_t hbm_budget_bytes; /* admission bound on bytes held by in-flight
+                                 requests (operands, result and scratch) */
+    int32_t slots;            /* concurrent groups in flight (streams), >= 1 */
+    int32_t max_group;        /* most requests per grouped launch, >= 1 */
+    int32_t device;           /* HIP device ordinal */
+    int32_t reserved;
+} moa_serve_cfg;
+
+typedef struct moa_req_info {
+    int64_t t_submit_ns;      /* CLOCK_MONOTONIC at moa_serve_submit */
+    int64_t t_admit_ns;       /* admitted under the budget */
+    int64_t t_start_ns;       /* its group's launch was enqueued */
+    int64_t t_done_ns;        /* completion observed by the scheduler */
+    int32_t status;           /* moa_status of the request */
+    int32_t group_size;       /* members of the launch it ran in */
+} moa_req_info;
+
+/* Starts the scheduler thread. Errors: MOA_ERR_INVALID (null, slots < 1,
+ * max_group < 1, budget <= 0), MOA_ERR_DEVICE. */
+moa_status moa_serve_create(const moa_serve_cfg *cfg, moa_server **out);
+
+/* Queues one product (descriptor copied). The operands are caller-owned
+ * device memory that must stay valid until the request completes. Returns a
+ * ticket. Errors: argument errors as moa_gemm; MOA_ERR_NOMEM if the request
+ * alone exceeds the whole budget. Thread-safe. */
+moa_status moa_serve_submit(moa_server *srv, const moa_gemm_desc *desc,
+                            uint64_t *ticket);
+
+/* MOA_OK and the timestamps once the request is done (its C is final),
+ * MOA_NOT_READY before, MOA_ERR_INVALID for an unknown ticket. A completed
+ * ticket may be polled any number of times. Thread-safe. */
+moa_status moa_serve_poll(moa_server *srv, uint64_t ticket,
+                          moa_req_info *out);
+
+/* Waits until every submitted request is done. */
+moa_status moa_serve_drain(moa_server *srv);
+
+/* Drains, stops the scheduler and frees the server. */
+moa_status moa_serve_destroy(moa_server *srv);
+
+/* Static string for a status code. */
+const char *moa_status_string(moa_status s);
+
+/* Thread-local description of the last error returned on this thread
+ * ("" if none). Valid until the next call on the same thread. */
+const char *moa_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MOA_H */

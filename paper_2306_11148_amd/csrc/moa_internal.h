@@ -1,0 +1,99 @@
+// Internal declarations shared by the HIP kernels and the C-ABI runtime.
+// Nothing here is part of the public ABI (include/moa.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+
+#include "moa.h"
+
+namespace moa {
+
+// ---------------------------------------------------------------- errors --
+void set_last_error(const std::string &msg);
+moa_status fail(moa_status s, const char *fmt, ...)
+    __attribute__((format(printf, 2, 3)));
+moa_status hip_fail(hipError_t e, const char *what);
+
+// ----------------------------------------------------------------- plans --
+// Kernel identities (reported through moa_plan_info::kernel).
+enum KernelId : int32_t {
+    K_NONE = 0,
+    K_ONF_F64 = 1,
+    K_ONF_F32 = 2,
+    K_MFMA_F32 = 3,
+    K_SPLIT_BF16 = 4,
+    K_FP8 = 5,
+    K_FP8_2TERM = 6,
+};
+
+// The dimension lift of one product: i -> (workgroup row block, lane rows),
+// j -> (workgroup column block, lane columns), k -> (LDS slab, in-slab).
+struct Plan {
+    moa_path path = MOA_PATH_AUTO;
+    KernelId kernel = K_NONE;
+    int variant = 0;          // index into the kernel's instantiation table
+    int tile_m = 0, tile_n = 0, tile_k = 0;
+    int wave_m = 0, wave_n = 0;
+    int lane_m = 0, lane_n = 0;
+    int threads = 256;
+    int lds_bytes = 0;
+    int64_t workgroups = 0;
+    int64_t workspace_bytes = 0;
+    int64_t static_components = 0;
+};
+
+// Validates `d` (shapes, pointers, enums, aliasing) without touching the
+// device. `need_ptrs` = false skips pointer checks (plan queries).
+moa_status validate(const moa_gemm_desc &d, bool need_ptrs);
+moa_path resolve_path(const moa_gemm_desc &d);
+moa_status make_plan(const moa_gemm_desc &d, Plan *out);
+
+// gfx950 constants used by the static rule and the planner.
+constexpr int64_t kL1Bytes = 32 * 1024;        // vector L1 per CU
+constexpr int64_t kLdsBytes = 160 * 1024;      // LDS per CU
+constexpr int kNumCUs = 256;
+constexpr int kNumXCDs = 8;
+
+int64_t static_block_components(int64_t budget, int64_t elem, int64_t nblocks);
+
+// --------------------------------------------------------------- kernels --
+// Each launcher enqueues the whole product for `d` on `stream` using `plan`
+// and returns the first HIP error.
+hipError_t launch_onf(const moa_gemm_desc &d, const Plan &plan, hipStream_t stream);
+int onf_variant_count(moa_dtype t);
+void onf_variant_shape(moa_dtype t, int v, Plan *p);
+
+hipError_t launch_mfma_f32(const moa_gemm_desc &d, const Plan &plan, hipStream_t stream);
+void mfma_f32_shape(Plan *p);
+
+hipError_t launch_split_bf16(const moa_gemm_desc &d, const Plan &plan, hipStream_t stream);
+void split_bf16_shape(int variant, Plan *p);
+int split_bf16_variant_count();
+
+hipError_t launch_fp8(const moa_gemm_desc &d, const Plan &plan, void *workspace,
+                      hipStream_t stream);
+void fp8_shape(bool two_term, Plan *p);
+int64_t fp8_workspace_bytes(int64_t m, int64_t n, int64_t p, bool two_term);
+
+hipError_t launch_split_only(const float *X, int64_t count, uint16_t *hi, uint16_t *lo,
+                             hipStream_t stream);
+hipError_t launch_quantise_fp8(const float *A, int64_t m, int64_t n, const float *B,
+                               int64_t p, bool two_term, int32_t *e, uint8_t *qA,
+                               uint8_t *lA, int32_t *f, uint8_t *qB, uint8_t *lB,
+                               uint32_t *amax_scratch, hipStream_t stream);
+hipError_t launch_error_norm(int64_t count, moa_dtype xt, const void *X, const double *R,
+                             double *out, double *partials, int nblocks, hipStream_t stream);
+
+// Runs one product: plan + scratch + launch. Used by moa_gemm and by the
+// grouped and serving paths for members that run alone.
+moa_status run_gemm(const moa_gemm_desc &d, hipStream_t stream);
+
+// Stream-ordered scratch (hipMallocAsync on the default pool of the current
+// device, pool kept warm).
+moa_status scratch_alloc(void **ptr, int64_t bytes, hipStream_t stream);
+void scratch_free(void *ptr, hipStream_t stream);
+
+}  // namespace moa

@@ -1,0 +1,301 @@
+// Plain ONF kernel: Eq. 3 with one fused multiply-add per (i, j, k), k in
+// ascending order for every element of C.
+//
+// The paper's generic program walks row i of C and, for each k, adds the
+// scalar A[i,k] times the contiguous row k of B (Fig. 1, section "From Normal
+// Form to C Program"). Its dimension lifting (section "Dimension Lifting to
+// Machine Coordinates") splits i over processors and j over register groups,
+// and the k (sigma) loop into blocks. On gfx950 the same splits become:
+//   i -> (workgroup row block of TM rows, lane row group; R rows per lane,
+//         strided by the TR row groups of the workgroup)
+//   j -> (workgroup column block of TN columns, lane column group; VJ columns
+//         per lane in VJ/VW runs of VW contiguous elements = one 16-byte
+//         vector each)
+//   k -> (LDS slab of BK, in-slab index)
+// Rows of A and B enter LDS as contiguous 16-byte vectors (coalesced row
+// reads, the contiguous access Eq. 3 prescribes), double-buffered through
+// registers. Each lane keeps its R x VJ block of C in registers for the whole
+// k loop, so the k-sum of every element is the plain ascending sequence of
+// fma(A[i,k], B[k,j], acc) -- bitwise the paper's loop with fma.
+#include "moa_internal.h"
+
+namespace moa {
+namespace {
+
+template <typename T> struct Vec;
+template <> struct Vec<float> { using type = float4; static constexpr int W = 4; };
+template <> struct Vec<double> { using type = double2; static constexpr int W = 2; };
+
+__device__ __forceinline__ float fma_t(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_t(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename T, int TM, int TN, int BK, int R, int VJ>
+__global__ __launch_bounds__(256) void onf_kernel(const T *__restrict__ A,
+                                                  const T *__restrict__ B,
+                                                  T *__restrict__ C, int64_t m,
+                                                  int64_t n, int64_t p,
+                                                  int accumulate, int vec_a,
+                                                  int vec_b, int vec_c) {
+    using V = typename Vec<T>::type;
+    constexpr int VW = Vec<T>::W;          // elements per 16-byte vector
+    constexpr int TC = TN / VJ;            // lane column groups
+    constexpr int TR = TM / R;             // lane row groups
+    static_assert(TC * TR == 256, "256 threads");
+    static_assert(VJ % VW == 0 && BK % VW == 0, "vector multiples");
+    constexpr int G = VJ / VW;             // column runs per lane
+    constexpr int PAD_A = VW;              // keeps rows 16-byte aligned, skews banks
+    constexpr int LDA = BK + PAD_A;
+    constexpr int A_VECS = TM * BK / VW;   // vectors per A slab
+    constexpr int B_VECS = BK * TN / VW;
+    constexpr int A_PER = (A_VECS + 255) / 256;
+    constexpr int B_PER = (B_VECS + 255) / 256;
+
+    __shared__ __attribute__((aligned(16))) T As[2][TM * LDA];
+    __shared__ __attribute__((aligned(16))) T Bs[2][BK * TN];
+
+    const int t = threadIdx.x;
+    const int tr = t / TC;                 // row group
+    const int tc = t % TC;                 // column group
+    const int64_t i0 = (int64_t)blockIdx.y * TM;
+    const int64_t j0 = (int64_t)blockIdx.x * TN;
+
+    // ---- C block in registers; the accumulate form starts from C --------
+    T acc[R][VJ];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+        for (int v = 0; v < VJ; ++v) acc[q][v] = T(0);
+    if (accumulate) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int64_t i = i0 + tr + (int64_t)TR * q;
+            if (i >= m) continue;
+#pragma unroll
+            for (int g = 0; g < G; ++g)
+#pragma unroll
+                for (int e = 0; e < VW; ++e) {
+                    const int64_t j = j0 + g * (TC * VW) + tc * VW + e;
+                    if (j < p) acc[q][g * VW + e] = C[i * p + j];
+                }
+        }
+    }
+
+    // ---- global -> registers for one k slab ------------------------------
+    V ra[A_PER], rb[B_PER];
+    auto load_slab = [&](int64_t k0) {
+#pragma unroll
+        for (int s = 0; s < A_PER; ++s) {
+            const int v = t + 256 * s;
+            V val;
+#pragma unroll
+            for (int e = 0; e < VW; ++e) ((T *)&val)[e] = T(0);
+            if (v < A_VECS) {
+                const int row = v / (BK / VW);
+                const int kv = (v % (BK / VW)) * VW;
+                const int64_t i = i0 + row, k = k0 + kv;
+                if (i < m) {
+                    if (vec_a && k + VW <= n) {
+                        val = *reinterpret_cast<const V *>(A + i * n + k);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VW; ++e)
+                            if (k + e < n) ((T *)&val)[e] = A[i * n + k + e];
+                    }
+                }
+            }
+            ra[s] = val;
+        }
+#pragma unroll
+        for (int s = 0; s < B_PER; ++s) {
+            const int v = t + 256 * s;
+            V val;
+#pragma unroll
+            for (int e = 0; e < VW; ++e) ((T *)&val)[e] = T(0);
+            if (v < B_VECS) {
+                const int kk = v / (TN / VW);
+                const int jv = (v % (TN / VW)) * VW;
+                const int64_t k = k0 + kk, j = j0 + jv;
+                if (k < n) {
+                    if (vec_b && j + VW <= p) {
+                        val = *reinterpret_cast<const V *>(B + k * p + j);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VW; ++e)
+                            if (j + e < p) ((T *)&val)[e] = B[k * p + j + e];
+                    }
+                }
+            }
+            rb[s] = val;
+        }
+    };
+    auto store_slab = [&](int buf) {
+#pragma unroll
+        for (int s = 0; s < A_PER; ++s) {
+            const int v = t + 256 * s;
+            if (v < A_VECS) {
+                const int row = v / (BK / VW);
+                const int kv = (v % (BK / VW)) * VW;
+                *reinterpret_cast<V *>(&As[buf][row * LDA + kv]) = ra[s];
+            }
+        }
+#pragma unroll
+        for (int s = 0; s < B_PER; ++s) {
+            const int v = t + 256 * s;
+            if (v < B_VECS) {
+                const int kk = v / (TN / VW);
+                const int jv = (v % (TN / VW)) * VW;
+                *reinterpret_cast<V *>(&Bs[buf][kk * TN + jv]) = rb[s];
+            }
+        }
+    };
+
+    // ---- one in-slab step: k ascending ------------------------------------
+    auto step = [&](const T *as, const T *bs, int kk) {
+        T a[R];
+#pragma unroll
+        for (int q = 0; q < R; ++q) a[q] = as[(tr + TR * q) * LDA + kk];
+        T b[VJ];
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const V bv = *reinterpret_cast<const V *>(&bs[kk * TN + g * (TC * VW) + tc * VW]);
+#pragma unroll
+            for (int e = 0; e < VW; ++e) b[g * VW + e] = ((const T *)&bv)[e];
+        }
+#pragma unroll
+        for (int q = 0; q < R; ++q)
+#pragma unroll
+            for (int v = 0; v < VJ; ++v) acc[q][v] = fma_t(a[q], b[v], acc[q][v]);
+    };
+
+    const int64_t nslabs = (n + BK - 1) / BK;
+    if (nslabs > 0) {
+        load_slab(0);
+        store_slab(0);
+        __syncthreads();
+    }
+    for (int64_t s = 0; s < nslabs; ++s) {
+        const int buf = (int)(s & 1);
+        const int64_t k0 = s * BK;
+        if (s + 1 < nslabs) load_slab(k0 + BK);
+        const T *as = As[buf];
+        const T *bs = Bs[buf];
+        const int64_t kn = n - k0;
+        if (kn >= BK) {
+#pragma unroll
+            for (int kk = 0; kk < BK; kk += VW) {
+                // A values for VW consecutive k come from one vector read per row
+                V av[R];
+#pragma unroll
+                for (int q = 0; q < R; ++q)
+                    av[q] = *reinterpret_cast<const V *>(&as[(tr + TR * q) * LDA + kk]);
+#pragma unroll
+                for (int e = 0; e < VW; ++e) {
+                    T b[VJ];
+#pragma unroll
+                    for (int g = 0; g < G; ++g) {
+                        const V bv = *reinterpret_cast<const V *>(
+                            &bs[(kk + e) * TN + g * (TC * VW) + tc * VW]);
+#pragma unroll
+                        for (int w = 0; w < VW; ++w) b[g * VW + w] = ((const T *)&bv)[w];
+                    }
+#pragma unroll
+                    for (int q = 0; q < R; ++q) {
+                        const T a = ((const T *)&av[q])[e];
+#pragma unroll
+                        for (int v = 0; v < VJ; ++v) acc[q][v] = fma_t(a, b[v], acc[q][v]);
+                    }
+                }
+            }
+        } else {
+            for (int kk = 0; kk < (int)kn; ++kk) step(as, bs, kk);
+        }
+        if (s + 1 < nslabs) store_slab(buf ^ 1);
+        __syncthreads();
+    }
+
+    // ---- write the C block: contiguous runs of row i ----------------------
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int64_t i = i0 + tr + (int64_t)TR * q;
+        if (i >= m) continue;
+#pragma unroll
+        for (int g = 0; g < G; ++g) {
+            const int64_t j = j0 + g * (TC * VW) + tc * VW;
+            if (vec_c && j + VW <= p) {
+                V out;
+#pragma unroll
+                for (int e = 0; e < VW; ++e) ((T *)&out)[e] = acc[q][g * VW + e];
+                *reinterpret_cast<V *>(C + i * p + j) = out;
+            } else {
+#pragma unroll
+                for (int e = 0; e < VW; ++e)
+                    if (j + e < p) C[i * p + j + e] = acc[q][g * VW + e];
+            }
+        }
+    }
+}
+
+struct OnfShape { int tm, tn, bk, r, vj; };
+
+// Instantiation tables. The first entry per type is the paper's static block
+// for the 32 KB vector L1 (three blocks of A, B and C): 1024 FP64 components
+// (32 x 32) and 2048 FP32 components (32 x 64). Larger entries trade LDS for
+// register blocking; the planner picks among them.
+constexpr OnfShape kF64[] = {{32, 32, 16, 2, 2}, {64, 64, 16, 4, 4}, {64, 128, 16, 4, 8}, {128, 128, 16, 8, 8}};
+constexpr OnfShape kF32[] = {{32, 64, 16, 2, 4}, {64, 64, 16, 4, 4}, {64, 128, 16, 4, 8}, {128, 128, 16, 8, 8}};
+
+template <typename T, int TM, int TN, int BK, int R, int VJ>
+hipError_t launch_one(const moa_gemm_desc &d, hipStream_t st) {
+    const T *A = static_cast<const T *>(d.A);
+    const T *B = static_cast<const T *>(d.B);
+    T *C = static_cast<T *>(d.C);
+    constexpr int VW = Vec<T>::W;
+    const int vec_a = (d.n % VW == 0) && ((uintptr_t)A % 16 == 0);
+    const int vec_b = (d.p % VW == 0) && ((uintptr_t)B % 16 == 0);
+    const int vec_c = (d.p % VW == 0) && ((uintptr_t)C % 16 == 0);
+    dim3 grid((unsigned)((d.p + TN - 1) / TN), (unsigned)((d.m + TM - 1) / TM));
+    hipLaunchKernelGGL((onf_kernel<T, TM, TN, BK, R, VJ>), grid, dim3(256), 0, st, A, B, C,
+                       d.m, d.n, d.p, d.accumulate, vec_a, vec_b, vec_c);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int onf_variant_count(moa_dtype t) {
+    return t == MOA_F64 ? (int)(sizeof(kF64) / sizeof(kF64[0]))
+                        : (int)(sizeof(kF32) / sizeof(kF32[0]));
+}
+
+void onf_variant_shape(moa_dtype t, int v, Plan *p) {
+    const OnfShape s = (t == MOA_F64) ? kF64[v] : kF32[v];
+    const int es = (t == MOA_F64) ? 8 : 4;
+    p->variant = v;
+    p->tile_m = s.tm;
+    p->tile_n = s.tn;
+    p->tile_k = s.bk;
+    p->lane_m = s.r;
+    p->lane_n = s.vj;
+    p->wave_m = s.r * (64 / (s.tn / s.vj));
+    p->wave_n = s.tn;
+    p->threads = 256;
+    p->lds_bytes = 2 * (s.tm * (s.bk + 16 / es) + s.bk * s.tn) * es;
+}
+
+hipError_t launch_onf(const moa_gemm_desc &d, const Plan &plan, hipStream_t st) {
+    if (d.dtype == MOA_F64) {
+        switch (plan.variant) {
+        case 0: return launch_one<double, 32, 32, 16, 2, 2>(d, st);
+        case 1: return launch_one<double, 64, 64, 16, 4, 4>(d, st);
+        case 2: return launch_one<double, 64, 128, 16, 4, 8>(d, st);
+        default: return launch_one<double, 128, 128, 16, 8, 8>(d, st);
+        }
+    }
+    switch (plan.variant) {
+    case 0: return launch_one<float, 32, 64, 16, 2, 4>(d, st);
+    case 1: return launch_one<float, 64, 64, 16, 4, 4>(d, st);
+    case 2: return launch_one<float, 64, 128, 16, 4, 8>(d, st);
+    default: return launch_one<float, 128, 128, 16, 8, 8>(d, st);
+    }
+}
+
+}  // namespace moa

@@ -1,0 +1,204 @@
+"""Thin Python binding of libmoa.so (include/moa.h), argument marshalling only.
+
+Every function keeps the name of the C entry point it calls. Tensors are
+PyTorch device tensors (torch is used for device memory and streams only);
+every step of the computation runs in the library's HIP kernels. If the
+library is missing this module raises -- there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libmoa.so")
+
+MOA_OK, MOA_ERR_INVALID, MOA_ERR_SHAPE, MOA_ERR_UNSUPPORTED = 0, 1, 2, 3
+MOA_ERR_NOMEM, MOA_ERR_DEVICE, MOA_NOT_READY = 4, 5, 6
+MOA_F64, MOA_F32 = 0, 1
+MOA_PATH_AUTO, MOA_PATH_ONF, MOA_PATH_MFMA_F32 = 0, 1, 2
+MOA_PATH_SPLIT_BF16, MOA_PATH_FP8_SCALED = 3, 4
+MOA_FLAG_FP8_TWO_TERM = 0x1
+
+PATHS = {"auto": MOA_PATH_AUTO, "onf": MOA_PATH_ONF, "mfma_f32": MOA_PATH_MFMA_F32,
+         "split_bf16": MOA_PATH_SPLIT_BF16, "fp8": MOA_PATH_FP8_SCALED}
+
+
+def MOA_FLAG_VARIANT(v: int) -> int:
+    return (v + 1) << 8
+
+
+class MoaError(RuntimeError):
+    def __init__(self, status: int, where: str, message: str):
+        super().__init__(f"{where}: {status_name(status)}: {message}")
+        self.status = status
+
+
+class moa_gemm_desc(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("p", ctypes.c_int64),
+                ("dtype", ctypes.c_int32), ("path", ctypes.c_int32),
+                ("A", ctypes.c_void_p), ("B", ctypes.c_void_p), ("C", ctypes.c_void_p),
+                ("accumulate", ctypes.c_int32), ("flags", ctypes.c_uint32)]
+
+
+class moa_plan_info(ctypes.Structure):
+    _fields_ = [("path", ctypes.c_int32), ("kernel", ctypes.c_int32),
+                ("tile_m", ctypes.c_int32), ("tile_n", ctypes.c_int32),
+                ("tile_k", ctypes.c_int32), ("wave_m", ctypes.c_int32),
+                ("wave_n", ctypes.c_int32), ("lane_m", ctypes.c_int32),
+                ("lane_n", ctypes.c_int32), ("threads", ctypes.c_int32),
+                ("lds_bytes", ctypes.c_int32), ("workgroups", ctypes.c_int64),
+                ("workspace_bytes", ctypes.c_int64), ("static_components", ctypes.c_int64)]
+
+
+class moa_serve_cfg(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("slots", ctypes.c_int32),
+                ("max_group", ctypes.c_int32), ("device", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class moa_req_info(ctypes.Structure):
+    _fields_ = [("t_submit_ns", ctypes.c_int64), ("t_admit_ns", ctypes.c_int64),
+                ("t_start_ns", ctypes.c_int64), ("t_done_ns", ctypes.c_int64),
+                ("status", ctypes.c_int32), ("group_size", ctypes.c_int32)]
+
+
+EXPORTS = [
+    "moa_gemm", "moa_gemm_grouped", "moa_plan_query", "moa_static_block_components",
+    "moa_split_bf16", "moa_quantise_fp8", "moa_error_norm", "moa_serve_create",
+    "moa_serve_submit", "moa_serve_poll", "moa_serve_drain", "moa_serve_destroy",
+    "moa_status_string", "moa_last_error",
+]
+
+_lib = None
+
+
+def lib():
+    """Load libmoa.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with "
+                           "`python -m paper_2306_11148_amd.build` (no fallback exists)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+    P = ctypes.POINTER
+    sig = {
+        "moa_gemm": ([P(moa_gemm_desc), vp], i32),
+        "moa_gemm_grouped": ([P(moa_gemm_desc), i64, vp], i32),
+        "moa_plan_query": ([P(moa_gemm_desc), P(moa_plan_info)], i32),
+        "moa_static_block_components": ([i64, i64, i64], i64),
+        "moa_split_bf16": ([vp, i64, i64, vp, vp, vp], i32),
+        "moa_quantise_fp8": ([vp, i64, i64, vp, i64, i32, vp, vp, vp, vp, vp, vp, vp], i32),
+        "moa_error_norm": ([i64, i32, vp, vp, vp, vp], i32),
+        "moa_serve_create": ([P(moa_serve_cfg), P(vp)], i32),
+        "moa_serve_submit": ([vp, P(moa_gemm_desc), P(ctypes.c_uint64)], i32),
+        "moa_serve_poll": ([vp, ctypes.c_uint64, P(moa_req_info)], i32),
+        "moa_serve_drain": ([vp], i32),
+        "moa_serve_destroy": ([vp], i32),
+        "moa_status_string": ([i32], ctypes.c_char_p),
+        "moa_last_error": ([], ctypes.c_char_p),
+    }
+    for name, (args, res) in sig.items():
+        fn = getattr(L, name)
+        fn.argtypes = args
+        fn.restype = res
+    _lib = L
+    return L
+
+
+def status_name(s: int) -> str:
+    return lib().moa_status_string(s).decode()
+
+
+def moa_last_error() -> str:
+    return lib().moa_last_error().decode()
+
+
+def _check(status: int, where: str):
+    if status != MOA_OK:
+        raise MoaError(status, where, moa_last_error())
+
+
+def _stream_handle(stream) -> int | None:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _dtype_code(t) -> int:
+    import torch
+    if t.dtype == torch.float64:
+        return MOA_F64
+    if t.dtype == torch.float32:
+        return MOA_F32
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def make_desc(A, B, C, path=MOA_PATH_AUTO, accumulate=False, flags=0) -> moa_gemm_desc:
+    """Descriptor for C (:= or +=) A.B from 2-D contiguous device tensors."""
+    for name, t in (("A", A), ("B", B), ("C", C)):
+        if t.dim() != 2 or not t.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous 2-D tensor (row-major, Eq. 4)")
+    m, n = A.shape
+    if B.shape[0] != n or tuple(C.shape) != (m, B.shape[1]):
+        raise ValueError(f"shapes {tuple(A.shape)} x {tuple(B.shape)} -> {tuple(C.shape)} do not conform")
+    if isinstance(path, str):
+        path = PATHS[path]
+    dt = _dtype_code(A)
+    if _dtype_code(B) != dt or _dtype_code(C) != dt:
+        raise TypeError("A, B and C must share one dtype")
+    return moa_gemm_desc(m, n, B.shape[1], dt, path, A.data_ptr() if A.numel() else None,
+                         B.data_ptr() if B.numel() else None, C.data_ptr() if C.numel() else None,
+                         int(bool(accumulate)), flags)
+
+
+def moa_gemm(A, B, C, path=MOA_PATH_AUTO, accumulate=False, flags=0, stream=None):
+    d = make_desc(A, B, C, path, accumulate, flags)
+    _check(lib().moa_gemm(ctypes.byref(d), _stream_handle(stream)), "moa_gemm")
+    return C
+
+
+def moa_gemm_desc_call(desc: moa_gemm_desc, stream=None) -> int:
+    """Raw call with a prepared descriptor; returns the status code."""
+    return lib().moa_gemm(ctypes.byref(desc), _stream_handle(stream))
+
+
+def moa_gemm_grouped(descs, stream=None):
+    arr = (moa_gemm_desc * len(descs))(*descs)
+    _check(lib().moa_gemm_grouped(arr, len(descs), _stream_handle(stream)), "moa_gemm_grouped")
+
+
+def moa_plan_query(desc: moa_gemm_desc) -> dict:
+    info = moa_plan_info()
+    _check(lib().moa_plan_query(ctypes.byref(desc), ctypes.byref(info)), "moa_plan_query")
+    return {f: getattr(info, f) for f, _ in moa_plan_info._fields_}
+
+
+def moa_static_block_components(budget_bytes: int, elem_bytes: int, nblocks: int = 3) -> int:
+    return lib().moa_static_block_components(budget_bytes, elem_bytes, nblocks)
+
+
+def moa_split_bf16(X, hi, lo, stream=None):
+    rows, cols = (X.shape if X.dim() == 2 else (1, X.numel()))
+    _check(lib().moa_split_bf16(X.data_ptr(), rows, cols, hi.data_ptr(), lo.data_ptr(),
+                                _stream_handle(stream)), "moa_split_bf16")
+
+
+def moa_quantise_fp8(A, B, e, qA, f, qB, lA=None, lB=None, two_term=False, stream=None):
+    m, n = A.shape
+    p = B.shape[1]
+    ptr = lambda t: t.data_ptr() if t is not None and t.numel() else None
+    _check(lib().moa_quantise_fp8(ptr(A), m, n, ptr(B), p, int(bool(two_term)), ptr(e), ptr(qA),
+                                  ptr(lA), ptr(f), ptr(qB), ptr(lB), _stream_handle(stream)),
+           "moa_quantise_fp8")
+
+
+def moa_error_norm(X, R, out, stream=None):
+    _check(lib().moa_error_norm(X.numel(), _dtype_code(X), X.data_ptr(), R.data_ptr(),
+                                out.data_ptr(), _stream_handle(stream)), "moa_error_norm")
+    return out

@@ -1,0 +1,112 @@
+"""Host-side checks of the C ABI (no GPU needed, nothing is launched).
+
+* libmoa.so loads and exports every function include/moa.h declares.
+* The block-size rule of section "Technical Details" reproduces the paper's
+  numbers (tests/golden/static_rule_paper.json) and agrees with the oracle's
+  statement of the same rule.
+* Argument errors (Eq. 1-2 shape and index rules) come back synchronously.
+* Planning (the dimension lift) is a pure host function.
+"""
+import ctypes
+import json
+import os
+import re
+
+import pytest
+
+from oracle import oracle as O
+from paper_2306_11148_amd import moa
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    text = open(os.path.join(ROOT, "include", "moa.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(moa_[a-z0-9_]+)\s*\(", text)) - {"moa_gemm_desc"})
+
+
+def test_library_exports_every_declared_function():
+    L = moa.lib()
+    names = header_functions()
+    assert "moa_gemm" in names and "moa_serve_submit" in names
+    for name in names:
+        assert hasattr(L, name), f"{name} declared in include/moa.h but not exported"
+    assert sorted(moa.EXPORTS) == names
+
+
+def test_static_rule_matches_paper_and_oracle():
+    g = json.load(open(os.path.join(ROOT, "tests", "golden", "static_rule_paper.json")))
+    for c in g["cases"]:
+        assert moa.moa_static_block_components(c["budget_bytes"], c["elem_bytes"], c["nblocks"]) \
+            == c["components"]
+    for budget in (0, 1, 23, 24, 25, 4096, 32768, 98304, 131072, 163840, 10**9):
+        for es in (1, 2, 4, 8):
+            for nb in (1, 2, 3):
+                assert moa.moa_static_block_components(budget, es, nb) == \
+                    O.static_block_components(budget, es, nb)
+    assert moa.moa_static_block_components(-1, 8, 3) == 0
+    assert moa.moa_static_block_components(32768, 0, 3) == 0
+
+
+def _desc(m, n, p, dtype=moa.MOA_F32, path=moa.MOA_PATH_AUTO, A=0x1000, B=0x100000000,
+          C=0x200000000, acc=0, flags=0):
+    return moa.moa_gemm_desc(m, n, p, dtype, path, A, B, C, acc, flags)
+
+
+def test_plan_static_components_and_shapes():
+    q = moa.moa_plan_query(_desc(256, 256, 256, moa.MOA_F64))
+    assert q["path"] == moa.MOA_PATH_ONF
+    assert q["static_components"] == 1024            # 32 x 32 doubles in a 32 KB L1
+    q0 = moa.moa_plan_query(_desc(256, 256, 256, moa.MOA_F64, flags=moa.MOA_FLAG_VARIANT(0)))
+    assert q0["tile_m"] * q0["tile_n"] == 1024       # the static block itself
+    q32 = moa.moa_plan_query(_desc(256, 256, 256, moa.MOA_F32, moa.MOA_PATH_ONF,
+                                   flags=moa.MOA_FLAG_VARIANT(0)))
+    assert q32["static_components"] == 2048 and q32["tile_m"] * q32["tile_n"] == 2048
+    big = moa.moa_plan_query(_desc(8192, 8192, 8192))
+    assert big["path"] == moa.MOA_PATH_SPLIT_BF16
+    assert big["workgroups"] >= 256
+    f8 = moa.moa_plan_query(_desc(100, 200, 300, path=moa.MOA_PATH_FP8_SCALED))
+    assert f8["workspace_bytes"] >= 100 * 200 + 200 * 300
+
+
+def call(d):
+    return moa.lib().moa_gemm(ctypes.byref(d), None)
+
+
+def test_argument_errors_are_synchronous():
+    L = moa.lib()
+    assert L.moa_gemm(None, None) == moa.MOA_ERR_INVALID
+    assert call(_desc(-1, 2, 3)) == moa.MOA_ERR_SHAPE
+    assert call(_desc(2, 2, 2, dtype=7)) == moa.MOA_ERR_INVALID
+    assert call(_desc(2, 2, 2, path=9)) == moa.MOA_ERR_INVALID
+    assert call(_desc(2, 2, 2, flags=0x80)) == moa.MOA_ERR_INVALID
+    assert call(_desc(2, 2, 2, moa.MOA_F64, moa.MOA_PATH_SPLIT_BF16)) == moa.MOA_ERR_UNSUPPORTED
+    assert "ONF" in moa.moa_last_error()
+    assert call(_desc(2, 2, 2, A=0)) == moa.MOA_ERR_INVALID
+    # C overlapping A (the paper's program reads C while it writes it)
+    assert call(_desc(4, 4, 4, A=0x1000, C=0x1000 + 16)) == moa.MOA_ERR_INVALID
+    assert call(_desc(2**40, 2**40, 2)) == moa.MOA_ERR_SHAPE
+    assert call(_desc(2, 2, 2, A=0x1002)) == moa.MOA_ERR_INVALID        # misaligned
+    assert call(_desc(2, 2, 2, flags=moa.MOA_FLAG_VARIANT(40))) == moa.MOA_ERR_INVALID
+    # empty outputs are a successful no-op and never touch the device
+    assert call(_desc(0, 5, 7, A=0, C=0)) == moa.MOA_OK
+    assert call(_desc(5, 7, 0, B=0, C=0)) == moa.MOA_OK
+    assert L.moa_gemm_grouped(None, -1, None) == moa.MOA_ERR_INVALID
+    assert L.moa_gemm_grouped(None, 1, None) == moa.MOA_ERR_INVALID
+    assert L.moa_gemm_grouped(None, 0, None) == moa.MOA_OK
+
+
+def test_status_strings():
+    for code, name in [(0, "MOA_OK"), (1, "MOA_ERR_INVALID"), (2, "MOA_ERR_SHAPE"),
+                       (3, "MOA_ERR_UNSUPPORTED"), (4, "MOA_ERR_NOMEM"), (5, "MOA_ERR_DEVICE"),
+                       (6, "MOA_NOT_READY")]:
+        assert moa.status_name(code) == name
+    assert moa.status_name(99) == "MOA_UNKNOWN_STATUS"
+
+
+def test_descriptor_layout_matches_header():
+    # int64 m,n,p; int32 dtype,path; 3 pointers; int32 accumulate; uint32 flags
+    assert ctypes.sizeof(moa.moa_gemm_desc) == 3 * 8 + 2 * 4 + 3 * 8 + 2 * 4
+    assert moa.moa_gemm_desc.A.offset == 32
+    assert ctypes.sizeof(moa.moa_plan_info) == 11 * 4 + 4 + 3 * 8
