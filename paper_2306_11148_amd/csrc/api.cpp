@@ -115,12 +115,13 @@ moa_status run_gemm(const moa_gemm_desc &d, hipStream_t stream) {
     switch (pl.path) {
     case MOA_PATH_ONF: e = launch_onf(d, pl, stream); break;
     case MOA_PATH_MFMA_F32: e = launch_mfma_f32(d, pl, stream); break;
-    case MOA_PATH_SPLIT_BF16: e = launch_split_bf16(d, pl, stream); break;
+    case MOA_PATH_SPLIT_BF16:
     case MOA_PATH_FP8_SCALED: {
         void *ws = nullptr;
         s = scratch_alloc(&ws, pl.workspace_bytes, stream);
         if (s != MOA_OK) return s;
-        e = launch_fp8(d, pl, ws, stream);
+        e = pl.path == MOA_PATH_SPLIT_BF16 ? launch_split_bf16(d, pl, ws, stream)
+                                            : launch_fp8(d, pl, ws, stream);
         scratch_free(ws, stream);
         break;
     }

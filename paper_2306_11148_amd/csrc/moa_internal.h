@@ -69,9 +69,12 @@ void onf_variant_shape(moa_dtype t, int v, Plan *p);
 hipError_t launch_mfma_f32(const moa_gemm_desc &d, const Plan &plan, hipStream_t stream);
 void mfma_f32_shape(Plan *p);
 
-hipError_t launch_split_bf16(const moa_gemm_desc &d, const Plan &plan, hipStream_t stream);
+hipError_t launch_split_bf16(const moa_gemm_desc &d, const Plan &plan, void *workspace,
+                             hipStream_t stream);
+hipError_t launch_split_pack(const moa_gemm_desc &d, void *workspace, hipStream_t stream);
 void split_bf16_shape(int variant, Plan *p);
 int split_bf16_variant_count();
+int64_t split_bf16_workspace_bytes(int64_t m, int64_t n, int64_t p);
 
 hipError_t launch_fp8(const moa_gemm_desc &d, const Plan &plan, void *workspace,
                       hipStream_t stream);

@@ -81,6 +81,11 @@ moa_status make_plan(const moa_gemm_desc &d, Plan *out) {
             }
         }
         split_bf16_shape(v, &pl);
+        pl.workspace_bytes = split_bf16_workspace_bytes(d.m, d.n, d.p);
+        // 256 record rows of (n/16) 64-byte records must stay below 2^31 bytes
+        // (32-bit buffer offsets of one tile).
+        if ((d.n + 15) / 16 > 131071)
+            return fail(MOA_ERR_SHAPE, "n = %lld exceeds the split-BF16 offset range", (long long)d.n);
         break;
     }
     case MOA_PATH_FP8_SCALED: {

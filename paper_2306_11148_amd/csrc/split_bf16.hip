@@ -1,109 +1,218 @@
-// Split-BF16 matrix-core kernel: C = hi(A).hi(B) + hi(A).lo(B) + lo(A).hi(B)
-// with FP32 accumulation, where x = hi + lo + O(2^-16 |x|) and hi, lo are
-// BF16. This evaluates Eq. 3 (section "MoA Matrix Multiplication") to about
-// FP32 accuracy on the BF16 matrix cores.
+// Split-BF16 matrix-core path: C = hi(A).hi(B) + hi(A).lo(B) + lo(A).hi(B)
+// with FP32 accumulation, where x = hi + lo + O(2^-16 |x|), hi = RNE_bf16(x),
+// lo = RNE_bf16(x - hi). This evaluates Eq. 3 (section "MoA Matrix
+// Multiplication") to about FP32 accuracy on the BF16 matrix cores.
 //
-// Blocking follows the blocked form of Fig. 2: each workgroup owns a BM x BN
-// block of C, walks the k extent in slabs of BK (the sigma loop broken into
-// blocks), and the per-slab block products are summed in registers (the
-// "addition loop" over blocks). Operands are conditioned while they are
-// staged: FP32 rows of A and columns of B are read from HBM, split into
-// (hi, lo) in registers and stored to LDS as k-contiguous BF16 runs, so no
-// split copy of A or B is ever written to HBM.
+// Two stages.
 //
-// LDS row layout (one row per row of A / column of B):
-//   [hi: BK bf16][lo: BK bf16][16-byte pad]  -> 144 bytes for BK = 32.
-// The 9 x 16-byte pitch puts 8 consecutive rows in 8 different 16-byte bank
-// groups, so the fragment reads (32 consecutive rows, one 16-byte run each)
-// and the staging writes (consecutive rows) are free of bank conflicts.
+// 1. Conditioning (HBM-bound): A and B are rewritten as "slab records". The k
+//    extent is cut into slabs of 16 (the sigma loop broken into blocks,
+//    section "Dimension Lifting to Machine Coordinates"); for every row i of
+//    A and every column j of B, slab s becomes one contiguous 64-byte record
+//        [hi of x[16s .. 16s+15] (16 bf16)][lo of the same (16 bf16)]
+//    zero-padded past n. B is transposed on the way (column j of B becomes
+//    record row j), so both operands are k-contiguous, and the records of one
+//    row follow each other (record (r, s) at (r * S + s) * 64 bytes).
+//
+// 2. Contraction (matrix-core bound), the blocked form of Fig. 2: each
+//    workgroup owns a BM x BN block of C and walks the S slabs; per slab the
+//    BM + BN records go straight from HBM into LDS (buffer_load ... lds, no
+//    register staging) through a ring of NSTAGE buffers, so loads run three
+//    slabs ahead of the matrix cores. The block products of the slabs are
+//    summed in registers (the "addition loop" over blocks). The fragments of
+//    slab t+1 are read from LDS while the matrix-core steps of slab t issue.
+//
+// LDS holds one 64-byte row per record. gfx950's LDS serves a 16-byte read
+// for 16 lanes per cycle out of a 256-byte bank window (64 banks), i.e. four
+// consecutive rows at once. Chunk c of row r is stored at chunk position
+// c ^ ((r / 4) mod 4): the 16 rows of one fragment-read cycle then occupy 16
+// distinct 16-byte bank groups. The direct loads stay linear (lane L writes
+// bytes 16L .. 16L+15 of its wave's 1 KiB window = 16 rows), so each lane
+// fetches the logical chunk that belongs at its physical position.
 #include "moa_internal.h"
 #include "tile_common.h"
 
 namespace moa {
 namespace {
 
-constexpr int BK = 32;
-constexpr int ROW = 2 * BK + 8;        // bf16 elements per LDS row (144 bytes)
+constexpr int SLAB = 16;                  // k per record
+constexpr int REC = 2 * SLAB;             // bf16 per record (hi + lo)
+constexpr int REC_BYTES = REC * 2;        // 64
+constexpr int NSTAGE = 4;                 // LDS ring depth
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+
+// gfx9 s_waitcnt immediate that waits until at most n vector-memory
+// operations of this wave are outstanding (expcnt and lgkmcnt not waited on).
+constexpr int waitcnt_vm(int n) { return (n & 0xF) | (((n >> 4) & 3) << 14) | (0x7 << 4) | (0xF << 8); }
+
+// Workgroup barrier without the release fence of __syncthreads(): that fence
+// would also wait for the direct loads still in flight for later slabs. Each
+// wave first waits (s_waitcnt) for its own loads of the slab it is about to
+// read; LDS reads are complete before their values are used. The "memory"
+// clobber keeps the compiler from moving LDS accesses across the barrier.
+__device__ __forceinline__ void ring_barrier() { asm volatile("s_barrier" ::: "memory"); }
+
+// ---------------------------------------------------------------- stage 1 --
+
+// Rows of X (rows x K, row-major) -> records. One thread per 8-k chunk.
+__global__ __launch_bounds__(256) void pack_rows_kernel(const float *__restrict__ X, int64_t rows,
+                                                        int64_t K, int64_t S, int vec,
+                                                        uint16_t *__restrict__ P) {
+    const int64_t chunks = rows * S * 2;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < chunks; q += stride) {
+        const int64_t r = q / (S * 2);
+        const int64_t rem = q - r * S * 2;
+        const int64_t s = rem >> 1;
+        const int c = (int)(rem & 1);
+        const int64_t k = s * SLAB + c * 8;
+        float x[8];
+        if (vec && k + 8 <= K) {
+            const float4 *src = reinterpret_cast<const float4 *>(X + r * K + k);
+            const float4 a = src[0], b = src[1];
+            x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+            x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e) x[e] = (k + e < K) ? X[r * K + k + e] : 0.0f;
+        }
+        uint4 hi, lo;
+        split_pair(x[0], x[1], &hi.x, &lo.x);
+        split_pair(x[2], x[3], &hi.y, &lo.y);
+        split_pair(x[4], x[5], &hi.z, &lo.z);
+        split_pair(x[6], x[7], &hi.w, &lo.w);
+        uint16_t *rec = P + (r * S + s) * REC;
+        *reinterpret_cast<uint4 *>(rec + c * 8) = hi;
+        *reinterpret_cast<uint4 *>(rec + SLAB + c * 8) = lo;
+    }
+}
+
+// Columns of X (K x cols, row-major) -> records (transposed). A 64 x 64 block
+// (four slabs of 64 columns) per workgroup goes through LDS; reads of X rows
+// are contiguous, and each thread writes one whole 64-byte record, four
+// neighbouring threads four consecutive records of one column.
+__global__ __launch_bounds__(256) void pack_cols_kernel(const float *__restrict__ X, int64_t K,
+                                                        int64_t cols, int64_t S,
+                                                        uint16_t *__restrict__ P) {
+    __shared__ float tile[4 * SLAB][64 + 1];
+    const int64_t j0 = (int64_t)blockIdx.x * 64;
+    const int64_t s0 = (int64_t)blockIdx.y * 4;
+    const int t = threadIdx.x;
+    {
+        const int jj = t & 63;
+        const int64_t j = j0 + jj;
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            const int kk = (t >> 6) + 4 * q;
+            const int64_t k = s0 * SLAB + kk;
+            tile[kk][jj] = (k < K && j < cols) ? X[k * cols + j] : 0.0f;
+        }
+    }
+    __syncthreads();
+    const int jj = t >> 2, part = t & 3;
+    const int64_t j = j0 + jj, s = s0 + part;
+    if (j >= cols || s >= S) return;
+    uint4 h[2], l[2];
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+        const int kb = part * SLAB + c * 8;
+        split_pair(tile[kb + 0][jj], tile[kb + 1][jj], &h[c].x, &l[c].x);
+        split_pair(tile[kb + 2][jj], tile[kb + 3][jj], &h[c].y, &l[c].y);
+        split_pair(tile[kb + 4][jj], tile[kb + 5][jj], &h[c].z, &l[c].z);
+        split_pair(tile[kb + 6][jj], tile[kb + 7][jj], &h[c].w, &l[c].w);
+    }
+    uint4 *rec = reinterpret_cast<uint4 *>(P + (j * S + s) * REC);
+    rec[0] = h[0];
+    rec[1] = h[1];
+    rec[2] = l[0];
+    rec[3] = l[1];
+}
+
+// ---------------------------------------------------------------- stage 2 --
 
 template <int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__(256) void split_bf16_kernel(
-    const float *__restrict__ A, const float *__restrict__ B, float *__restrict__ C,
-    int64_t m, int64_t n, int64_t p, int accumulate, int tiles_m, int tiles_n, int vec_a) {
-    constexpr int WAVES_N = BN / WN;
-    static_assert((BM / WM) * WAVES_N == 4, "four waves");
-    constexpr int FM = WM / 32, FN = WN / 32;      // 32x32 blocks per wave
-    constexpr int CA = BM * (BK / 8) / 256;        // 8-element chunks per thread (A)
-    constexpr int CB = BN * (BK / 8) / 256;        // (B)
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void split_bf16_kernel(
+    const uint16_t *__restrict__ Ap, const uint16_t *__restrict__ Bp, float *__restrict__ C,
+    int64_t m, int64_t p, int64_t S, int accumulate, int tiles_m, int tiles_n) {
+    constexpr int WAVES_M = BM / WM, WAVES_N = BN / WN, NW = WAVES_M * WAVES_N;
+    constexpr int FM = WM / 32, FN = WN / 32;
+    constexpr int ROWS = BM + BN;                     // records per slab
+    constexpr int STAGE = ROWS * REC_BYTES;           // bytes per LDS buffer
+    constexpr int LPW = ROWS / 16 / NW;               // 1 KiB direct loads per wave per slab
+    static_assert(ROWS % (16 * NW) == 0 && BM % 16 == 0, "whole loads per wave");
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[NSTAGE * STAGE];
 
-    __shared__ __attribute__((aligned(16))) uint16_t lds[2][(BM + BN) * ROW];
-
-    const int t = threadIdx.x;
-    const int lane = t & 63;
-    const int wave = t >> 6;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int wm = wave / WAVES_N, wn = wave % WAVES_N;
-
     int tm, tn;
-    const int total = tiles_m * tiles_n;
-    tile_coords(xcd_remap(blockIdx.x, total), tiles_m, tiles_n, 8, &tm, &tn);
-    const int64_t i0 = (int64_t)tm * BM;
-    const int64_t j0 = (int64_t)tn * BN;
+    tile_coords(xcd_remap(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, &tm, &tn);
+    // the integer divisions above run on the vector ALU; pin the (uniform)
+    // results to scalar registers so everything derived from them stays scalar
+    tm = __builtin_amdgcn_readfirstlane(tm);
+    tn = __builtin_amdgcn_readfirstlane(tn);
+    const int64_t i0 = (int64_t)tm * BM, j0 = (int64_t)tn * BN;
 
-    float ra[CA][8];
-    float rb[CB][8];
-
-    auto load = [&](int64_t k0) {
+    // Direct loads through two buffer resources based at this tile's first
+    // record row of A and of B. Load Q = wave*LPW + q fills LDS rows
+    // 16Q .. 16Q+15: lane L lands at row 16Q + L/4, physical chunk L%4, and
+    // fetches logical chunk (L%4) ^ ((row/4) mod 4) = (L%4) ^ (L/16). The row
+    // block and the slab go in the uniform soffset. Records past m (or p) lie
+    // beyond the resource's range and load as zeros (their outputs are not
+    // stored).
+    const int64_t rec_row = S * REC_BYTES;            // bytes per record row
+    const int64_t rows_a = min((int64_t)BM, m - i0), rows_b = min((int64_t)BN, p - j0);
+    const __amdgpu_buffer_rsrc_t rsrc_a = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(reinterpret_cast<const uint8_t *>(Ap) + i0 * rec_row), (short)0,
+        (int)(rows_a * rec_row), 0x00020000);
+    const __amdgpu_buffer_rsrc_t rsrc_b = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(reinterpret_cast<const uint8_t *>(Bp) + j0 * rec_row), (short)0,
+        (int)(rows_b * rec_row), 0x00020000);
+    const int voff = (int)((lane >> 2) * rec_row) + (((lane & 3) ^ (lane >> 4)) << 4);
+    // Each wave's LPW loads cover 16*LPW consecutive rows that are either
+    // all rows of A or all rows of B, so every load names one resource.
+    static_assert(BM % (16 * LPW) == 0, "a wave loads A rows or B rows, not both");
+    const bool loads_a = wave * LPW * 16 < BM;
+    const int row_base = loads_a ? wave * LPW * 16 : wave * LPW * 16 - BM;
+    auto issue = [&](int64_t s) {
+        uint8_t *buf = lds + (int)(s % NSTAGE) * STAGE + wave * LPW * 16 * REC_BYTES;
+        if (loads_a) {
 #pragma unroll
-        for (int s = 0; s < CA; ++s) {
-            const int cid = t + 256 * s;
-            const int row = cid % BM, kc = cid / BM;
-            const int64_t i = i0 + row, k = k0 + kc * 8;
-            if (i < m && vec_a && k + 8 <= n) {
-                const float4 *src = reinterpret_cast<const float4 *>(A + i * n + k);
-                const float4 x0 = src[0], x1 = src[1];
-                ra[s][0] = x0.x; ra[s][1] = x0.y; ra[s][2] = x0.z; ra[s][3] = x0.w;
-                ra[s][4] = x1.x; ra[s][5] = x1.y; ra[s][6] = x1.z; ra[s][7] = x1.w;
-            } else {
+            for (int q = 0; q < LPW; ++q)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rsrc_a, (lds_void_t *)(buf + q * 16 * REC_BYTES), 16, voff,
+                    (int)((row_base + q * 16) * rec_row + s * REC_BYTES), 0, 0);
+        } else {
 #pragma unroll
-                for (int e = 0; e < 8; ++e)
-                    ra[s][e] = (i < m && k + e < n) ? A[i * n + k + e] : 0.0f;
-            }
-        }
-#pragma unroll
-        for (int s = 0; s < CB; ++s) {
-            const int cid = t + 256 * s;
-            const int col = cid % BN, kc = cid / BN;
-            const int64_t j = j0 + col, k = k0 + kc * 8;
-#pragma unroll
-            for (int e = 0; e < 8; ++e)
-                rb[s][e] = (j < p && k + e < n) ? B[(k + e) * p + j] : 0.0f;
+            for (int q = 0; q < LPW; ++q)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    rsrc_b, (lds_void_t *)(buf + q * 16 * REC_BYTES), 16, voff,
+                    (int)((row_base + q * 16) * rec_row + s * REC_BYTES), 0, 0);
         }
     };
-    auto store = [&](int buf) {
-        uint16_t *base = lds[buf];
+
+    // Fragment of 32 records (rows) x 8 k: lane l reads logical chunk c of
+    // row base + l%32; hi is chunk l/32, lo is chunk 2 + l/32.
+    const int frow = lane & 31, fhalf = lane >> 5;
+    auto frag = [&](const uint8_t *buf, int row, int chunk) {
+        return *reinterpret_cast<const bf16x8_t *>(buf + row * REC_BYTES +
+                                                   ((chunk ^ ((row >> 2) & 3)) << 4));
+    };
+    struct Frags { bf16x8_t ah[FM], al[FM], bh[FN], bl[FN]; };
+    auto read_frags = [&](int64_t s, Frags &f) {
+        const uint8_t *buf = lds + (int)(s % NSTAGE) * STAGE;
 #pragma unroll
-        for (int s = 0; s < CA; ++s) {
-            const int cid = t + 256 * s;
-            const int row = cid % BM, kc = cid / BM;
-            uint4 hi, lo;
-            split_pair(ra[s][0], ra[s][1], &hi.x, &lo.x);
-            split_pair(ra[s][2], ra[s][3], &hi.y, &lo.y);
-            split_pair(ra[s][4], ra[s][5], &hi.z, &lo.z);
-            split_pair(ra[s][6], ra[s][7], &hi.w, &lo.w);
-            *reinterpret_cast<uint4 *>(base + row * ROW + kc * 8) = hi;
-            *reinterpret_cast<uint4 *>(base + row * ROW + BK + kc * 8) = lo;
+        for (int a = 0; a < FM; ++a) {
+            const int row = wm * WM + a * 32 + frow;
+            f.ah[a] = frag(buf, row, fhalf);
+            f.al[a] = frag(buf, row, 2 + fhalf);
         }
 #pragma unroll
-        for (int s = 0; s < CB; ++s) {
-            const int cid = t + 256 * s;
-            const int col = cid % BN, kc = cid / BN;
-            uint4 hi, lo;
-            split_pair(rb[s][0], rb[s][1], &hi.x, &lo.x);
-            split_pair(rb[s][2], rb[s][3], &hi.y, &lo.y);
-            split_pair(rb[s][4], rb[s][5], &hi.z, &lo.z);
-            split_pair(rb[s][6], rb[s][7], &hi.w, &lo.w);
-            uint16_t *bb = base + BM * ROW;
-            *reinterpret_cast<uint4 *>(bb + col * ROW + kc * 8) = hi;
-            *reinterpret_cast<uint4 *>(bb + col * ROW + BK + kc * 8) = lo;
+        for (int b = 0; b < FN; ++b) {
+            const int row = BM + wn * WN + b * 32 + frow;
+            f.bh[b] = frag(buf, row, fhalf);
+            f.bl[b] = frag(buf, row, 2 + fhalf);
         }
     };
 
@@ -111,47 +220,56 @@ __global__ __launch_bounds__(256) void split_bf16_kernel(
 #pragma unroll
     for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int b = 0; b < FN; ++b)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
+        for (int b = 0; b < FN; ++b) acc[a][b] = f32x16_t{};
 
-    const int64_t nslabs = (n + BK - 1) / BK;
-    if (nslabs > 0) {
-        load(0);
-        store(0);
-        __syncthreads();
-    }
-    const int frag_row = lane & 31;
-    const int frag_k = (lane >> 5) * 8;
-    for (int64_t s = 0; s < nslabs; ++s) {
-        const int buf = (int)(s & 1);
-        if (s + 1 < nslabs) load((s + 1) * BK);
-        const uint16_t *la = lds[buf] + (wm * WM + frag_row) * ROW + frag_k;
-        const uint16_t *lb = lds[buf] + BM * ROW + (wn * WN + frag_row) * ROW + frag_k;
+    // term-major order: consecutive matrix-core steps are independent
+    auto mma = [&](const Frags &f) {
 #pragma unroll
-        for (int ks = 0; ks < BK; ks += 16) {
-            bf16x8_t ah[FM], al[FM], bh[FN], bl[FN];
+        for (int a = 0; a < FM; ++a)
 #pragma unroll
-            for (int a = 0; a < FM; ++a) {
-                ah[a] = *reinterpret_cast<const bf16x8_t *>(la + a * 32 * ROW + ks);
-                al[a] = *reinterpret_cast<const bf16x8_t *>(la + a * 32 * ROW + BK + ks);
-            }
+            for (int b = 0; b < FN; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.al[a], f.bh[b], acc[a][b], 0, 0, 0);
 #pragma unroll
-            for (int b = 0; b < FN; ++b) {
-                bh[b] = *reinterpret_cast<const bf16x8_t *>(lb + b * 32 * ROW + ks);
-                bl[b] = *reinterpret_cast<const bf16x8_t *>(lb + b * 32 * ROW + BK + ks);
-            }
+        for (int a = 0; a < FM; ++a)
 #pragma unroll
-            for (int a = 0; a < FM; ++a)
+            for (int b = 0; b < FN; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.ah[a], f.bl[b], acc[a][b], 0, 0, 0);
 #pragma unroll
-                for (int b = 0; b < FN; ++b) {
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[a], bh[b], acc[a][b], 0, 0, 0);
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bl[b], acc[a][b], 0, 0, 0);
-                    acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[a], bh[b], acc[a][b], 0, 0, 0);
-                }
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int b = 0; b < FN; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.ah[a], f.bh[b], acc[a][b], 0, 0, 0);
+    };
+
+    // One step: make slab t+1 visible, refill the buffer slab t-1 used with
+    // slab t+3, read slab t+1's fragments, then issue slab t's products.
+    auto step = [&](int64_t t, const Frags &cur, Frags &next) {
+        if (t + 1 < S) {
+            if (t + 2 < S) __builtin_amdgcn_s_waitcnt(waitcnt_vm(LPW));
+            else __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+            ring_barrier();
+            if (t + 3 < S) issue(t + 3);
+            read_frags(t + 1, next);
         }
-        if (s + 1 < nslabs) store(buf ^ 1);
-        __syncthreads();
+        mma(cur);
+    };
+
+    if (S > 0) {
+        issue(0);
+        if (S > 1) issue(1);
+        if (S > 2) issue(2);
+        if (S > 2) __builtin_amdgcn_s_waitcnt(waitcnt_vm(2 * LPW));
+        else if (S > 1) __builtin_amdgcn_s_waitcnt(waitcnt_vm(LPW));
+        else __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+        ring_barrier();
+        Frags f0, f1;
+        read_frags(0, f0);
+        int64_t t = 0;
+        for (; t + 1 < S; t += 2) {
+            step(t, f0, f1);
+            step(t + 1, f1, f0);
+        }
+        if (t < S) step(t, f0, f1);
     }
 
     // Epilogue: register r of lane l holds C[8(r/4) + 4(l/32) + r%4][l%32] of
@@ -194,18 +312,17 @@ __global__ __launch_bounds__(256) void split_only_kernel(const float *__restrict
 }
 
 struct SplitShape { int bm, bn, wm, wn; };
-constexpr SplitShape kSplit[] = {{128, 128, 64, 64}, {256, 256, 128, 128}};
+constexpr SplitShape kSplit[] = {{128, 128, 64, 64}, {256, 256, 128, 64}};
 
 template <int BM, int BN, int WM, int WN>
-hipError_t launch_shape(const moa_gemm_desc &d, hipStream_t st) {
-    const float *A = static_cast<const float *>(d.A);
-    const float *B = static_cast<const float *>(d.B);
+hipError_t launch_shape(const moa_gemm_desc &d, const uint16_t *Ap, const uint16_t *Bp, int64_t S,
+                        hipStream_t st) {
     float *C = static_cast<float *>(d.C);
     const int tiles_m = (int)((d.m + BM - 1) / BM);
     const int tiles_n = (int)((d.p + BN - 1) / BN);
-    const int vec_a = (d.n % 8 == 0) && ((uintptr_t)A % 16 == 0);
-    hipLaunchKernelGGL((split_bf16_kernel<BM, BN, WM, WN>), dim3(tiles_m * tiles_n), dim3(256), 0,
-                       st, A, B, C, d.m, d.n, d.p, d.accumulate, tiles_m, tiles_n, vec_a);
+    constexpr int threads = (BM / WM) * (BN / WN) * 64;
+    hipLaunchKernelGGL((split_bf16_kernel<BM, BN, WM, WN>), dim3(tiles_m * tiles_n), dim3(threads), 0,
+                       st, Ap, Bp, C, d.m, d.p, S, d.accumulate, tiles_m, tiles_n);
     return hipGetLastError();
 }
 
@@ -213,23 +330,50 @@ hipError_t launch_shape(const moa_gemm_desc &d, hipStream_t st) {
 
 int split_bf16_variant_count() { return (int)(sizeof(kSplit) / sizeof(kSplit[0])); }
 
+int64_t split_bf16_workspace_bytes(int64_t m, int64_t n, int64_t p) {
+    const int64_t S = (n + SLAB - 1) / SLAB;
+    return (m + p) * S * REC_BYTES;
+}
+
 void split_bf16_shape(int v, Plan *p) {
     const SplitShape s = kSplit[v];
     p->variant = v;
     p->tile_m = s.bm;
     p->tile_n = s.bn;
-    p->tile_k = BK;
+    p->tile_k = SLAB;
     p->wave_m = s.wm;
     p->wave_n = s.wn;
     p->lane_m = p->lane_n = 0;
-    p->threads = 256;
-    p->lds_bytes = 2 * (s.bm + s.bn) * ROW * 2;
+    p->threads = (s.bm / s.wm) * (s.bn / s.wn) * 64;
+    p->lds_bytes = NSTAGE * (s.bm + s.bn) * REC_BYTES;
 }
 
-hipError_t launch_split_bf16(const moa_gemm_desc &d, const Plan &plan, hipStream_t st) {
+hipError_t launch_split_pack(const moa_gemm_desc &d, void *ws, hipStream_t st) {
+    const int64_t S = (d.n + SLAB - 1) / SLAB;
+    uint16_t *Ap = static_cast<uint16_t *>(ws);
+    uint16_t *Bp = Ap + d.m * S * REC;
+    const float *A = static_cast<const float *>(d.A);
+    const float *B = static_cast<const float *>(d.B);
+    if (S == 0) return hipSuccess;
+    const int vec = (d.n % 8 == 0) && ((uintptr_t)A % 16 == 0);
+    const int64_t chunks = d.m * S * 2;
+    int64_t blocks = (chunks + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(pack_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, d.m, d.n, S, vec, Ap);
+    hipLaunchKernelGGL(pack_cols_kernel, dim3((unsigned)((d.p + 63) / 64), (unsigned)((S + 3) / 4)), dim3(256),
+                       0, st, B, d.n, d.p, S, Bp);
+    return hipGetLastError();
+}
+
+hipError_t launch_split_bf16(const moa_gemm_desc &d, const Plan &plan, void *ws, hipStream_t st) {
+    hipError_t e = launch_split_pack(d, ws, st);
+    if (e != hipSuccess) return e;
+    const int64_t S = (d.n + SLAB - 1) / SLAB;
+    const uint16_t *Ap = static_cast<const uint16_t *>(ws);
+    const uint16_t *Bp = Ap + d.m * S * REC;
     switch (plan.variant) {
-    case 0: return launch_shape<128, 128, 64, 64>(d, st);
-    default: return launch_shape<256, 256, 128, 128>(d, st);
+    case 0: return launch_shape<128, 128, 64, 64>(d, Ap, Bp, S, st);
+    default: return launch_shape<256, 256, 128, 64>(d, Ap, Bp, S, st);
     }
 }
 
