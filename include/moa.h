@@ -127,13 +127,16 @@ typedef struct moa_plan_info {
  * MOA_ERR_NOMEM (scratch), MOA_ERR_DEVICE (launch failure). */
 moa_status moa_gemm(const moa_gemm_desc *desc, void *stream);
 
-/* `count` independent products in one persistent launch per path (all
- * members with the same resolved path share one launch). Members must not
- * write overlapping C. No ordering among members. Each result is bitwise the
- * result moa_gemm gives for the same descriptor. Descriptors are read on the
- * host during the call; the array may be reused when the call returns.
+/* `count` independent products. Members on the split-BF16 path (including
+ * F32 with MOA_PATH_AUTO) are conditioned together and contracted by ONE
+ * persistent launch that walks a shared tile list; members on other paths
+ * run as single launches on the same stream. No ordering among members. Each
+ * result is bitwise the result moa_gemm gives for the same descriptor.
+ * Descriptors are read on the host during the call; the array may be reused
+ * when the call returns.
  * Errors: as moa_gemm, checked for every member before anything launches;
- * MOA_ERR_INVALID for count < 0 or a null array with count > 0. */
+ * MOA_ERR_INVALID for count < 0, a null array with count > 0, or a member's
+ * C overlapping any member's A, B or C. */
 moa_status moa_gemm_grouped(const moa_gemm_desc *descs, int64_t count,
                             void *stream);
 

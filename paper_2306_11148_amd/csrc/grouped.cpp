@@ -1,19 +1,144 @@
-// Grouped products (placeholder: members run one after another on the
-// stream; replaced by the persistent grouped kernel).
+// moa_gemm_grouped: independent products in one launch sequence.
+//
+// Members on the split-BF16 path (the path of the batching workload) are
+// conditioned together and contracted by one persistent launch that walks a
+// shared tile list. Members on the other paths run as single launches, in
+// order, on the same stream. The member descriptors of the persistent launch
+// travel to the device through pinned staging buffers that are recycled once
+// the stream has consumed them.
+#include <algorithm>
+#include <mutex>
+#include <vector>
+
 #include "moa_internal.h"
+
+namespace moa {
+namespace {
+
+struct Staging {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+    hipEvent_t done = nullptr;
+};
+
+std::mutex g_staging_mu;
+std::vector<Staging> g_staging;
+
+moa_status staging_acquire(size_t bytes, Staging *out) {
+    {
+        std::lock_guard<std::mutex> lk(g_staging_mu);
+        for (size_t k = 0; k < g_staging.size(); ++k) {
+            if (g_staging[k].bytes >= bytes && hipEventQuery(g_staging[k].done) == hipSuccess) {
+                *out = g_staging[k];
+                g_staging.erase(g_staging.begin() + (long)k);
+                return MOA_OK;
+            }
+        }
+    }
+    Staging s;
+    s.bytes = bytes < 4096 ? 4096 : bytes;
+    hipError_t e = hipHostMalloc(&s.ptr, s.bytes, hipHostMallocDefault);
+    if (e != hipSuccess) return fail(MOA_ERR_NOMEM, "pinned staging of %zu bytes: %s", s.bytes, hipGetErrorString(e));
+    e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
+    if (e != hipSuccess) {
+        (void)hipHostFree(s.ptr);
+        return hip_fail(e, "hipEventCreateWithFlags");
+    }
+    *out = s;
+    return MOA_OK;
+}
+
+void staging_release(const Staging &s, hipStream_t stream) {
+    (void)hipEventRecord(s.done, stream);
+    std::lock_guard<std::mutex> lk(g_staging_mu);
+    g_staging.push_back(s);
+}
+
+}  // namespace
+
+moa_status check_group_overlap(const moa_gemm_desc *descs, int64_t count) {
+    struct Span { uintptr_t lo, hi; int64_t owner; };
+    std::vector<Span> outs;
+    for (int64_t g = 0; g < count; ++g) {
+        const moa_gemm_desc &d = descs[g];
+        const int64_t es = d.dtype == MOA_F64 ? 8 : 4;
+        if (d.m > 0 && d.p > 0)
+            outs.push_back({(uintptr_t)d.C, (uintptr_t)d.C + (uintptr_t)(d.m * d.p * es), g});
+    }
+    std::sort(outs.begin(), outs.end(), [](const Span &a, const Span &b) { return a.lo < b.lo; });
+    for (size_t k = 1; k < outs.size(); ++k)
+        if (outs[k].lo < outs[k - 1].hi)
+            return fail(MOA_ERR_INVALID, "C of members %lld and %lld overlap", (long long)outs[k - 1].owner,
+                        (long long)outs[k].owner);
+    auto hits = [&](uintptr_t lo, uintptr_t hi) {
+        // first output span ending after lo
+        size_t a = 0, b = outs.size();
+        while (a < b) {
+            const size_t mid = (a + b) / 2;
+            if (outs[mid].hi <= lo) a = mid + 1; else b = mid;
+        }
+        return a < outs.size() && outs[a].lo < hi;
+    };
+    for (int64_t g = 0; g < count; ++g) {
+        const moa_gemm_desc &d = descs[g];
+        const int64_t es = d.dtype == MOA_F64 ? 8 : 4;
+        if (d.m > 0 && d.n > 0 && hits((uintptr_t)d.A, (uintptr_t)d.A + (uintptr_t)(d.m * d.n * es)))
+            return fail(MOA_ERR_INVALID, "A of member %lld overlaps a member's C", (long long)g);
+        if (d.n > 0 && d.p > 0 && hits((uintptr_t)d.B, (uintptr_t)d.B + (uintptr_t)(d.n * d.p * es)))
+            return fail(MOA_ERR_INVALID, "B of member %lld overlaps a member's C", (long long)g);
+    }
+    return MOA_OK;
+}
+
+moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t stream) {
+    std::vector<const moa_gemm_desc *> split;
+    for (int64_t g = 0; g < count; ++g) {
+        const moa_gemm_desc &d = descs[g];
+        if (d.m == 0 || d.p == 0) continue;
+        if (resolve_path(d) == MOA_PATH_SPLIT_BF16) {
+            split.push_back(&d);
+        } else {
+            moa_status s = run_gemm(d, stream);
+            if (s != MOA_OK) return s;
+        }
+    }
+    if (split.empty()) return MOA_OK;
+    if (split.size() > (size_t)INT32_MAX) return fail(MOA_ERR_INVALID, "too many members");
+    const int cnt = (int)split.size();
+    void *ws = nullptr;
+    moa_status s = scratch_alloc(&ws, split_grouped_workspace_bytes(split.data(), cnt), stream);
+    if (s != MOA_OK) return s;
+    Staging st;
+    s = staging_acquire((size_t)split_grouped_desc_bytes(cnt), &st);
+    if (s != MOA_OK) {
+        scratch_free(ws, stream);
+        return s;
+    }
+    hipError_t e = launch_split_grouped(split.data(), cnt, ws, st.ptr, stream);
+    staging_release(st, stream);
+    scratch_free(ws, stream);
+    if (e != hipSuccess) return hip_fail(e, "grouped launch");
+    return MOA_OK;
+}
+
+}  // namespace moa
 
 using namespace moa;
 
 extern "C" moa_status moa_gemm_grouped(const moa_gemm_desc *descs, int64_t count, void *stream) {
-    if (count < 0) return fail(MOA_ERR_INVALID, "negative count");
-    if (count > 0 && !descs) return fail(MOA_ERR_INVALID, "null descriptor array");
-    for (int64_t g = 0; g < count; ++g) {
-        moa_status s = validate(descs[g], true);
+    try {
+        if (count < 0) return fail(MOA_ERR_INVALID, "negative count");
+        if (count > 0 && !descs) return fail(MOA_ERR_INVALID, "null descriptor array");
+        for (int64_t g = 0; g < count; ++g) {
+            moa_status s = validate(descs[g], true);
+            if (s != MOA_OK) return s;
+            Plan pl;
+            if (descs[g].m > 0 && descs[g].p > 0 && (s = make_plan(descs[g], &pl)) != MOA_OK) return s;
+        }
+        moa_status s = check_group_overlap(descs, count);
         if (s != MOA_OK) return s;
+        return run_grouped(descs, count, static_cast<hipStream_t>(stream));
+    } catch (...) {
+        return fail(MOA_ERR_DEVICE, "internal error");
     }
-    for (int64_t g = 0; g < count; ++g) {
-        moa_status s = run_gemm(descs[g], static_cast<hipStream_t>(stream));
-        if (s != MOA_OK) return s;
-    }
-    return MOA_OK;
 }

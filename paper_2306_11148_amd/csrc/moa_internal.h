@@ -75,6 +75,14 @@ hipError_t launch_split_pack(const moa_gemm_desc &d, void *workspace, hipStream_
 void split_bf16_shape(int variant, Plan *p);
 int split_bf16_variant_count();
 int64_t split_bf16_workspace_bytes(int64_t m, int64_t n, int64_t p);
+// Grouped split-BF16: all `members` in one conditioning pass and one
+// persistent launch. `host_staging` is pinned memory of at least
+// split_grouped_desc_bytes(count) bytes that stays untouched until the
+// stream has passed this call.
+int64_t split_grouped_workspace_bytes(const moa_gemm_desc *const *members, int count);
+int64_t split_grouped_desc_bytes(int count);
+hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, void *workspace,
+                                void *host_staging, hipStream_t stream);
 
 hipError_t launch_fp8(const moa_gemm_desc &d, const Plan &plan, void *workspace,
                       hipStream_t stream);
@@ -93,6 +101,11 @@ hipError_t launch_error_norm(int64_t count, moa_dtype xt, const void *X, const d
 // Runs one product: plan + scratch + launch. Used by moa_gemm and by the
 // grouped and serving paths for members that run alone.
 moa_status run_gemm(const moa_gemm_desc &d, hipStream_t stream);
+
+// Grouped products (validated by the caller): split-BF16 members in one
+// persistent launch, the others one after another.
+moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t stream);
+moa_status check_group_overlap(const moa_gemm_desc *descs, int64_t count);
 
 // Stream-ordered scratch (hipMallocAsync on the default pool of the current
 // device, pool kept warm).

@@ -29,6 +29,9 @@
 // distinct 16-byte bank groups. The direct loads stay linear (lane L writes
 // bytes 16L .. 16L+15 of its wave's 1 KiB window = 16 rows), so each lane
 // fetches the logical chunk that belongs at its physical position.
+#include <algorithm>
+#include <vector>
+
 #include "moa_internal.h"
 #include "tile_common.h"
 
@@ -55,49 +58,53 @@ __device__ __forceinline__ void ring_barrier() { asm volatile("s_barrier" ::: "m
 
 // ---------------------------------------------------------------- stage 1 --
 
-// Rows of X (rows x K, row-major) -> records. One thread per 8-k chunk.
+// Rows of X (rows x K, row-major) -> records: chunk q = 8 k values of one
+// record (2 chunks per record).
+__device__ __forceinline__ void pack_rows_chunk(const float *__restrict__ X, int64_t K, int64_t S,
+                                                int vec, uint16_t *__restrict__ P, int64_t q) {
+    const int64_t r = q / (S * 2);
+    const int64_t rem = q - r * S * 2;
+    const int64_t s = rem >> 1;
+    const int c = (int)(rem & 1);
+    const int64_t k = s * SLAB + c * 8;
+    float x[8];
+    if (vec && k + 8 <= K) {
+        const float4 *src = reinterpret_cast<const float4 *>(X + r * K + k);
+        const float4 a = src[0], b = src[1];
+        x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
+        x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = (k + e < K) ? X[r * K + k + e] : 0.0f;
+    }
+    uint4 hi, lo;
+    split_pair(x[0], x[1], &hi.x, &lo.x);
+    split_pair(x[2], x[3], &hi.y, &lo.y);
+    split_pair(x[4], x[5], &hi.z, &lo.z);
+    split_pair(x[6], x[7], &hi.w, &lo.w);
+    uint16_t *rec = P + (r * S + s) * REC;
+    *reinterpret_cast<uint4 *>(rec + c * 8) = hi;
+    *reinterpret_cast<uint4 *>(rec + SLAB + c * 8) = lo;
+}
+
 __global__ __launch_bounds__(256) void pack_rows_kernel(const float *__restrict__ X, int64_t rows,
                                                         int64_t K, int64_t S, int vec,
                                                         uint16_t *__restrict__ P) {
     const int64_t chunks = rows * S * 2;
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < chunks; q += stride) {
-        const int64_t r = q / (S * 2);
-        const int64_t rem = q - r * S * 2;
-        const int64_t s = rem >> 1;
-        const int c = (int)(rem & 1);
-        const int64_t k = s * SLAB + c * 8;
-        float x[8];
-        if (vec && k + 8 <= K) {
-            const float4 *src = reinterpret_cast<const float4 *>(X + r * K + k);
-            const float4 a = src[0], b = src[1];
-            x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
-            x[4] = b.x; x[5] = b.y; x[6] = b.z; x[7] = b.w;
-        } else {
-#pragma unroll
-            for (int e = 0; e < 8; ++e) x[e] = (k + e < K) ? X[r * K + k + e] : 0.0f;
-        }
-        uint4 hi, lo;
-        split_pair(x[0], x[1], &hi.x, &lo.x);
-        split_pair(x[2], x[3], &hi.y, &lo.y);
-        split_pair(x[4], x[5], &hi.z, &lo.z);
-        split_pair(x[6], x[7], &hi.w, &lo.w);
-        uint16_t *rec = P + (r * S + s) * REC;
-        *reinterpret_cast<uint4 *>(rec + c * 8) = hi;
-        *reinterpret_cast<uint4 *>(rec + SLAB + c * 8) = lo;
-    }
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < chunks; q += (int64_t)gridDim.x * 256)
+        pack_rows_chunk(X, K, S, vec, P, q);
 }
 
-// Columns of X (K x cols, row-major) -> records (transposed). A 64 x 64 block
-// (four slabs of 64 columns) per workgroup goes through LDS; reads of X rows
-// are contiguous, and each thread writes one whole 64-byte record, four
-// neighbouring threads four consecutive records of one column.
-__global__ __launch_bounds__(256) void pack_cols_kernel(const float *__restrict__ X, int64_t K,
-                                                        int64_t cols, int64_t S,
-                                                        uint16_t *__restrict__ P) {
-    __shared__ float tile[4 * SLAB][64 + 1];
-    const int64_t j0 = (int64_t)blockIdx.x * 64;
-    const int64_t s0 = (int64_t)blockIdx.y * 4;
+// Columns of X (K x cols, row-major) -> records (transposed). Block (bx, by)
+// covers columns 64 bx .. 64 bx + 63 and slabs 4 by .. 4 by + 3; it goes
+// through LDS so that reads of X rows are contiguous and each thread writes
+// one whole 64-byte record (four neighbouring threads: four consecutive
+// records of one column). All 256 threads must call it together.
+__device__ __forceinline__ void pack_cols_block(const float *__restrict__ X, int64_t K, int64_t cols,
+                                                int64_t S, uint16_t *__restrict__ P, int64_t bx,
+                                                int64_t by, float (*tile)[64 + 1]) {
+    const int64_t j0 = bx * 64;
+    const int64_t s0 = by * 4;
     const int t = threadIdx.x;
     {
         const int jj = t & 63;
@@ -129,30 +136,41 @@ __global__ __launch_bounds__(256) void pack_cols_kernel(const float *__restrict_
     rec[3] = l[1];
 }
 
+__global__ __launch_bounds__(256) void pack_cols_kernel(const float *__restrict__ X, int64_t K,
+                                                        int64_t cols, int64_t S,
+                                                        uint16_t *__restrict__ P) {
+    __shared__ float tile[4 * SLAB][64 + 1];
+    pack_cols_block(X, K, cols, S, P, blockIdx.x, blockIdx.y, tile);
+}
+
 // ---------------------------------------------------------------- stage 2 --
 
-template <int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void split_bf16_kernel(
-    const uint16_t *__restrict__ Ap, const uint16_t *__restrict__ Bp, float *__restrict__ C,
-    int64_t m, int64_t p, int64_t S, int accumulate, int tiles_m, int tiles_n) {
-    constexpr int WAVES_M = BM / WM, WAVES_N = BN / WN, NW = WAVES_M * WAVES_N;
-    constexpr int FM = WM / 32, FN = WN / 32;
-    constexpr int ROWS = BM + BN;                     // records per slab
-    constexpr int STAGE = ROWS * REC_BYTES;           // bytes per LDS buffer
-    constexpr int LPW = ROWS / 16 / NW;               // 1 KiB direct loads per wave per slab
+// Geometry of one block configuration.
+template <int BM, int BN, int WM, int WN> struct TileCfg {
+    static constexpr int WAVES_M = BM / WM, WAVES_N = BN / WN, NW = WAVES_M * WAVES_N;
+    static constexpr int THREADS = NW * 64;
+    static constexpr int FM = WM / 32, FN = WN / 32;
+    static constexpr int ROWS = BM + BN;                  // records per slab
+    static constexpr int STAGE = ROWS * REC_BYTES;        // bytes per LDS buffer
+    static constexpr int LDS = NSTAGE * STAGE;
+    static constexpr int LPW = ROWS / 16 / NW;            // 1 KiB direct loads per wave per slab
     static_assert(ROWS % (16 * NW) == 0 && BM % 16 == 0, "whole loads per wave");
-    __shared__ __attribute__((aligned(1024))) uint8_t lds[NSTAGE * STAGE];
+};
 
+// One BM x BN block of C at (i0, j0): the whole k walk and the epilogue.
+// `lds` is the workgroup's ring of NSTAGE buffers. On entry no wave may still
+// be reading `lds` (the caller's barrier); on exit every wave has finished.
+template <int BM, int BN, int WM, int WN>
+__device__ __forceinline__ void split_tile(const uint16_t *__restrict__ Ap,
+                                           const uint16_t *__restrict__ Bp, float *__restrict__ C,
+                                           int64_t m, int64_t p, int64_t S, int accumulate,
+                                           int64_t i0, int64_t j0, uint8_t *lds) {
+    using G = TileCfg<BM, BN, WM, WN>;
+    constexpr int WAVES_N = G::WAVES_N, FM = G::FM, FN = G::FN;
+    constexpr int STAGE = G::STAGE, LPW = G::LPW;
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int wm = wave / WAVES_N, wn = wave % WAVES_N;
-    int tm, tn;
-    tile_coords(xcd_remap(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, &tm, &tn);
-    // the integer divisions above run on the vector ALU; pin the (uniform)
-    // results to scalar registers so everything derived from them stays scalar
-    tm = __builtin_amdgcn_readfirstlane(tm);
-    tn = __builtin_amdgcn_readfirstlane(tn);
-    const int64_t i0 = (int64_t)tm * BM, j0 = (int64_t)tn * BN;
 
     // Direct loads through two buffer resources based at this tile's first
     // record row of A and of B. Load Q = wave*LPW + q fills LDS rows
@@ -292,6 +310,94 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void split_bf16_kernel(
         }
 }
 
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void split_bf16_kernel(
+    const uint16_t *__restrict__ Ap, const uint16_t *__restrict__ Bp, float *__restrict__ C,
+    int64_t m, int64_t p, int64_t S, int accumulate, int tiles_m, int tiles_n) {
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[TileCfg<BM, BN, WM, WN>::LDS];
+    int tm, tn;
+    tile_coords(xcd_remap(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, &tm, &tn);
+    // the integer divisions above run on the vector ALU; pin the (uniform)
+    // results to scalar registers so everything derived from them stays scalar
+    tm = __builtin_amdgcn_readfirstlane(tm);
+    tn = __builtin_amdgcn_readfirstlane(tn);
+    split_tile<BM, BN, WM, WN>(Ap, Bp, C, m, p, S, accumulate, (int64_t)tm * BM, (int64_t)tn * BN, lds);
+}
+
+// ------------------------------------------------------- grouped (persistent)
+// Independent products share one launch. Members are listed longest k walk
+// first; their tiles form one work list (member g owns tile ids
+// [first[g], first[g+1])), and persistent workgroups claim tile ids from an
+// atomic counter until the list is exhausted. Every element of every member
+// receives exactly the operation sequence of the single-product kernel (the
+// per-element order depends only on the slab walk, not on the block shape),
+// so grouped and single results are bitwise equal.
+struct GroupMember {
+    const float *A, *B;
+    float *C;
+    uint16_t *Ap, *Bp;                  // records of this member in the workspace
+    int64_t m, n, p, S;
+    int64_t first_tile;                 // first work-list id of this member
+    int32_t tiles_n, accumulate;
+};
+
+__device__ __forceinline__ int find_member(const GroupMember *__restrict__ g, int count, int64_t tile) {
+    int lo = 0, hi = count - 1;         // last member with first_tile <= tile
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (g[mid].first_tile <= tile) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+template <int BM, int BN, int WM, int WN>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void split_grouped_kernel(
+    const GroupMember *__restrict__ g, int count, int64_t total_tiles,
+    unsigned long long *__restrict__ counter) {
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[TileCfg<BM, BN, WM, WN>::LDS];
+    __shared__ int64_t s_tile;
+    for (;;) {
+        __syncthreads();                // nobody still reads lds or s_tile
+        if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(counter, 1ull);
+        __syncthreads();
+        const int64_t tile = s_tile;
+        if (tile >= total_tiles) break;
+        const int k = __builtin_amdgcn_readfirstlane(find_member(g, count, tile));
+        const GroupMember &d = g[k];
+        const int64_t local = tile - d.first_tile;
+        const int64_t tm = local / d.tiles_n, tn = local - tm * d.tiles_n;
+        split_tile<BM, BN, WM, WN>(d.Ap, d.Bp, d.C, d.m, d.p, d.S, d.accumulate,
+                                   __builtin_amdgcn_readfirstlane((int)tm) * (int64_t)BM,
+                                   __builtin_amdgcn_readfirstlane((int)tn) * (int64_t)BN, lds);
+    }
+}
+
+// Grouped conditioning: each workgroup walks a share of every member's
+// chunks (rows of A) and 64 x 64 blocks (columns of B).
+__global__ __launch_bounds__(256) void grouped_pack_rows_kernel(const GroupMember *__restrict__ g,
+                                                                int count) {
+    for (int k = blockIdx.y; k < count; k += gridDim.y) {
+        const GroupMember d = g[k];
+        const int vec = (d.n % 8 == 0) && ((uintptr_t)d.A % 16 == 0);
+        const int64_t chunks = d.m * d.S * 2;
+        for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < chunks; q += (int64_t)gridDim.x * 256)
+            pack_rows_chunk(d.A, d.n, d.S, vec, d.Ap, q);
+    }
+}
+
+__global__ __launch_bounds__(256) void grouped_pack_cols_kernel(const GroupMember *__restrict__ g,
+                                                                int count) {
+    __shared__ float tile[4 * SLAB][64 + 1];
+    for (int k = blockIdx.y; k < count; k += gridDim.y) {
+        const GroupMember d = g[k];
+        const int64_t bx = (d.p + 63) / 64, by = (d.S + 3) / 4;
+        for (int64_t b = blockIdx.x; b < bx * by; b += gridDim.x) {
+            __syncthreads();
+            pack_cols_block(d.B, d.n, d.p, d.S, d.Bp, b % bx, b / bx, tile);
+        }
+    }
+}
+
 // Standalone conditioning kernel: hi/lo planes of a row-major FP32 array.
 __global__ __launch_bounds__(256) void split_only_kernel(const float *__restrict__ X, int64_t count,
                                                          uint16_t *__restrict__ hi,
@@ -375,6 +481,68 @@ hipError_t launch_split_bf16(const moa_gemm_desc &d, const Plan &plan, void *ws,
     case 0: return launch_shape<128, 128, 64, 64>(d, Ap, Bp, S, st);
     default: return launch_shape<256, 256, 128, 64>(d, Ap, Bp, S, st);
     }
+}
+
+namespace {
+__global__ void zero_u64_kernel(unsigned long long *x) { *x = 0ull; }
+constexpr int GB_M = 128, GB_N = 128, GW_M = 64, GW_N = 64;   // grouped block shape
+int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+}  // namespace
+
+int64_t split_grouped_workspace_bytes(const moa_gemm_desc *const *members, int count) {
+    int64_t b = 256 + align256((int64_t)count * (int64_t)sizeof(GroupMember));
+    for (int k = 0; k < count; ++k)
+        b += align256(split_bf16_workspace_bytes(members[k]->m, members[k]->n, members[k]->p));
+    return b;
+}
+
+int64_t split_grouped_desc_bytes(int count) { return (int64_t)count * (int64_t)sizeof(GroupMember); }
+
+hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, void *ws,
+                                void *host_staging, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    // longest k walk first: the tail of the work list holds the cheapest tiles
+    std::vector<int> order(count);
+    for (int k = 0; k < count; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        return members[a]->n > members[b]->n;
+    });
+    char *base = static_cast<char *>(ws);
+    unsigned long long *counter = reinterpret_cast<unsigned long long *>(base);
+    GroupMember *dev_members = reinterpret_cast<GroupMember *>(base + 256);
+    char *rec = base + 256 + align256((int64_t)count * (int64_t)sizeof(GroupMember));
+    GroupMember *h = static_cast<GroupMember *>(host_staging);
+    int64_t tiles = 0;
+    for (int q = 0; q < count; ++q) {
+        const moa_gemm_desc &d = *members[order[q]];
+        GroupMember g;
+        g.A = static_cast<const float *>(d.A);
+        g.B = static_cast<const float *>(d.B);
+        g.C = static_cast<float *>(d.C);
+        g.m = d.m; g.n = d.n; g.p = d.p;
+        g.S = (d.n + SLAB - 1) / SLAB;
+        g.Ap = reinterpret_cast<uint16_t *>(rec);
+        g.Bp = g.Ap + d.m * g.S * REC;
+        rec += align256(split_bf16_workspace_bytes(d.m, d.n, d.p));
+        g.first_tile = tiles;
+        g.tiles_n = (int32_t)((d.p + GB_N - 1) / GB_N);
+        g.accumulate = d.accumulate;
+        tiles += ((d.m + GB_M - 1) / GB_M) * g.tiles_n;
+        h[q] = g;
+    }
+    hipError_t e = hipMemcpyAsync(dev_members, h, (size_t)count * sizeof(GroupMember),
+                                  hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, st, counter);
+    const unsigned gy = (unsigned)std::min(count, 65535);
+    hipLaunchKernelGGL(grouped_pack_rows_kernel, dim3(32, gy), dim3(256), 0, st, dev_members, count);
+    hipLaunchKernelGGL(grouped_pack_cols_kernel, dim3(16, gy), dim3(256), 0, st, dev_members, count);
+    const int64_t grid = std::min<int64_t>(tiles, 2 * kNumCUs);   // two 64 KiB-LDS blocks per CU
+    if (grid > 0)
+        hipLaunchKernelGGL((split_grouped_kernel<GB_M, GB_N, GW_M, GW_N>), dim3((unsigned)grid),
+                           dim3(TileCfg<GB_M, GB_N, GW_M, GW_N>::THREADS), 0, st, dev_members, count,
+                           tiles, counter);
+    return hipGetLastError();
 }
 
 hipError_t launch_split_only(const float *X, int64_t count, uint16_t *hi, uint16_t *lo,

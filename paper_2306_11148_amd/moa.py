@@ -202,3 +202,37 @@ def moa_error_norm(X, R, out, stream=None):
     _check(lib().moa_error_norm(X.numel(), _dtype_code(X), X.data_ptr(), R.data_ptr(),
                                 out.data_ptr(), _stream_handle(stream)), "moa_error_norm")
     return out
+
+
+# ------------------------------------------------------------------ serving --
+
+def moa_serve_create(hbm_budget_bytes: int, slots: int = 4, max_group: int = 16, device: int = 0):
+    """Start a server; returns an opaque handle (int)."""
+    cfg = moa_serve_cfg(hbm_budget_bytes, slots, max_group, device, 0)
+    h = ctypes.c_void_p()
+    _check(lib().moa_serve_create(ctypes.byref(cfg), ctypes.byref(h)), "moa_serve_create")
+    return h.value
+
+
+def moa_serve_submit(srv, desc: moa_gemm_desc) -> int:
+    t = ctypes.c_uint64()
+    _check(lib().moa_serve_submit(srv, ctypes.byref(desc), ctypes.byref(t)), "moa_serve_submit")
+    return t.value
+
+
+def moa_serve_poll(srv, ticket: int):
+    """Request info as a dict once done, None while it runs."""
+    info = moa_req_info()
+    s = lib().moa_serve_poll(srv, ticket, ctypes.byref(info))
+    if s == MOA_NOT_READY:
+        return None
+    _check(s, "moa_serve_poll")
+    return {f: getattr(info, f) for f, _ in moa_req_info._fields_}
+
+
+def moa_serve_drain(srv):
+    _check(lib().moa_serve_drain(srv), "moa_serve_drain")
+
+
+def moa_serve_destroy(srv):
+    _check(lib().moa_serve_destroy(srv), "moa_serve_destroy")

@@ -110,3 +110,31 @@ def test_descriptor_layout_matches_header():
     assert ctypes.sizeof(moa.moa_gemm_desc) == 3 * 8 + 2 * 4 + 3 * 8 + 2 * 4
     assert moa.moa_gemm_desc.A.offset == 32
     assert ctypes.sizeof(moa.moa_plan_info) == 11 * 4 + 4 + 3 * 8
+
+
+def test_grouped_overlap_rejected_before_launch():
+    L = moa.lib()
+    d1 = _desc(4, 4, 4, A=0x10000, B=0x20000, C=0x30000)
+    d2 = _desc(4, 4, 4, A=0x40000, B=0x50000, C=0x30000 + 32)      # C overlaps d1's C
+    arr = (moa.moa_gemm_desc * 2)(d1, d2)
+    assert L.moa_gemm_grouped(arr, 2, None) == moa.MOA_ERR_INVALID
+    d3 = _desc(4, 4, 4, A=0x30000, B=0x50000, C=0x60000)            # A reads d1's C
+    arr = (moa.moa_gemm_desc * 2)(d1, d3)
+    assert L.moa_gemm_grouped(arr, 2, None) == moa.MOA_ERR_INVALID
+    bad = _desc(-1, 4, 4)
+    arr = (moa.moa_gemm_desc * 2)(d1, bad)
+    assert L.moa_gemm_grouped(arr, 2, None) == moa.MOA_ERR_SHAPE
+
+
+def test_serve_argument_errors_before_device():
+    L = moa.lib()
+    h = ctypes.c_void_p()
+    assert L.moa_serve_create(None, ctypes.byref(h)) == moa.MOA_ERR_INVALID
+    for cfg in (moa.moa_serve_cfg(0, 1, 1, 0, 0), moa.moa_serve_cfg(1 << 30, 0, 1, 0, 0),
+                moa.moa_serve_cfg(1 << 30, 1, 0, 0, 0)):
+        assert L.moa_serve_create(ctypes.byref(cfg), ctypes.byref(h)) == moa.MOA_ERR_INVALID
+    t = ctypes.c_uint64()
+    assert L.moa_serve_submit(None, None, ctypes.byref(t)) == moa.MOA_ERR_INVALID
+    assert L.moa_serve_poll(None, 1, None) == moa.MOA_ERR_INVALID
+    assert L.moa_serve_drain(None) == moa.MOA_ERR_INVALID
+    assert L.moa_serve_destroy(None) == moa.MOA_OK

@@ -1,0 +1,105 @@
+"""Grouped products: one persistent launch for the split-BF16 members.
+
+* Each member's result is bitwise the result of moa_gemm on the same
+  descriptor (the per-element operation sequence does not depend on which
+  launch or block shape produced it).
+* The batching workload at full size -- 512 products, m, n, p log-uniform in
+  [32, 2048], N(0,1) FP32 -- is checked member by member against the FP64
+  oracle (normwise <= 1e-5).
+"""
+import numpy as np
+import pytest
+import torch
+
+from oracle import oracle as O
+from paper_2306_11148_amd import inputs, moa
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda:0"
+
+
+def make_members(shapes, seed, path="split_bf16", accumulate=False):
+    ops = inputs.grouped_operands(shapes, seed=seed)
+    host, dev, descs = [], [], []
+    for (A, B) in ops:
+        At = torch.from_numpy(A).to(DEV)
+        Bt = torch.from_numpy(B).to(DEV)
+        C0 = (np.arange(A.shape[0] * B.shape[1], dtype=np.float32).reshape(A.shape[0], B.shape[1]) % 7
+              if accumulate else np.full((A.shape[0], B.shape[1]), np.nan, np.float32))
+        Ct = torch.from_numpy(C0).to(DEV)
+        host.append((A, B, C0))
+        dev.append((At, Bt, Ct))
+        descs.append(moa.make_desc(At, Bt, Ct, path=path, accumulate=accumulate))
+    return host, dev, descs
+
+
+def singles(host, path, accumulate=False):
+    out = []
+    for A, B, C0 in host:
+        At, Bt, Ct = (torch.from_numpy(x).to(DEV) for x in (A, B, C0))
+        moa.moa_gemm(At, Bt, Ct, path=path, accumulate=accumulate)
+        out.append(Ct)
+    torch.cuda.synchronize()
+    return [c.cpu().numpy() for c in out]
+
+
+@pytest.mark.parametrize("accumulate", [False, True])
+def test_grouped_split_bitwise_equals_single(accumulate):
+    shapes = inputs.grouped_shapes(40, lo=1, hi=700, seed=14)
+    host, dev, descs = make_members(shapes, seed=14, accumulate=accumulate)
+    moa.moa_gemm_grouped(descs)
+    torch.cuda.synchronize()
+    ref = singles(host, "split_bf16", accumulate)
+    for k, ((A, B, C0), (_, _, Ct)) in enumerate(zip(host, dev)):
+        got = Ct.cpu().numpy()
+        assert np.array_equal(got, ref[k]), f"member {k} shape {A.shape} x {B.shape}"
+        R = O.gemm_f64(A.astype(np.float64), B.astype(np.float64),
+                       C0.astype(np.float64) if accumulate else None, accumulate)
+        assert O.rel_err(got, R) <= 1e-5
+
+
+def test_grouped_mixed_paths_bitwise_equals_single():
+    shapes = inputs.grouped_shapes(12, lo=5, hi=300, seed=21)
+    paths = ["split_bf16", "onf", "fp8", "mfma_f32"] * 3
+    ops = inputs.grouped_operands(shapes, seed=21)
+    descs, outs, refs = [], [], []
+    for (A, B), path in zip(ops, paths):
+        At, Bt = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+        Ct = torch.empty((A.shape[0], B.shape[1]), device=DEV)
+        Rt = torch.empty_like(Ct)
+        descs.append(moa.make_desc(At, Bt, Ct, path=path))
+        outs.append((At, Bt, Ct))
+        moa.moa_gemm(At, Bt, Rt, path=path)
+        refs.append(Rt)
+    moa.moa_gemm_grouped(descs)
+    torch.cuda.synchronize()
+    for (At, Bt, Ct), Rt in zip(outs, refs):
+        assert torch.equal(Ct, Rt)
+
+
+def test_grouped_empty_members_and_empty_group():
+    A = torch.zeros((0, 4), device=DEV)
+    B = torch.zeros((4, 3), device=DEV)
+    C = torch.zeros((0, 3), device=DEV)
+    moa.moa_gemm_grouped([moa.make_desc(A, B, C)])
+    moa.moa_gemm_grouped([])
+    A2 = torch.zeros((5, 0), device=DEV)
+    B2 = torch.zeros((0, 6), device=DEV)
+    C2 = torch.full((5, 6), 3.0, device=DEV)
+    moa.moa_gemm_grouped([moa.make_desc(A2, B2, C2)])
+    torch.cuda.synchronize()
+    assert torch.all(C2 == 0)
+
+
+def test_grouped_batching_workload_full_size():
+    """512 products, m, n, p log-uniform in [32, 2048] (seed 4): every member
+    against the FP64 oracle."""
+    shapes = inputs.grouped_shapes(512, 32, 2048, seed=4)
+    host, dev, descs = make_members(shapes, seed=4)
+    moa.moa_gemm_grouped(descs)
+    torch.cuda.synchronize()
+    worst = 0.0
+    for (A, B, _), (_, _, Ct) in zip(host, dev):
+        R = O.gemm_f64(A.astype(np.float64), B.astype(np.float64))
+        worst = max(worst, O.rel_err(Ct.cpu().numpy(), R))
+    assert worst <= 1e-5, worst
