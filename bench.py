@@ -30,6 +30,7 @@ BF16_PEAK_TF = 2516.6       # dense BF16 matrix-core peak, MI355X
 FP32_VEC_PEAK_TF = 157.3    # FP32 vector peak with packed FMA, MI355X
 FP32_FMA_UNPACKED_TF = 78.6  # one v_fma_f32 per lane per clock: 256 CU x 64 lanes x 2 x 2.4 GHz
 FP8_PEAK_TF = 5033.2
+COPY_CAL_BYTES = 192 * 2 ** 20   # size of the calibration copy for HBM byte counters
 
 
 def parse():
@@ -43,6 +44,10 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-energy", action="store_true")
+    ap.add_argument("--serve-rate", type=float, default=5000.0)
+    ap.add_argument("--serve-seconds", type=float, default=1.0)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-grouped", action="store_true")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of known size (for counter scaling)")
     return ap.parse_args()
@@ -134,18 +139,37 @@ def pct(xs, q):
 
 
 def energy_per_call(fn, seconds, ms_each, energy, torch):
+    """Board joules per call over about `seconds` of back-to-back calls, with
+    the GFX clock and socket power sampled every 10 ms while they run."""
     if energy is None or energy.h is None:
         return None
+    import threading
     reps = max(5, int(seconds * 1e3 / max(ms_each, 1e-3)))
+    samples, stop = [], threading.Event()
+
+    def sampler():
+        while not stop.is_set():
+            samples.append(energy.snapshot())
+            time.sleep(0.01)
+
     torch.cuda.synchronize()
+    th = threading.Thread(target=sampler)
     e0, t0 = energy.joules(), time.perf_counter()
+    th.start()
     for _ in range(reps):
         fn()
     torch.cuda.synchronize()
     e1, t1 = energy.joules(), time.perf_counter()
-    snap = energy.snapshot()
+    stop.set()
+    th.join()
+
+    def med(key):
+        v = sorted(x[key] for x in samples if isinstance(x.get(key), (int, float)))
+        return v[len(v) // 2] if v else None
     return {"joules_per_gemm": (e1 - e0) / reps, "reps": reps, "seconds": t1 - t0,
-            "avg_power_w": (e1 - e0) / (t1 - t0), **snap}
+            "avg_power_w": (e1 - e0) / (t1 - t0), "median_gfx_clock_mhz": med("gfx_clock_mhz"),
+            "median_power_w": med("power_w"), "median_temp_hotspot_c": med("temp_hotspot_c"),
+            "clock_samples": len(samples)}
 
 
 def cpu_baseline(A, B, C_gpu, n, target_s):
@@ -180,6 +204,117 @@ def cpu_baseline(A, B, C_gpu, n, target_s):
             "sample": f"{len(all_rows)} seeded rows of the {n}^3 FP32 product (inputs widened to "
                       f"FP64), {done_t:.1f} s of oracle time",
             "seconds": done_t}, err
+
+
+def grouped_section(torch, moa, inputs, reps=10):
+    """512 products, m, n, p log-uniform in [32, 2048] (seed 4), N(0,1) FP32
+    operands drawn on the device from a seeded generator: one grouped launch
+    versus one launch per product."""
+    shapes = inputs.grouped_shapes(512, 32, 2048, seed=4)
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    descs, keep = [], []
+    for m, n, p in shapes:
+        A = torch.randn((int(m), int(n)), generator=gen, device="cuda")
+        B = torch.randn((int(n), int(p)), generator=gen, device="cuda")
+        C = torch.empty((int(m), int(p)), device="cuda")
+        keep.append((A, B, C))
+        descs.append(moa.make_desc(A, B, C, path=moa.MOA_PATH_SPLIT_BF16))
+    flops = float(sum(2.0 * m * n * p for m, n, p in shapes))
+    import ctypes
+    arr = (moa.moa_gemm_desc * len(descs))(*descs)
+    L, st = moa.lib(), torch.cuda.current_stream().cuda_stream
+
+    def grouped():
+        if L.moa_gemm_grouped(arr, len(descs), st) != 0:
+            raise RuntimeError(moa.moa_last_error())
+
+    def singles():
+        for d in descs:
+            if L.moa_gemm(ctypes.byref(d), st) != 0:
+                raise RuntimeError(moa.moa_last_error())
+    for _ in range(2):
+        grouped()
+        singles()
+    per_g, tot_g = timed_loop(grouped, reps, torch)
+    per_s, tot_s = timed_loop(singles, reps, torch)
+    ms_g, ms_s = tot_g / reps, tot_s / reps
+    del keep
+    return {"workload": "512 products, m,n,p log-uniform [32,2048], split-BF16, seed 4",
+            "flop": flops, "grouped_ms": round(ms_g, 4), "per_gemm_launches_ms": round(ms_s, 4),
+            "grouped_tflops": round(flops / ms_g / 1e9, 2),
+            "per_gemm_tflops": round(flops / ms_s / 1e9, 2),
+            "speedup": round(ms_s / ms_g, 3)}
+
+
+def serving_section(torch, moa, inputs, rate, seconds, seed=5):
+    """Open-loop Poisson arrivals at `rate` req/s for `seconds`: m, p log-uniform
+    [64, 4096], n log-uniform [64, 8192], 70% split-BF16 / 30% two-term FP8.
+    Operands are contiguous slices of two resident N(0,1) pools; results go to
+    a ring arena. Latency = completion - scheduled arrival (no coordinated
+    omission: requests are submitted at their scheduled times, late or not)."""
+    import ctypes
+    import numpy as np
+    count = max(1, int(rate * seconds))
+    t_arr, shapes, split = inputs.serving_stream(count, rate, seed=seed)
+    gen = torch.Generator(device="cuda").manual_seed(seed)
+    pool_elems = 4096 * 8192
+    pool_a = torch.randn(pool_elems, generator=gen, device="cuda")
+    pool_b = torch.randn(pool_elems, generator=gen, device="cuda")
+    off_a = inputs.pool_offsets(seed + 1, count, shapes[:, 0] * shapes[:, 1], pool_elems)
+    off_b = inputs.pool_offsets(seed + 2, count, shapes[:, 1] * shapes[:, 2], pool_elems)
+    arena_elems = 1 << 30
+    arena = torch.empty(arena_elems, device="cuda")
+    srv = moa.moa_serve_create(200 << 30, slots=4, max_group=16)
+    L = moa.lib()
+    tickets, sched_ns, flops = [], [], 0.0
+    held = []                       # (arena start, end, ticket) in allocation order
+    cursor = 0
+    try:
+        t0 = time.monotonic_ns() + 20_000_000
+        for q in range(count):
+            m, n, p = (int(x) for x in shapes[q])
+            size = m * p
+            if cursor + size > arena_elems:
+                cursor = 0
+            while held and held[0][0] < cursor + size and cursor < held[0][1]:
+                if moa.moa_serve_poll(srv, held[0][2]) is None:
+                    continue
+                held.pop(0)
+            A = pool_a[off_a[q]:off_a[q] + m * n].view(m, n)
+            B = pool_b[off_b[q]:off_b[q] + n * p].view(n, p)
+            C = arena[cursor:cursor + size].view(m, p)
+            path = moa.MOA_PATH_SPLIT_BF16 if split[q] else moa.MOA_PATH_FP8_SCALED
+            flags = 0 if split[q] else moa.MOA_FLAG_FP8_TWO_TERM
+            d = moa.make_desc(A, B, C, path=path, flags=flags)
+            due = t0 + int(t_arr[q] * 1e9)
+            while time.monotonic_ns() < due:
+                pass
+            tk = ctypes.c_uint64()
+            if L.moa_serve_submit(srv, ctypes.byref(d), ctypes.byref(tk)) != 0:
+                raise RuntimeError(moa.moa_last_error())
+            tickets.append(tk.value)
+            sched_ns.append(due)
+            held.append((cursor, cursor + size, tk.value))
+            cursor += size
+            flops += 2.0 * m * n * p
+        moa.moa_serve_drain(srv)
+        infos = [moa.moa_serve_poll(srv, t) for t in tickets]
+    finally:
+        moa.moa_serve_destroy(srv)
+    lat = np.array([(i["t_done_ns"] - s) / 1e6 for i, s in zip(infos, sched_ns)])
+    skip = int(0.05 * count)
+    body = lat[skip:]
+    span = (max(i["t_done_ns"] for i in infos) - sched_ns[0]) / 1e9
+    bad = sum(1 for i in infos if i["status"] != 0)
+    groups = np.array([i["group_size"] for i in infos])
+    return {"rate_req_per_s": rate, "requests": count, "seconds": round(span, 3),
+            "latency_ms": {"p50": round(float(np.percentile(body, 50)), 3),
+                           "p99": round(float(np.percentile(body, 99)), 3),
+                           "mean": round(float(body.mean()), 3)},
+            "tflops": round(flops / span / 1e12, 2), "failed": bad,
+            "mean_group_size": round(float(groups.mean()), 2),
+            "mix": "70% split-BF16 / 30% two-term FP8, HBM budget 200 GB, 4 slots, groups <= 16",
+            "first_5pct_discarded": skip}
 
 
 def main():
@@ -225,9 +360,21 @@ def main():
     torch.cuda.synchronize()
     per, total_ms = timed_loop(step, args.steps, torch)
     ms = total_ms / args.steps
+    # the same loop again with the library's event tracing on: per-kernel
+    # times of the contraction and of the operand conditioning
+    moa.moa_trace_read(reset=True)
+    moa.moa_trace_enable(True)
+    timed_loop(step, args.steps, torch)
+    moa.moa_trace_enable(False)
+    traced = moa.moa_trace_read(reset=True)
+    n_k, ms_k = traced.get("split_bf16", (0, 0.0))
+    kernel_ms = ms_k / n_k if n_k else ms
+    n_p, ms_p = traced.get("split_pack", (0, 0.0))
+    pack_ms = ms_p / n_p if n_p else None
     flops = 2.0 * N ** 3
     tflops = flops / (ms * 1e-3) / 1e12
     issued = 3 * flops / (ms * 1e-3) / 1e12
+    issued_kernel = 3 * flops / (kernel_ms * 1e-3) / 1e12
 
     onf()
     per_onf, total_onf = timed_loop(onf, args.onf_steps, torch)
@@ -239,11 +386,16 @@ def main():
     e_onf = energy_per_call(onf, args.energy_seconds, ms_onf, energy, torch)
 
     if args.copy_calibration:
-        src = torch.empty(256 * 2 ** 20 // 4, dtype=torch.float32, device=dev).fill_(1.0)
+        # one device-to-device copy of exactly COPY_CAL_BYTES, identifiable by size
+        src = torch.empty(COPY_CAL_BYTES // 4, dtype=torch.float32, device=dev).fill_(1.0)
         dst = torch.empty_like(src)
         torch.cuda.synchronize()
         dst.copy_(src)
         torch.cuda.synchronize()
+
+    grouped = None if args.no_grouped else grouped_section(torch, moa, inputs)
+    serving = None if args.no_serving else serving_section(torch, moa, inputs, args.serve_rate,
+                                                             args.serve_seconds)
 
     C_h = C.cpu().numpy()
     onf_h = C_onf.cpu().numpy()
@@ -275,14 +427,16 @@ def main():
         "pct_of_bf16_peak_issued": round(100 * issued / BF16_PEAK_TF, 2),
         "latency_ms": {"p50": round(pct(per, 50), 4), "p99": round(pct(per, 99), 4),
                        "min": round(min(per), 4), "max": round(max(per), 4)},
-        "roofline": {"bound": "mfma", "achieved": round(issued, 2), "peak": BF16_PEAK_TF,
-                     "unit": "TFLOP/s", "frac": round(issued / BF16_PEAK_TF, 4),
+        "roofline": {"bound": "mfma", "achieved": round(issued_kernel, 2), "peak": BF16_PEAK_TF,
+                     "unit": "TFLOP/s", "frac": round(issued_kernel / BF16_PEAK_TF, 4),
                      "traffic": measured_traffic("paper_2306_11148_amd/csrc/split_bf16.hip",
                                                  "profiles/split_bf16_N8192_traffic.json")
                      if N == 8192 else None,
                      "kernel": "split_bf16_kernel",
                      "work_per_launch": "3 * 2 N^3 BF16 matrix-core flop (hi.hi + hi.lo + lo.hi)",
-                     "avg_kernel_ms": round(ms, 4)},
+                     "avg_kernel_ms": round(kernel_ms, 4),
+                     "kernel_timing": "HIP events on the launch stream (library tracing)",
+                     "conditioning_kernels_ms": None if pack_ms is None else round(pack_ms, 4)},
         "onf": {"tflops": round(tflops_onf, 2), "ms": round(ms_onf, 3),
                 "pct_of_fp32_vector_peak": round(100 * tflops_onf / FP32_VEC_PEAK_TF, 2),
                 "pct_of_unpacked_fma_peak": round(100 * tflops_onf / FP32_FMA_UNPACKED_TF, 2),
@@ -293,6 +447,8 @@ def main():
         "energy": {"split_bf16": e_split, "onf": e_onf,
                    "note": None if (energy and energy.h is not None) else
                    (energy.err if energy else "disabled")},
+        "grouped": grouped,
+        "serving": serving,
         "cpu_baseline": cpu,
     }
     if e_split and e_onf:

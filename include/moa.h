@@ -179,6 +179,42 @@ moa_status moa_error_norm(int64_t count, int32_t x_dtype, const void *X,
                           const double *R, double *out, void *stream);
 
 /* ------------------------------------------------------------------------
+ * Kernel timing (profiling aid). While enabled, every kernel the library
+ * launches is bracketed by two HIP events recorded on the launch's own
+ * stream; moa_trace_read folds the finished pairs into per-kernel totals.
+ * ---------------------------------------------------------------------- */
+typedef enum moa_kernel {
+    MOA_K_ONF_F64 = 1,        /* plain ONF contraction, FP64 */
+    MOA_K_ONF_F32 = 2,        /* plain ONF contraction, FP32 */
+    MOA_K_MFMA_F32 = 3,       /* FP32 matrix-core contraction */
+    MOA_K_SPLIT_BF16 = 4,     /* split-BF16 contraction (single product) */
+    MOA_K_FP8 = 5,            /* scaled-FP8 contraction, one term */
+    MOA_K_FP8_2TERM = 6,      /* scaled-FP8 contraction, two terms */
+    MOA_K_SPLIT_PACK = 7,     /* split-BF16 operand conditioning */
+    MOA_K_FP8_QUANT = 8,      /* FP8 operand conditioning */
+    MOA_K_SPLIT_GROUPED = 9,  /* grouped persistent split-BF16 contraction */
+    MOA_K_COUNT = 10
+} moa_kernel;
+
+typedef struct moa_trace_stat {
+    int32_t kernel;           /* moa_kernel */
+    int32_t reserved;
+    int64_t launches;         /* completed launches folded in */
+    double total_ms;          /* sum of their event-measured durations */
+} moa_trace_stat;
+
+/* Turns tracing on (non-zero) or off. Off by default. Thread-safe. */
+moa_status moa_trace_enable(int32_t on);
+
+/* Folds every finished event pair into the totals and writes one entry per
+ * kernel kind with launches > 0 (at most `capacity`) to `out`, the number
+ * written to `*count`. Pairs whose work has not finished are kept for the
+ * next call (synchronize the streams first for complete totals). With
+ * reset != 0 the totals are cleared after reading. Host memory only. */
+moa_status moa_trace_read(moa_trace_stat *out, int32_t capacity, int32_t *count,
+                          int32_t reset);
+
+/* ------------------------------------------------------------------------
  * Serving: a request loop that admits products of mixed shapes under an HBM
  * budget and batches them into grouped launches on several streams
  * (continuous batching: requests that arrive while others run are admitted

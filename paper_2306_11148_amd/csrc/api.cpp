@@ -113,8 +113,16 @@ moa_status run_gemm(const moa_gemm_desc &d, hipStream_t stream) {
     if (s != MOA_OK) return s;
     hipError_t e = hipSuccess;
     switch (pl.path) {
-    case MOA_PATH_ONF: e = launch_onf(d, pl, stream); break;
-    case MOA_PATH_MFMA_F32: e = launch_mfma_f32(d, pl, stream); break;
+    case MOA_PATH_ONF: {
+        TraceScope ts(pl.kernel, stream);
+        e = launch_onf(d, pl, stream);
+        break;
+    }
+    case MOA_PATH_MFMA_F32: {
+        TraceScope ts(pl.kernel, stream);
+        e = launch_mfma_f32(d, pl, stream);
+        break;
+    }
     case MOA_PATH_SPLIT_BF16:
     case MOA_PATH_FP8_SCALED: {
         void *ws = nullptr;

@@ -397,10 +397,14 @@ int64_t fp8_workspace_bytes(int64_t m, int64_t n, int64_t p, bool two) {
 hipError_t launch_fp8(const moa_gemm_desc &d, const Plan &plan, void *ws, hipStream_t st) {
     const bool two = (d.flags & MOA_FLAG_FP8_TWO_TERM) != 0;
     const Fp8Workspace w = carve(ws, d.m, d.n, d.p, two);
-    hipError_t err = conditioning(static_cast<const float *>(d.A), d.m, d.n,
-                                  static_cast<const float *>(d.B), d.p, two, w.amaxA, w.amaxB, w.e,
-                                  w.qA, w.lA, w.f, w.qBt, w.lBt, true, st);
+    hipError_t err;
+    {
+        TraceScope ts(MOA_K_FP8_QUANT, st);
+        err = conditioning(static_cast<const float *>(d.A), d.m, d.n, static_cast<const float *>(d.B),
+                           d.p, two, w.amaxA, w.amaxB, w.e, w.qA, w.lA, w.f, w.qBt, w.lBt, true, st);
+    }
     if (err != hipSuccess) return err;
+    TraceScope ts(two ? MOA_K_FP8_2TERM : MOA_K_FP8, st);
     const int tiles_m = (int)((d.m + BM - 1) / BM), tiles_n = (int)((d.p + BN - 1) / BN);
     const int vec = (d.n % 16 == 0);
     float *C = static_cast<float *>(d.C);

@@ -59,6 +59,22 @@ constexpr int kNumXCDs = 8;
 
 int64_t static_block_components(int64_t budget, int64_t elem, int64_t nblocks);
 
+// ----------------------------------------------------------------- trace --
+// Brackets the launches made in its lifetime with events on `stream` while
+// tracing is enabled (moa_trace_enable); a no-op otherwise.
+class TraceScope {
+  public:
+    TraceScope(int32_t kernel, hipStream_t stream);
+    ~TraceScope();
+    TraceScope(const TraceScope &) = delete;
+    TraceScope &operator=(const TraceScope &) = delete;
+
+  private:
+    int32_t kernel_;
+    hipStream_t stream_;
+    hipEvent_t start_ = nullptr;
+};
+
 // --------------------------------------------------------------- kernels --
 // Each launcher enqueues the whole product for `d` on `stream` using `plan`
 // and returns the first HIP error.

@@ -11,8 +11,12 @@
 //    A and every column j of B, slab s becomes one contiguous 64-byte record
 //        [hi of x[16s .. 16s+15] (16 bf16)][lo of the same (16 bf16)]
 //    zero-padded past n. B is transposed on the way (column j of B becomes
-//    record row j), so both operands are k-contiguous, and the records of one
-//    row follow each other (record (r, s) at (r * S + s) * 64 bytes).
+//    record row j), so both operands are k-contiguous. Records are stored in
+//    tiles of 16 rows x 1 slab: record (r, s) lives at byte
+//        ((r / 16) * S + s) * 1024 + (r mod 16) * 64,
+//    so the 16 records a wave moves into LDS in one load are one contiguous
+//    KiB of whole cache lines. Row counts are padded to a multiple of 16 with
+//    zero records.
 //
 // 2. Contraction (matrix-core bound), the blocked form of Fig. 2: each
 //    workgroup owns a BM x BN block of C and walks the S slabs; per slab the
@@ -41,6 +45,13 @@ namespace {
 constexpr int SLAB = 16;                  // k per record
 constexpr int REC = 2 * SLAB;             // bf16 per record (hi + lo)
 constexpr int REC_BYTES = REC * 2;        // 64
+constexpr int GROUP = 16;                 // rows per record tile (1 KiB per slab)
+
+// bf16 offset of record (r, s) in a record array with S slabs per row
+__device__ __forceinline__ int64_t rec_off(int64_t r, int64_t s, int64_t S) {
+    return ((r / GROUP) * S + s) * (GROUP * REC) + (r % GROUP) * REC;
+}
+__host__ __device__ inline int64_t padded_rows(int64_t rows) { return (rows + GROUP - 1) / GROUP * GROUP; }
 constexpr int NSTAGE = 4;                 // LDS ring depth
 
 typedef __attribute__((address_space(3))) void lds_void_t;
@@ -60,15 +71,22 @@ __device__ __forceinline__ void ring_barrier() { asm volatile("s_barrier" ::: "m
 
 // Rows of X (rows x K, row-major) -> records: chunk q = 8 k values of one
 // record (2 chunks per record).
-__device__ __forceinline__ void pack_rows_chunk(const float *__restrict__ X, int64_t K, int64_t S,
-                                                int vec, uint16_t *__restrict__ P, int64_t q) {
-    const int64_t r = q / (S * 2);
-    const int64_t rem = q - r * S * 2;
-    const int64_t s = rem >> 1;
-    const int c = (int)(rem & 1);
+__device__ __forceinline__ void pack_rows_chunk(const float *__restrict__ X, int64_t rows, int64_t K,
+                                                int64_t S, int vec, uint16_t *__restrict__ P,
+                                                int64_t q) {
+    // q -> (row tile g, slab s, row rr in the tile, chunk c): consecutive
+    // threads fill one KiB tile contiguously
+    const int c = (int)(q & 1);
+    const int64_t rr = (q >> 1) % GROUP;
+    const int64_t gs = (q >> 1) / GROUP;
+    const int64_t s = gs % S, g = gs / S;
+    const int64_t r = g * GROUP + rr;
     const int64_t k = s * SLAB + c * 8;
     float x[8];
-    if (vec && k + 8 <= K) {
+    if (r >= rows) {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) x[e] = 0.0f;
+    } else if (vec && k + 8 <= K) {
         const float4 *src = reinterpret_cast<const float4 *>(X + r * K + k);
         const float4 a = src[0], b = src[1];
         x[0] = a.x; x[1] = a.y; x[2] = a.z; x[3] = a.w;
@@ -82,7 +100,7 @@ __device__ __forceinline__ void pack_rows_chunk(const float *__restrict__ X, int
     split_pair(x[2], x[3], &hi.y, &lo.y);
     split_pair(x[4], x[5], &hi.z, &lo.z);
     split_pair(x[6], x[7], &hi.w, &lo.w);
-    uint16_t *rec = P + (r * S + s) * REC;
+    uint16_t *rec = P + rec_off(r, s, S);
     *reinterpret_cast<uint4 *>(rec + c * 8) = hi;
     *reinterpret_cast<uint4 *>(rec + SLAB + c * 8) = lo;
 }
@@ -90,36 +108,49 @@ __device__ __forceinline__ void pack_rows_chunk(const float *__restrict__ X, int
 __global__ __launch_bounds__(256) void pack_rows_kernel(const float *__restrict__ X, int64_t rows,
                                                         int64_t K, int64_t S, int vec,
                                                         uint16_t *__restrict__ P) {
-    const int64_t chunks = rows * S * 2;
+    const int64_t chunks = padded_rows(rows) * S * 2;
     for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < chunks; q += (int64_t)gridDim.x * 256)
-        pack_rows_chunk(X, K, S, vec, P, q);
+        pack_rows_chunk(X, rows, K, S, vec, P, q);
 }
 
 // Columns of X (K x cols, row-major) -> records (transposed). Block (bx, by)
 // covers columns 64 bx .. 64 bx + 63 and slabs 4 by .. 4 by + 3; it goes
 // through LDS so that reads of X rows are contiguous and each thread writes
-// one whole 64-byte record (four neighbouring threads: four consecutive
-// records of one column). All 256 threads must call it together.
+// one whole 64-byte record (a wave: 64 columns of one slab = four whole
+// record tiles). Columns past `cols` get zero records. All 256 threads must
+// call it together.
 __device__ __forceinline__ void pack_cols_block(const float *__restrict__ X, int64_t K, int64_t cols,
                                                 int64_t S, uint16_t *__restrict__ P, int64_t bx,
-                                                int64_t by, float (*tile)[64 + 1]) {
+                                                int64_t by, float (*tile)[64 + 4], int vec) {
     const int64_t j0 = bx * 64;
     const int64_t s0 = by * 4;
     const int t = threadIdx.x;
     {
-        const int jj = t & 63;
-        const int64_t j = j0 + jj;
+        // thread -> (k row kk = t/16 + 16 i, four columns 4 (t%16) .. +3)
+        const int jq = (t & 15) * 4;
+        const int64_t j = j0 + jq;
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            const int kk = (t >> 6) + 4 * q;
+        for (int i = 0; i < 4; ++i) {
+            const int kk = (t >> 4) + 16 * i;
             const int64_t k = s0 * SLAB + kk;
-            tile[kk][jj] = (k < K && j < cols) ? X[k * cols + j] : 0.0f;
+            float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+            if (k < K) {
+                if (vec && j + 4 <= cols) {
+                    v = *reinterpret_cast<const float4 *>(X + k * cols + j);
+                } else {
+                    float *e = reinterpret_cast<float *>(&v);
+#pragma unroll
+                    for (int q = 0; q < 4; ++q)
+                        if (j + q < cols) e[q] = X[k * cols + j + q];
+                }
+            }
+            *reinterpret_cast<float4 *>(&tile[kk][jq]) = v;
         }
     }
     __syncthreads();
-    const int jj = t >> 2, part = t & 3;
+    const int jj = t & 63, part = t >> 6;
     const int64_t j = j0 + jj, s = s0 + part;
-    if (j >= cols || s >= S) return;
+    if (j >= padded_rows(cols) || s >= S) return;
     uint4 h[2], l[2];
 #pragma unroll
     for (int c = 0; c < 2; ++c) {
@@ -129,7 +160,7 @@ __device__ __forceinline__ void pack_cols_block(const float *__restrict__ X, int
         split_pair(tile[kb + 4][jj], tile[kb + 5][jj], &h[c].z, &l[c].z);
         split_pair(tile[kb + 6][jj], tile[kb + 7][jj], &h[c].w, &l[c].w);
     }
-    uint4 *rec = reinterpret_cast<uint4 *>(P + (j * S + s) * REC);
+    uint4 *rec = reinterpret_cast<uint4 *>(P + rec_off(j, s, S));
     rec[0] = h[0];
     rec[1] = h[1];
     rec[2] = l[0];
@@ -137,10 +168,14 @@ __device__ __forceinline__ void pack_cols_block(const float *__restrict__ X, int
 }
 
 __global__ __launch_bounds__(256) void pack_cols_kernel(const float *__restrict__ X, int64_t K,
-                                                        int64_t cols, int64_t S,
+                                                        int64_t cols, int64_t S, int vec,
                                                         uint16_t *__restrict__ P) {
-    __shared__ float tile[4 * SLAB][64 + 1];
-    pack_cols_block(X, K, cols, S, P, blockIdx.x, blockIdx.y, tile);
+    __shared__ __attribute__((aligned(16))) float tile[4 * SLAB][64 + 4];
+    const int64_t by_count = (S + 3) / 4;
+    for (int64_t by = blockIdx.y; by < by_count; by += gridDim.y) {
+        pack_cols_block(X, K, cols, S, P, blockIdx.x, by, tile, vec);
+        __syncthreads();
+    }
 }
 
 // ---------------------------------------------------------------- stage 2 --
@@ -179,15 +214,16 @@ __device__ __forceinline__ void split_tile(const uint16_t *__restrict__ Ap,
     // block and the slab go in the uniform soffset. Records past m (or p) lie
     // beyond the resource's range and load as zeros (their outputs are not
     // stored).
-    const int64_t rec_row = S * REC_BYTES;            // bytes per record row
-    const int64_t rows_a = min((int64_t)BM, m - i0), rows_b = min((int64_t)BN, p - j0);
+    const int64_t tile_row = S * GROUP * REC_BYTES;   // bytes per row tile (16 rows, all slabs)
+    const int64_t tiles_a = min((int64_t)BM, padded_rows(m) - i0) / GROUP;
+    const int64_t tiles_b = min((int64_t)BN, padded_rows(p) - j0) / GROUP;
     const __amdgpu_buffer_rsrc_t rsrc_a = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(reinterpret_cast<const uint8_t *>(Ap) + i0 * rec_row), (short)0,
-        (int)(rows_a * rec_row), 0x00020000);
+        (void *)(reinterpret_cast<const uint8_t *>(Ap) + (i0 / GROUP) * tile_row), (short)0,
+        (int)(tiles_a * tile_row), 0x00020000);
     const __amdgpu_buffer_rsrc_t rsrc_b = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(reinterpret_cast<const uint8_t *>(Bp) + j0 * rec_row), (short)0,
-        (int)(rows_b * rec_row), 0x00020000);
-    const int voff = (int)((lane >> 2) * rec_row) + (((lane & 3) ^ (lane >> 4)) << 4);
+        (void *)(reinterpret_cast<const uint8_t *>(Bp) + (j0 / GROUP) * tile_row), (short)0,
+        (int)(tiles_b * tile_row), 0x00020000);
+    const int voff = (lane >> 2) * REC_BYTES + (((lane & 3) ^ (lane >> 4)) << 4);
     // Each wave's LPW loads cover 16*LPW consecutive rows that are either
     // all rows of A or all rows of B, so every load names one resource.
     static_assert(BM % (16 * LPW) == 0, "a wave loads A rows or B rows, not both");
@@ -200,13 +236,13 @@ __device__ __forceinline__ void split_tile(const uint16_t *__restrict__ Ap,
             for (int q = 0; q < LPW; ++q)
                 __builtin_amdgcn_raw_ptr_buffer_load_lds(
                     rsrc_a, (lds_void_t *)(buf + q * 16 * REC_BYTES), 16, voff,
-                    (int)((row_base + q * 16) * rec_row + s * REC_BYTES), 0, 0);
+                    (int)((row_base / GROUP + q) * tile_row + s * GROUP * REC_BYTES), 0, 0);
         } else {
 #pragma unroll
             for (int q = 0; q < LPW; ++q)
                 __builtin_amdgcn_raw_ptr_buffer_load_lds(
                     rsrc_b, (lds_void_t *)(buf + q * 16 * REC_BYTES), 16, voff,
-                    (int)((row_base + q * 16) * rec_row + s * REC_BYTES), 0, 0);
+                    (int)((row_base / GROUP + q) * tile_row + s * GROUP * REC_BYTES), 0, 0);
         }
     };
 
@@ -379,21 +415,22 @@ __global__ __launch_bounds__(256) void grouped_pack_rows_kernel(const GroupMembe
     for (int k = blockIdx.y; k < count; k += gridDim.y) {
         const GroupMember d = g[k];
         const int vec = (d.n % 8 == 0) && ((uintptr_t)d.A % 16 == 0);
-        const int64_t chunks = d.m * d.S * 2;
+        const int64_t chunks = padded_rows(d.m) * d.S * 2;
         for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < chunks; q += (int64_t)gridDim.x * 256)
-            pack_rows_chunk(d.A, d.n, d.S, vec, d.Ap, q);
+            pack_rows_chunk(d.A, d.m, d.n, d.S, vec, d.Ap, q);
     }
 }
 
 __global__ __launch_bounds__(256) void grouped_pack_cols_kernel(const GroupMember *__restrict__ g,
                                                                 int count) {
-    __shared__ float tile[4 * SLAB][64 + 1];
+    __shared__ __attribute__((aligned(16))) float tile[4 * SLAB][64 + 4];
     for (int k = blockIdx.y; k < count; k += gridDim.y) {
         const GroupMember d = g[k];
+        const int vec = (d.p % 4 == 0) && ((uintptr_t)d.B % 16 == 0);
         const int64_t bx = (d.p + 63) / 64, by = (d.S + 3) / 4;
         for (int64_t b = blockIdx.x; b < bx * by; b += gridDim.x) {
             __syncthreads();
-            pack_cols_block(d.B, d.n, d.p, d.S, d.Bp, b % bx, b / bx, tile);
+            pack_cols_block(d.B, d.n, d.p, d.S, d.Bp, b % bx, b / bx, tile, vec);
         }
     }
 }
@@ -438,7 +475,7 @@ int split_bf16_variant_count() { return (int)(sizeof(kSplit) / sizeof(kSplit[0])
 
 int64_t split_bf16_workspace_bytes(int64_t m, int64_t n, int64_t p) {
     const int64_t S = (n + SLAB - 1) / SLAB;
-    return (m + p) * S * REC_BYTES;
+    return (padded_rows(m) + padded_rows(p)) * S * REC_BYTES;
 }
 
 void split_bf16_shape(int v, Plan *p) {
@@ -457,26 +494,33 @@ void split_bf16_shape(int v, Plan *p) {
 hipError_t launch_split_pack(const moa_gemm_desc &d, void *ws, hipStream_t st) {
     const int64_t S = (d.n + SLAB - 1) / SLAB;
     uint16_t *Ap = static_cast<uint16_t *>(ws);
-    uint16_t *Bp = Ap + d.m * S * REC;
+    uint16_t *Bp = Ap + padded_rows(d.m) * S * REC;
     const float *A = static_cast<const float *>(d.A);
     const float *B = static_cast<const float *>(d.B);
     if (S == 0) return hipSuccess;
     const int vec = (d.n % 8 == 0) && ((uintptr_t)A % 16 == 0);
-    const int64_t chunks = d.m * S * 2;
+    const int64_t chunks = padded_rows(d.m) * S * 2;
     int64_t blocks = (chunks + 255) / 256;
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(pack_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, d.m, d.n, S, vec, Ap);
-    hipLaunchKernelGGL(pack_cols_kernel, dim3((unsigned)((d.p + 63) / 64), (unsigned)((S + 3) / 4)), dim3(256),
-                       0, st, B, d.n, d.p, S, Bp);
+    const int vec_b = (d.p % 4 == 0) && ((uintptr_t)B % 16 == 0);
+    const int64_t by = (S + 3) / 4;
+    hipLaunchKernelGGL(pack_cols_kernel, dim3((unsigned)((d.p + 63) / 64), (unsigned)(by < 65535 ? by : 65535)),
+                       dim3(256), 0, st, B, d.n, d.p, S, vec_b, Bp);
     return hipGetLastError();
 }
 
 hipError_t launch_split_bf16(const moa_gemm_desc &d, const Plan &plan, void *ws, hipStream_t st) {
-    hipError_t e = launch_split_pack(d, ws, st);
+    hipError_t e;
+    {
+        TraceScope ts(MOA_K_SPLIT_PACK, st);
+        e = launch_split_pack(d, ws, st);
+    }
     if (e != hipSuccess) return e;
+    TraceScope ts(MOA_K_SPLIT_BF16, st);
     const int64_t S = (d.n + SLAB - 1) / SLAB;
     const uint16_t *Ap = static_cast<const uint16_t *>(ws);
-    const uint16_t *Bp = Ap + d.m * S * REC;
+    const uint16_t *Bp = Ap + padded_rows(d.m) * S * REC;
     switch (plan.variant) {
     case 0: return launch_shape<128, 128, 64, 64>(d, Ap, Bp, S, st);
     default: return launch_shape<256, 256, 128, 64>(d, Ap, Bp, S, st);
@@ -522,7 +566,7 @@ hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, 
         g.m = d.m; g.n = d.n; g.p = d.p;
         g.S = (d.n + SLAB - 1) / SLAB;
         g.Ap = reinterpret_cast<uint16_t *>(rec);
-        g.Bp = g.Ap + d.m * g.S * REC;
+        g.Bp = g.Ap + padded_rows(d.m) * g.S * REC;
         rec += align256(split_bf16_workspace_bytes(d.m, d.n, d.p));
         g.first_tile = tiles;
         g.tiles_n = (int32_t)((d.p + GB_N - 1) / GB_N);
@@ -535,9 +579,13 @@ hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, 
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, st, counter);
     const unsigned gy = (unsigned)std::min(count, 65535);
-    hipLaunchKernelGGL(grouped_pack_rows_kernel, dim3(32, gy), dim3(256), 0, st, dev_members, count);
-    hipLaunchKernelGGL(grouped_pack_cols_kernel, dim3(16, gy), dim3(256), 0, st, dev_members, count);
+    {
+        TraceScope ts(MOA_K_SPLIT_PACK, st);
+        hipLaunchKernelGGL(grouped_pack_rows_kernel, dim3(32, gy), dim3(256), 0, st, dev_members, count);
+        hipLaunchKernelGGL(grouped_pack_cols_kernel, dim3(16, gy), dim3(256), 0, st, dev_members, count);
+    }
     const int64_t grid = std::min<int64_t>(tiles, 2 * kNumCUs);   // two 64 KiB-LDS blocks per CU
+    TraceScope ts(MOA_K_SPLIT_GROUPED, st);
     if (grid > 0)
         hipLaunchKernelGGL((split_grouped_kernel<GB_M, GB_N, GW_M, GW_N>), dim3((unsigned)grid),
                            dim3(TileCfg<GB_M, GB_N, GW_M, GW_N>::THREADS), 0, st, dev_members, count,

@@ -67,8 +67,16 @@ EXPORTS = [
     "moa_gemm", "moa_gemm_grouped", "moa_plan_query", "moa_static_block_components",
     "moa_split_bf16", "moa_quantise_fp8", "moa_error_norm", "moa_serve_create",
     "moa_serve_submit", "moa_serve_poll", "moa_serve_drain", "moa_serve_destroy",
-    "moa_status_string", "moa_last_error",
+    "moa_status_string", "moa_last_error", "moa_trace_enable", "moa_trace_read",
 ]
+
+MOA_KERNELS = {1: "onf_f64", 2: "onf_f32", 3: "mfma_f32", 4: "split_bf16", 5: "fp8", 6: "fp8_2term",
+               7: "split_pack", 8: "fp8_quant", 9: "split_grouped"}
+
+
+class moa_trace_stat(ctypes.Structure):
+    _fields_ = [("kernel", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("launches", ctypes.c_int64), ("total_ms", ctypes.c_double)]
 
 _lib = None
 
@@ -99,6 +107,8 @@ def lib():
         "moa_serve_destroy": ([vp], i32),
         "moa_status_string": ([i32], ctypes.c_char_p),
         "moa_last_error": ([], ctypes.c_char_p),
+        "moa_trace_enable": ([i32], i32),
+        "moa_trace_read": ([P(moa_trace_stat), i32, P(i32), i32], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -236,3 +246,18 @@ def moa_serve_drain(srv):
 
 def moa_serve_destroy(srv):
     _check(lib().moa_serve_destroy(srv), "moa_serve_destroy")
+
+
+# ------------------------------------------------------------------ tracing --
+
+def moa_trace_enable(on: bool = True):
+    _check(lib().moa_trace_enable(int(bool(on))), "moa_trace_enable")
+
+
+def moa_trace_read(reset: bool = False) -> dict:
+    """{kernel name: (launches, total_ms)} for finished traced launches."""
+    buf = (moa_trace_stat * 16)()
+    n = ctypes.c_int32()
+    _check(lib().moa_trace_read(buf, 16, ctypes.byref(n), int(bool(reset))), "moa_trace_read")
+    return {MOA_KERNELS.get(buf[k].kernel, str(buf[k].kernel)): (buf[k].launches, buf[k].total_ms)
+            for k in range(n.value)}
