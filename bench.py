@@ -48,6 +48,9 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-grouped", action="store_true")
+    ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--sweep", type=str, default=None,
+                    help="comma-separated N list: time/energy sweep only (one JSON line per point)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run one plain device copy of known size (for counter scaling)")
     return ap.parse_args()
@@ -172,8 +175,10 @@ def energy_per_call(fn, seconds, ms_each, energy, torch):
             "clock_samples": len(samples)}
 
 
-def cpu_baseline(A, B, C_gpu, n, target_s):
-    """The FP64 oracle on a seeded row sample of the same product."""
+def cpu_baseline(A, B, C_gpu, n, target_s, onf_rows=None, precision=None):
+    """The CPU leg: the FP64 oracle timed on a seeded, growing row sample of
+    the same product (about target_s of oracle time), plus every error figure
+    of the run (the oracle is used nowhere else in this script)."""
     import numpy as np
     from oracle import oracle as O
     threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
@@ -199,11 +204,18 @@ def cpu_baseline(A, B, C_gpu, n, target_s):
     all_rows = np.concatenate(done_rows)
     Rall = np.concatenate(refs)
     flops = 2.0 * len(all_rows) * A.shape[1] * B.shape[1]
-    err = O.rel_err(C_gpu[all_rows], Rall)
+    errs = {"split_bf16": O.rel_err(C_gpu[all_rows], Rall)}
+    if onf_rows is not None:
+        r_idx, got = onf_rows
+        errs["onf_f32"] = O.rel_err(got, O.gemm_rows_f64(A, B, r_idx))
+    if precision is not None:
+        pA, pB, p_rows, kept = precision
+        Rp = O.gemm_rows_f64(pA.astype(np.float64), pB.astype(np.float64), p_rows)
+        errs["precision"] = {k: O.rel_err(v, Rp) for k, v in kept.items()}
     return {"value": flops / done_t / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(all_rows)} seeded rows of the {n}^3 FP32 product (inputs widened to "
                       f"FP64), {done_t:.1f} s of oracle time",
-            "seconds": done_t}, err
+            "seconds": done_t}, errs
 
 
 def grouped_section(torch, moa, inputs, reps=10):
@@ -317,6 +329,72 @@ def serving_section(torch, moa, inputs, rate, seconds, seed=5):
             "first_5pct_discarded": skip}
 
 
+def precision_section(torch, moa, inputs, reps=5):
+    """m=8192, n=4096, p=8192, FP32 inputs N(0,1)*10^U(-3,3) per row of A and
+    column of B (seed 3): every path timed; 48 seeded rows of each result are
+    kept for the CPU leg, which measures their error against the oracle."""
+    import ctypes
+    import numpy as np
+    m, n, p = 8192, 4096, 8192
+    A_h, B_h = inputs.row_col_scaled_f32(m, n, p, seed=3)
+    A = torch.from_numpy(A_h).cuda()
+    B = torch.from_numpy(B_h).cuda()
+    C = torch.empty((m, p), device="cuda")
+    rows = np.sort(np.random.default_rng(33).choice(m, 48, replace=False))
+    out = {"workload": "m=8192 n=4096 p=8192, N(0,1)*10^U(-3,3) per row of A / column of B, seed 3",
+           "error": "normwise vs the FP64 oracle on 48 seeded rows (computed in the CPU leg)"}
+    kept = {}
+    paths = [("onf_f32", moa.MOA_PATH_ONF, 0), ("mfma_f32", moa.MOA_PATH_MFMA_F32, 0),
+             ("split_bf16", moa.MOA_PATH_SPLIT_BF16, 0), ("fp8_1term", moa.MOA_PATH_FP8_SCALED, 0),
+             ("fp8_2term", moa.MOA_PATH_FP8_SCALED, moa.MOA_FLAG_FP8_TWO_TERM)]
+    L, st = moa.lib(), torch.cuda.current_stream().cuda_stream
+    for name, path, flags in paths:
+        d = moa.make_desc(A, B, C, path=path, flags=flags)
+
+        def f():
+            if L.moa_gemm(ctypes.byref(d), st) != 0:
+                raise RuntimeError(moa.moa_last_error())
+        f()
+        torch.cuda.synchronize()
+        kept[name] = C.cpu().numpy()[rows]
+        _, tot = timed_loop(f, reps, torch)
+        ms = tot / reps
+        out[name] = {"ms": round(ms, 4), "tflops": round(2.0 * m * n * p / ms / 1e9, 2),
+                     "normwise_err": None}
+    return out, (A_h, B_h, rows, kept)
+
+
+def sweep(args, torch, moa, inputs):
+    """Time and joules per product against N for the square FP32 workload, per
+    path (the paper's time/energy-versus-N axes), one JSON line per point."""
+    energy = Energy()
+    for N in [int(x) for x in args.sweep.split(",")]:
+        gen = torch.Generator(device="cuda").manual_seed(N)
+        A = torch.randn((N, N), generator=gen, device="cuda")
+        B = torch.randn((N, N), generator=gen, device="cuda")
+        C = torch.empty((N, N), device="cuda")
+        for name, path, flags in (("onf_f32", moa.MOA_PATH_ONF, 0),
+                                  ("mfma_f32", moa.MOA_PATH_MFMA_F32, 0),
+                                  ("split_bf16", moa.MOA_PATH_SPLIT_BF16, 0)):
+            d = moa.make_desc(A, B, C, path=path, flags=flags)
+            L, st = moa.lib(), torch.cuda.current_stream().cuda_stream
+            import ctypes
+
+            def f():
+                if L.moa_gemm(ctypes.byref(d), st) != 0:
+                    raise RuntimeError(moa.moa_last_error())
+            f()
+            reps = max(3, min(200, int(200.0 / (2.0 * N ** 3 / 1e11))))
+            per, tot = timed_loop(f, reps, torch)
+            ms = tot / reps
+            e = energy_per_call(f, args.energy_seconds, ms, energy, torch)
+            print(json.dumps({"sweep": "square FP32", "N": N, "path": name, "ms": round(ms, 4),
+                              "tflops": round(2.0 * N ** 3 / ms / 1e9, 2),
+                              "p50_ms": round(pct(per, 50), 4), "p99_ms": round(pct(per, 99), 4),
+                              "energy": e}), flush=True)
+        del A, B, C
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -330,6 +408,9 @@ def main():
     moa.lib()  # fail loudly if the HIP library is missing
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.sweep:
+        sweep(args, torch, moa, inputs)
+        return
     N = args.n
     A_h, B_h = inputs.normal_f32(N, N, N, seed=N)
     A = torch.from_numpy(A_h).to(dev)
@@ -394,6 +475,7 @@ def main():
         torch.cuda.synchronize()
 
     grouped = None if args.no_grouped else grouped_section(torch, moa, inputs)
+    precision, precision_keep = (None, None) if args.no_precision else precision_section(torch, moa, inputs)
     serving = None if args.no_serving else serving_section(torch, moa, inputs, args.serve_rate,
                                                              args.serve_seconds)
 
@@ -402,11 +484,13 @@ def main():
     cpu = None
     err_split = err_onf = None
     if not args.no_cpu_baseline:
-        cpu, err_split = cpu_baseline(A_h, B_h, C_h, N, args.cpu_seconds)
-        from oracle import oracle as O
-        rows = np.arange(0, N, max(1, N // 64))
-        Rs = O.gemm_rows_f64(A_h, B_h, rows)
-        err_onf = O.rel_err(onf_h[rows], Rs)
+        onf_rows = np.arange(0, N, max(1, N // 64))
+        cpu, errs = cpu_baseline(A_h, B_h, C_h, N, args.cpu_seconds, (onf_rows, onf_h[onf_rows]),
+                                 precision_keep)
+        err_split, err_onf = errs["split_bf16"], errs.get("onf_f32")
+        if precision is not None and "precision" in errs:
+            for k, e in errs["precision"].items():
+                precision[k]["normwise_err"] = e
 
     result = {
         "metric": "TFLOP/s + % peak at N=8192 (ONF vs split-BF16 MFMA); p50/p99 GEMM latency",
@@ -449,6 +533,7 @@ def main():
                    (energy.err if energy else "disabled")},
         "grouped": grouped,
         "serving": serving,
+        "precision": precision,
         "cpu_baseline": cpu,
     }
     if e_split and e_onf:

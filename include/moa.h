@@ -140,6 +140,22 @@ moa_status moa_gemm(const moa_gemm_desc *desc, void *stream);
 moa_status moa_gemm_grouped(const moa_gemm_desc *descs, int64_t count,
                             void *stream);
 
+/* Prepared groups: a fixed set of products launched many times. Creation
+ * validates the members as moa_gemm_grouped does, allocates a workspace owned
+ * by the group, uploads the member list once and captures the whole grouped
+ * launch sequence (conditioning + one persistent contraction for split-BF16
+ * members, single launches for ONF and FP32 matrix-core members) in a HIP
+ * graph. Each moa_group_launch replays it on `stream` (asynchronously) with
+ * the operand pointers given at creation; results are bitwise those of
+ * moa_gemm. Members on the FP8 path (per-call scratch) are refused with
+ * MOA_ERR_UNSUPPORTED. Creation synchronizes with the device; replays of one
+ * group must not overlap each other. moa_group_destroy waits for the group's
+ * outstanding work and frees it. */
+typedef struct moa_group moa_group;
+moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group **out);
+moa_status moa_group_launch(moa_group *group, void *stream);
+moa_status moa_group_destroy(moa_group *group);
+
 /* The plan moa_gemm would use for `desc` (no launch; pointers may be null).
  * Returns the same argument errors as moa_gemm. */
 moa_status moa_plan_query(const moa_gemm_desc *desc, moa_plan_info *out);

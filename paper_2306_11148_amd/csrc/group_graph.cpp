@@ -1,0 +1,114 @@
+// Prepared groups: the grouped launch of a fixed set of products captured
+// once in a HIP graph and replayed. The workspace and the device member list
+// are owned by the group; the captured sequence (counter reset, grouped
+// conditioning, persistent contraction, and single launches of ONF / FP32
+// matrix-core members) allocates, copies and clears nothing, so every replay
+// repeats exactly the same work on the same buffers.
+#include <vector>
+
+#include "moa_internal.h"
+
+struct moa_group {
+    void *ws = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+using namespace moa;
+
+namespace {
+
+void release(moa_group *g) {
+    if (!g) return;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->ws) (void)hipFree(g->ws);   // hipFree waits for work using it
+    delete g;
+}
+
+}  // namespace
+
+extern "C" {
+
+moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group **out) {
+    try {
+        if (!out) return fail(MOA_ERR_INVALID, "null output");
+        *out = nullptr;
+        if (count < 0 || (count > 0 && !descs)) return fail(MOA_ERR_INVALID, "bad descriptor array");
+        std::vector<const moa_gemm_desc *> split;
+        std::vector<moa_gemm_desc> single;
+        for (int64_t k = 0; k < count; ++k) {
+            const moa_gemm_desc &d = descs[k];
+            moa_status s = validate(d, true);
+            if (s != MOA_OK) return s;
+            if (d.m == 0 || d.p == 0) continue;
+            Plan pl;
+            if ((s = make_plan(d, &pl)) != MOA_OK) return s;
+            if (pl.path == MOA_PATH_SPLIT_BF16) split.push_back(&d);
+            else if (pl.workspace_bytes == 0) single.push_back(d);
+            else return fail(MOA_ERR_UNSUPPORTED, "member %lld needs per-call scratch (FP8): not in a prepared group",
+                             (long long)k);
+        }
+        moa_status s = check_group_overlap(descs, count);
+        if (s != MOA_OK) return s;
+        auto *g = new moa_group();
+        hipError_t e = hipSuccess;
+        int64_t tiles = 0;
+        const int cnt = (int)split.size();
+        if (cnt > 0) {
+            e = hipMalloc(&g->ws, (size_t)split_grouped_workspace_bytes(split.data(), cnt));
+            if (e != hipSuccess) {
+                release(g);
+                return fail(MOA_ERR_NOMEM, "group workspace: %s", hipGetErrorString(e));
+            }
+            std::vector<char> host((size_t)split_grouped_desc_bytes(cnt));
+            tiles = split_grouped_layout(split.data(), cnt, g->ws, host.data());
+            e = hipMemcpy(static_cast<char *>(g->ws) + 256, host.data(), host.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                release(g);
+                return hip_fail(e, "group member upload");
+            }
+        }
+        hipStream_t cs = nullptr;
+        if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) {
+            release(g);
+            return hip_fail(e, "capture stream");
+        }
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess && cnt > 0) e = split_grouped_enqueue(g->ws, cnt, tiles, cs);
+        moa_status rs = MOA_OK;
+        for (size_t k = 0; e == hipSuccess && rs == MOA_OK && k < single.size(); ++k)
+            rs = run_gemm(single[k], cs);
+        hipGraph_t graph = nullptr;
+        const hipError_t ee = hipStreamEndCapture(cs, &graph);
+        (void)hipStreamDestroy(cs);
+        g->graph = graph;
+        if (e != hipSuccess || ee != hipSuccess || rs != MOA_OK || !graph) {
+            release(g);
+            if (rs != MOA_OK) return rs;
+            return hip_fail(e != hipSuccess ? e : ee, "group capture");
+        }
+        if ((e = hipGraphInstantiate(&g->exec, g->graph, nullptr, nullptr, 0)) != hipSuccess) {
+            release(g);
+            return hip_fail(e, "hipGraphInstantiate");
+        }
+        *out = g;
+        return MOA_OK;
+    } catch (...) {
+        return fail(MOA_ERR_DEVICE, "internal error");
+    }
+}
+
+moa_status moa_group_launch(moa_group *g, void *stream) {
+    if (!g) return fail(MOA_ERR_INVALID, "null group");
+    const hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return MOA_OK;
+}
+
+moa_status moa_group_destroy(moa_group *g) {
+    release(g);
+    return MOA_OK;
+}
+
+}  // extern "C"

@@ -21,8 +21,8 @@
 // 2. Contraction (matrix-core bound), the blocked form of Fig. 2: each
 //    workgroup owns a BM x BN block of C and walks the S slabs; per slab the
 //    BM + BN records go straight from HBM into LDS (buffer_load ... lds, no
-//    register staging) through a ring of NSTAGE buffers, so loads run three
-//    slabs ahead of the matrix cores. The block products of the slabs are
+//    register staging) through a ring of NSTAGE buffers, so loads run
+//    NSTAGE - 1 slabs ahead of the matrix cores. The block products of the slabs are
 //    summed in registers (the "addition loop" over blocks). The fragments of
 //    slab t+1 are read from LDS while the matrix-core steps of slab t issue.
 //
@@ -52,7 +52,7 @@ __device__ __forceinline__ int64_t rec_off(int64_t r, int64_t s, int64_t S) {
     return ((r / GROUP) * S + s) * (GROUP * REC) + (r % GROUP) * REC;
 }
 __host__ __device__ inline int64_t padded_rows(int64_t rows) { return (rows + GROUP - 1) / GROUP * GROUP; }
-constexpr int NSTAGE = 4;                 // LDS ring depth
+constexpr int NSTAGE = 3;                 // LDS ring depth (3 measured faster than 4 or 5)
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
@@ -297,24 +297,36 @@ __device__ __forceinline__ void split_tile(const uint16_t *__restrict__ Ap,
 
     // One step: make slab t+1 visible, refill the buffer slab t-1 used with
     // slab t+3, read slab t+1's fragments, then issue slab t's products.
+    // Wait until at most `stages` slabs of this wave's loads are still in
+    // flight (the immediate of s_waitcnt must be a constant).
+    auto wait_loads = [&](int64_t stages) {
+        switch (stages <= 0 ? 0 : stages >= 3 ? 3 : (int)stages) {
+        case 0: __builtin_amdgcn_s_waitcnt(waitcnt_vm(0)); break;
+        case 1: __builtin_amdgcn_s_waitcnt(waitcnt_vm(LPW)); break;
+        case 2: __builtin_amdgcn_s_waitcnt(waitcnt_vm(2 * LPW)); break;
+        default: __builtin_amdgcn_s_waitcnt(waitcnt_vm(3 * LPW)); break;
+        }
+    };
+    static_assert(NSTAGE >= 3 && NSTAGE <= 5, "wait_loads covers up to 3 slabs in flight");
+
+    // One step: make slab t+1 visible (its loads landed in every wave), refill
+    // the buffer slab t-1 used with slab t+NSTAGE-1, read slab t+1's
+    // fragments, then issue slab t's products.
     auto step = [&](int64_t t, const Frags &cur, Frags &next) {
         if (t + 1 < S) {
-            if (t + 2 < S) __builtin_amdgcn_s_waitcnt(waitcnt_vm(LPW));
-            else __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+            // issued so far: slabs up to t + NSTAGE - 2; t + 1 must have landed
+            wait_loads(min((int64_t)NSTAGE - 3, S - t - 2));
             ring_barrier();
-            if (t + 3 < S) issue(t + 3);
+            if (t + NSTAGE - 1 < S) issue(t + NSTAGE - 1);
             read_frags(t + 1, next);
         }
         mma(cur);
     };
 
     if (S > 0) {
-        issue(0);
-        if (S > 1) issue(1);
-        if (S > 2) issue(2);
-        if (S > 2) __builtin_amdgcn_s_waitcnt(waitcnt_vm(2 * LPW));
-        else if (S > 1) __builtin_amdgcn_s_waitcnt(waitcnt_vm(LPW));
-        else __builtin_amdgcn_s_waitcnt(waitcnt_vm(0));
+        for (int q = 0; q < NSTAGE - 1; ++q)
+            if (q < S) issue(q);
+        wait_loads(min((int64_t)NSTAGE - 2, S - 1));   // slab 0 has landed
         ring_barrier();
         Frags f0, f1;
         read_frags(0, f0);
@@ -542,18 +554,17 @@ int64_t split_grouped_workspace_bytes(const moa_gemm_desc *const *members, int c
 
 int64_t split_grouped_desc_bytes(int count) { return (int64_t)count * (int64_t)sizeof(GroupMember); }
 
-hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, void *ws,
-                                void *host_staging, hipStream_t st) {
-    if (count <= 0) return hipSuccess;
-    // longest k walk first: the tail of the work list holds the cheapest tiles
+// Lays out the members (longest k walk first: the tail of the work list holds
+// the cheapest tiles) in `host_staging` and the workspace; returns the tile
+// count. The device member array is at ws + 256, the claim counter at ws.
+int64_t split_grouped_layout(const moa_gemm_desc *const *members, int count, void *ws,
+                             void *host_staging) {
     std::vector<int> order(count);
     for (int k = 0; k < count; ++k) order[k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         return members[a]->n > members[b]->n;
     });
     char *base = static_cast<char *>(ws);
-    unsigned long long *counter = reinterpret_cast<unsigned long long *>(base);
-    GroupMember *dev_members = reinterpret_cast<GroupMember *>(base + 256);
     char *rec = base + 256 + align256((int64_t)count * (int64_t)sizeof(GroupMember));
     GroupMember *h = static_cast<GroupMember *>(host_staging);
     int64_t tiles = 0;
@@ -574,9 +585,16 @@ hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, 
         tiles += ((d.m + GB_M - 1) / GB_M) * g.tiles_n;
         h[q] = g;
     }
-    hipError_t e = hipMemcpyAsync(dev_members, h, (size_t)count * sizeof(GroupMember),
-                                  hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return e;
+    return tiles;
+}
+
+// The device part of a grouped launch: reset the claim counter, condition
+// every member, run the persistent contraction. Contains no allocation, copy
+// or memset, so it can be captured in a graph and replayed.
+hipError_t split_grouped_enqueue(void *ws, int count, int64_t tiles, hipStream_t st) {
+    char *base = static_cast<char *>(ws);
+    unsigned long long *counter = reinterpret_cast<unsigned long long *>(base);
+    const GroupMember *dev_members = reinterpret_cast<const GroupMember *>(base + 256);
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, st, counter);
     const unsigned gy = (unsigned)std::min(count, 65535);
     {
@@ -591,6 +609,17 @@ hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, 
                            dim3(TileCfg<GB_M, GB_N, GW_M, GW_N>::THREADS), 0, st, dev_members, count,
                            tiles, counter);
     return hipGetLastError();
+}
+
+hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, void *ws,
+                                void *host_staging, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const int64_t tiles = split_grouped_layout(members, count, ws, host_staging);
+    char *base = static_cast<char *>(ws);
+    hipError_t e = hipMemcpyAsync(base + 256, host_staging, (size_t)count * sizeof(GroupMember),
+                                  hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    return split_grouped_enqueue(ws, count, tiles, st);
 }
 
 hipError_t launch_split_only(const float *X, int64_t count, uint16_t *hi, uint16_t *lo,

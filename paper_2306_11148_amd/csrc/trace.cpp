@@ -38,6 +38,9 @@ hipEvent_t take_event() {
 
 TraceScope::TraceScope(int32_t kernel, hipStream_t stream) : kernel_(kernel), stream_(stream) {
     if (!g_on.load(std::memory_order_relaxed)) return;
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(stream_, &cap) != hipSuccess || cap != hipStreamCaptureStatusNone)
+        return;   // no timing events inside graph captures
     start_ = take_event();
     if (start_ && hipEventRecord(start_, stream_) != hipSuccess) {
         (void)hipEventDestroy(start_);

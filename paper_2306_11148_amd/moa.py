@@ -68,6 +68,7 @@ EXPORTS = [
     "moa_split_bf16", "moa_quantise_fp8", "moa_error_norm", "moa_serve_create",
     "moa_serve_submit", "moa_serve_poll", "moa_serve_drain", "moa_serve_destroy",
     "moa_status_string", "moa_last_error", "moa_trace_enable", "moa_trace_read",
+    "moa_group_create", "moa_group_launch", "moa_group_destroy",
 ]
 
 MOA_KERNELS = {1: "onf_f64", 2: "onf_f32", 3: "mfma_f32", 4: "split_bf16", 5: "fp8", 6: "fp8_2term",
@@ -108,6 +109,9 @@ def lib():
         "moa_status_string": ([i32], ctypes.c_char_p),
         "moa_last_error": ([], ctypes.c_char_p),
         "moa_trace_enable": ([i32], i32),
+        "moa_group_create": ([P(moa_gemm_desc), i64, P(vp)], i32),
+        "moa_group_launch": ([vp, vp], i32),
+        "moa_group_destroy": ([vp], i32),
         "moa_trace_read": ([P(moa_trace_stat), i32, P(i32), i32], i32),
     }
     for name, (args, res) in sig.items():
@@ -261,3 +265,20 @@ def moa_trace_read(reset: bool = False) -> dict:
     _check(lib().moa_trace_read(buf, 16, ctypes.byref(n), int(bool(reset))), "moa_trace_read")
     return {MOA_KERNELS.get(buf[k].kernel, str(buf[k].kernel)): (buf[k].launches, buf[k].total_ms)
             for k in range(n.value)}
+
+
+# ----------------------------------------------------------- prepared groups --
+
+def moa_group_create(descs) -> int:
+    arr = (moa_gemm_desc * len(descs))(*descs)
+    h = ctypes.c_void_p()
+    _check(lib().moa_group_create(arr, len(descs), ctypes.byref(h)), "moa_group_create")
+    return h.value
+
+
+def moa_group_launch(group, stream=None):
+    _check(lib().moa_group_launch(group, _stream_handle(stream)), "moa_group_launch")
+
+
+def moa_group_destroy(group):
+    _check(lib().moa_group_destroy(group), "moa_group_destroy")

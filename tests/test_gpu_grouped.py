@@ -103,3 +103,41 @@ def test_grouped_batching_workload_full_size():
         R = O.gemm_f64(A.astype(np.float64), B.astype(np.float64))
         worst = max(worst, O.rel_err(Ct.cpu().numpy(), R))
     assert worst <= 1e-5, worst
+
+
+def test_prepared_group_graph_replays_match_single_launches():
+    """Captured once, replayed three times with eager work and synchronisation
+    in between; every replay is checked against single launches."""
+    shapes = inputs.grouped_shapes(18, lo=3, hi=400, seed=31)
+    ops = inputs.grouped_operands(shapes, seed=31)
+    paths = ["split_bf16"] * 14 + ["onf", "mfma_f32", "onf", "split_bf16"]
+    members, refs = [], []
+    for (A, B), path in zip(ops, paths):
+        At, Bt = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+        Ct = torch.empty((A.shape[0], B.shape[1]), device=DEV)
+        Rt = torch.empty_like(Ct)
+        moa.moa_gemm(At, Bt, Rt, path=path)
+        members.append((At, Bt, Ct, moa.make_desc(At, Bt, Ct, path=path)))
+        refs.append(Rt)
+    torch.cuda.synchronize()
+    g = moa.moa_group_create([m[3] for m in members])
+    try:
+        for replay in range(3):
+            for _, _, Ct, _ in members:
+                Ct.fill_(float("nan"))
+            torch.cuda.synchronize()
+            moa.moa_group_launch(g)
+            torch.cuda.synchronize()
+            for (_, _, Ct, _), Rt in zip(members, refs):
+                assert torch.equal(Ct, Rt), f"replay {replay}"
+    finally:
+        moa.moa_group_destroy(g)
+
+
+def test_prepared_group_refuses_fp8_members():
+    A = torch.randn((8, 8), device=DEV)
+    B = torch.randn((8, 8), device=DEV)
+    C = torch.empty((8, 8), device=DEV)
+    with pytest.raises(moa.MoaError) as ei:
+        moa.moa_group_create([moa.make_desc(A, B, C, path="fp8")])
+    assert ei.value.status == moa.MOA_ERR_UNSUPPORTED
