@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-serving", action="store_true")
     ap.add_argument("--no-grouped", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--block-sweep", type=str, default=None,
+                    help="comma-separated N list: ONF FP64 time/energy per block size only")
     ap.add_argument("--sweep", type=str, default=None,
                     help="comma-separated N list: time/energy sweep only (one JSON line per point)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -395,6 +397,37 @@ def sweep(args, torch, moa, inputs):
         del A, B, C
 
 
+def block_sweep(args, torch, moa):
+    """The paper's experiment on this GPU: time and joules per product against
+    N for every block size of the plain ONF kernel in FP64 (one JSON line per
+    point). Block sizes are the planner's ONF instantiations, the first being
+    the static rule's 32 x 32 doubles."""
+    import ctypes
+    energy = Energy()
+    L, st = moa.lib(), torch.cuda.current_stream().cuda_stream
+    for N in [int(x) for x in args.block_sweep.split(",")]:
+        gen = torch.Generator(device="cuda").manual_seed(N)
+        A = torch.rand((N, N), generator=gen, device="cuda", dtype=torch.float64) * 2 - 1
+        B = torch.rand((N, N), generator=gen, device="cuda", dtype=torch.float64) * 2 - 1
+        C = torch.empty((N, N), device="cuda", dtype=torch.float64)
+        for v in range(4):
+            d = moa.make_desc(A, B, C, path=moa.MOA_PATH_ONF, flags=moa.MOA_FLAG_VARIANT(v))
+            plan = moa.moa_plan_query(d)
+
+            def f():
+                if L.moa_gemm(ctypes.byref(d), st) != 0:
+                    raise RuntimeError(moa.moa_last_error())
+            f()
+            reps = max(2, min(100, int(0.5 / (2.0 * N ** 3 / 5e13))))
+            per, tot = timed_loop(f, reps, torch)
+            ms = tot / reps
+            e = energy_per_call(f, min(args.energy_seconds, 1.0), ms, energy, torch)
+            print(json.dumps({"block_sweep": "ONF FP64", "N": N, "block": [plan["tile_m"], plan["tile_n"]],
+                              "components": plan["tile_m"] * plan["tile_n"], "ms": round(ms, 4),
+                              "tflops": round(2.0 * N ** 3 / ms / 1e9, 3), "energy": e}), flush=True)
+        del A, B, C
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -410,6 +443,9 @@ def main():
     torch.cuda.set_device(dev)
     if args.sweep:
         sweep(args, torch, moa, inputs)
+        return
+    if args.block_sweep:
+        block_sweep(args, torch, moa)
         return
     N = args.n
     A_h, B_h = inputs.normal_f32(N, N, N, seed=N)

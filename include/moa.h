@@ -118,6 +118,8 @@ typedef struct moa_plan_info {
     int64_t workgroups;       /* grid size */
     int64_t workspace_bytes;  /* scratch taken from the stream allocator */
     int64_t static_components;/* static block size rule result (components) */
+    int32_t variant;          /* instantiation of the path's kernel table */
+    int32_t tuned;            /* 1 if the variant came from the autotuner */
 } moa_plan_info;
 
 /* Eq. 3 on the device. Asynchronous on `stream`.
@@ -159,6 +161,25 @@ moa_status moa_group_destroy(moa_group *group);
 /* The plan moa_gemm would use for `desc` (no launch; pointers may be null).
  * Returns the same argument errors as moa_gemm. */
 moa_status moa_plan_query(const moa_gemm_desc *desc, moa_plan_info *out);
+
+/* Autotuner. The planner starts from the static rule (below) and picks a
+ * kernel instantiation from shape alone; moa_autotune times every
+ * instantiation of desc's path on the caller's buffers (C is overwritten;
+ * `reps` >= 1 timed runs each, after one warm-up) on `stream`, waits for
+ * them, and records the fastest for desc's shape class -- (dtype, path,
+ * FP8 term count, ceil(log2 m), ceil(log2 n), ceil(log2 p)). moa_gemm,
+ * moa_gemm_grouped's single launches and moa_plan_query then use the
+ * recorded instantiation for every product of that class unless
+ * MOA_FLAG_VARIANT forces one. `chosen` (may be null) receives the plan and
+ * `best_ms` (may be null) the time per run of the winner. Errors: as
+ * moa_gemm; MOA_ERR_INVALID for reps < 1. */
+moa_status moa_autotune(const moa_gemm_desc *desc, int32_t reps, void *stream,
+                        moa_plan_info *chosen, double *best_ms);
+/* Writes the recorded classes to a text file (one class per line) /
+ * merges a file written by moa_autotune_save / forgets every record. */
+moa_status moa_autotune_save(const char *path);
+moa_status moa_autotune_load(const char *path);
+moa_status moa_autotune_clear(void);
 
 /* Block-size rule of section "Technical Details": the largest power of two b
  * with nblocks * b * elem_bytes <= budget_bytes (one block each of A, B and C

@@ -179,10 +179,83 @@ moa_status moa_plan_query(const moa_gemm_desc *desc, moa_plan_info *out) {
         out->workgroups = pl.workgroups;
         out->workspace_bytes = pl.workspace_bytes;
         out->static_components = pl.static_components;
+        out->variant = pl.variant;
+        out->tuned = pl.tuned ? 1 : 0;
         return MOA_OK;
     } catch (...) {
         return fail(MOA_ERR_DEVICE, "internal error");
     }
+}
+
+moa_status moa_autotune(const moa_gemm_desc *desc, int32_t reps, void *stream, moa_plan_info *chosen,
+                        double *best_ms) {
+    try {
+        if (!desc) return fail(MOA_ERR_INVALID, "null descriptor");
+        if (reps < 1) return fail(MOA_ERR_INVALID, "reps must be >= 1");
+        moa_status s = validate(*desc, true);
+        if (s != MOA_OK) return s;
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        const moa_path path = resolve_path(*desc);
+        if (desc->m > 0 && desc->p > 0) {
+            const int nv = variant_count(*desc, path);
+            hipEvent_t a = nullptr, b = nullptr;
+            hipError_t e = hipEventCreate(&a);
+            if (e == hipSuccess) e = hipEventCreate(&b);
+            if (e != hipSuccess) {
+                if (a) (void)hipEventDestroy(a);
+                return hip_fail(e, "hipEventCreate");
+            }
+            int best = -1;
+            float best_t = 0.0f;
+            for (int v = 0; v < nv && s == MOA_OK; ++v) {
+                moa_gemm_desc d = *desc;
+                d.path = path;
+                d.flags = (d.flags & ~MOA_FLAG_VARIANT_MASK) | MOA_FLAG_VARIANT(v);
+                Plan pl;
+                if (make_plan(d, &pl) != MOA_OK) continue;       // e.g. a grid limit
+                if ((s = run_gemm(d, st)) != MOA_OK) break;      // warm-up
+                (void)hipEventRecord(a, st);
+                for (int r = 0; r < reps && s == MOA_OK; ++r) s = run_gemm(d, st);
+                (void)hipEventRecord(b, st);
+                if ((e = hipEventSynchronize(b)) != hipSuccess) {
+                    s = hip_fail(e, "autotune timing");
+                    break;
+                }
+                float ms = 0.0f;
+                (void)hipEventElapsedTime(&ms, a, b);
+                ms /= (float)reps;
+                if (best < 0 || ms < best_t) {
+                    best = v;
+                    best_t = ms;
+                }
+            }
+            (void)hipEventDestroy(a);
+            (void)hipEventDestroy(b);
+            if (s != MOA_OK) return s;
+            if (best < 0) return fail(MOA_ERR_UNSUPPORTED, "no variant of path %d can run this shape", (int)path);
+            record_tuned_variant(*desc, path, best, best_t);
+            if (best_ms) *best_ms = best_t;
+        }
+        if (chosen) return moa_plan_query(desc, chosen);
+        return MOA_OK;
+    } catch (...) {
+        return fail(MOA_ERR_DEVICE, "internal error");
+    }
+}
+
+moa_status moa_autotune_save(const char *path) {
+    if (!path) return fail(MOA_ERR_INVALID, "null path");
+    return autotune_save(path);
+}
+
+moa_status moa_autotune_load(const char *path) {
+    if (!path) return fail(MOA_ERR_INVALID, "null path");
+    return autotune_load(path);
+}
+
+moa_status moa_autotune_clear(void) {
+    autotune_clear();
+    return MOA_OK;
 }
 
 int64_t moa_static_block_components(int64_t budget_bytes, int64_t elem_bytes, int64_t nblocks) {

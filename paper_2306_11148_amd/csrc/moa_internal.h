@@ -43,6 +43,7 @@ struct Plan {
     int64_t workgroups = 0;
     int64_t workspace_bytes = 0;
     int64_t static_components = 0;
+    bool tuned = false;
 };
 
 // Validates `d` (shapes, pointers, enums, aliasing) without touching the
@@ -58,6 +59,14 @@ constexpr int kNumCUs = 256;
 constexpr int kNumXCDs = 8;
 
 int64_t static_block_components(int64_t budget, int64_t elem, int64_t nblocks);
+
+// Autotuner table: shape class -> variant (-1 if none recorded).
+int tuned_variant(const moa_gemm_desc &d, moa_path path);
+void record_tuned_variant(const moa_gemm_desc &d, moa_path path, int variant, double ms);
+int variant_count(const moa_gemm_desc &d, moa_path path);
+moa_status autotune_save(const char *path);
+moa_status autotune_load(const char *path);
+void autotune_clear();
 
 // ----------------------------------------------------------------- trace --
 // Brackets the launches made in its lifetime with events on `stream` while

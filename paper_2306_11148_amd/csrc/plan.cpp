@@ -11,11 +11,100 @@
 // planner (and the autotuner) choose among: a launch must also cover the 256
 // CUs several times over, so the planner takes the largest block that still
 // yields at least one workgroup per CU and falls back to the smallest.
+#include <array>
+#include <cstdio>
 #include <cstdlib>
+#include <map>
+#include <mutex>
 
 #include "moa_internal.h"
 
 namespace moa {
+
+namespace {
+
+using ClassKey = std::array<int, 6>;
+struct Tuned { int variant; double ms; };
+std::mutex g_tune_mu;
+std::map<ClassKey, Tuned> g_tuned;
+
+int ceil_log2(int64_t x) {
+    int r = 0;
+    while (r < 62 && (int64_t(1) << r) < x) ++r;
+    return r;
+}
+
+ClassKey class_key(const moa_gemm_desc &d, moa_path path) {
+    return {d.dtype, (int)path, (d.flags & MOA_FLAG_FP8_TWO_TERM) ? 2 : 1, ceil_log2(d.m),
+            ceil_log2(d.n), ceil_log2(d.p)};
+}
+
+}  // namespace
+
+int tuned_variant(const moa_gemm_desc &d, moa_path path) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(class_key(d, path));
+    return it == g_tuned.end() ? -1 : it->second.variant;
+}
+
+void record_tuned_variant(const moa_gemm_desc &d, moa_path path, int variant, double ms) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[class_key(d, path)] = {variant, ms};
+}
+
+int variant_count(const moa_gemm_desc &d, moa_path path) {
+    switch (path) {
+    case MOA_PATH_ONF: return onf_variant_count((moa_dtype)d.dtype);
+    case MOA_PATH_SPLIT_BF16: return split_bf16_variant_count();
+    default: return 1;
+    }
+}
+
+moa_status autotune_save(const char *path) {
+    FILE *f = std::fopen(path, "w");
+    if (!f) return fail(MOA_ERR_INVALID, "cannot write %s", path);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::fprintf(f, "# moa autotune v1: dtype path terms log2m log2n log2p variant ms\n");
+    for (const auto &kv : g_tuned)
+        std::fprintf(f, "%d %d %d %d %d %d %d %.6f\n", kv.first[0], kv.first[1], kv.first[2], kv.first[3],
+                     kv.first[4], kv.first[5], kv.second.variant, kv.second.ms);
+    std::fclose(f);
+    return MOA_OK;
+}
+
+moa_status autotune_load(const char *path) {
+    FILE *f = std::fopen(path, "r");
+    if (!f) return fail(MOA_ERR_INVALID, "cannot read %s", path);
+    char line[256];
+    std::map<ClassKey, Tuned> add;
+    while (std::fgets(line, sizeof line, f)) {
+        if (line[0] == '#') continue;
+        ClassKey k;
+        Tuned t;
+        if (std::sscanf(line, "%d %d %d %d %d %d %d %lf", &k[0], &k[1], &k[2], &k[3], &k[4], &k[5], &t.variant,
+                        &t.ms) != 8) {
+            std::fclose(f);
+            return fail(MOA_ERR_INVALID, "malformed line in %s: %s", path, line);
+        }
+        moa_gemm_desc probe{};
+        probe.dtype = k[0];
+        if (k[1] < MOA_PATH_ONF || k[1] > MOA_PATH_FP8_SCALED || (k[0] != MOA_F64 && k[0] != MOA_F32) ||
+            t.variant < 0 || t.variant >= variant_count(probe, (moa_path)k[1])) {
+            std::fclose(f);
+            return fail(MOA_ERR_INVALID, "out-of-range entry in %s: %s", path, line);
+        }
+        add[k] = t;
+    }
+    std::fclose(f);
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    for (const auto &kv : add) g_tuned[kv.first] = kv.second;
+    return MOA_OK;
+}
+
+void autotune_clear() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned.clear();
+}
 
 int64_t static_block_components(int64_t budget, int64_t elem, int64_t nblocks) {
     if (budget <= 0 || elem <= 0 || nblocks <= 0) return 0;
@@ -49,7 +138,10 @@ moa_status make_plan(const moa_gemm_desc &d, Plan *out) {
         if (forced >= 0) {
             if (forced >= nv) return fail(MOA_ERR_INVALID, "variant %d out of range (ONF has %d)", forced, nv);
             v = forced;
+        } else if ((v = tuned_variant(d, pl.path)) >= 0) {
+            pl.tuned = true;
         } else {
+            v = 0;
             for (int c = nv - 1; c >= 0; --c) {
                 Plan t;
                 onf_variant_shape((moa_dtype)d.dtype, c, &t);
@@ -73,7 +165,10 @@ moa_status make_plan(const moa_gemm_desc &d, Plan *out) {
         if (forced >= 0) {
             if (forced >= nv) return fail(MOA_ERR_INVALID, "variant %d out of range (SPLIT_BF16 has %d)", forced, nv);
             v = forced;
+        } else if ((v = tuned_variant(d, pl.path)) >= 0) {
+            pl.tuned = true;
         } else {
+            v = 0;
             for (int c = nv - 1; c >= 0; --c) {
                 Plan t;
                 split_bf16_shape(c, &t);

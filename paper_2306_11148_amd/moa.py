@@ -48,7 +48,8 @@ class moa_plan_info(ctypes.Structure):
                 ("wave_n", ctypes.c_int32), ("lane_m", ctypes.c_int32),
                 ("lane_n", ctypes.c_int32), ("threads", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32), ("workgroups", ctypes.c_int64),
-                ("workspace_bytes", ctypes.c_int64), ("static_components", ctypes.c_int64)]
+                ("workspace_bytes", ctypes.c_int64), ("static_components", ctypes.c_int64),
+                ("variant", ctypes.c_int32), ("tuned", ctypes.c_int32)]
 
 
 class moa_serve_cfg(ctypes.Structure):
@@ -69,6 +70,7 @@ EXPORTS = [
     "moa_serve_submit", "moa_serve_poll", "moa_serve_drain", "moa_serve_destroy",
     "moa_status_string", "moa_last_error", "moa_trace_enable", "moa_trace_read",
     "moa_group_create", "moa_group_launch", "moa_group_destroy",
+    "moa_autotune", "moa_autotune_save", "moa_autotune_load", "moa_autotune_clear",
 ]
 
 MOA_KERNELS = {1: "onf_f64", 2: "onf_f32", 3: "mfma_f32", 4: "split_bf16", 5: "fp8", 6: "fp8_2term",
@@ -109,6 +111,10 @@ def lib():
         "moa_status_string": ([i32], ctypes.c_char_p),
         "moa_last_error": ([], ctypes.c_char_p),
         "moa_trace_enable": ([i32], i32),
+        "moa_autotune": ([P(moa_gemm_desc), i32, vp, P(moa_plan_info), P(ctypes.c_double)], i32),
+        "moa_autotune_save": ([ctypes.c_char_p], i32),
+        "moa_autotune_load": ([ctypes.c_char_p], i32),
+        "moa_autotune_clear": ([], i32),
         "moa_group_create": ([P(moa_gemm_desc), i64, P(vp)], i32),
         "moa_group_launch": ([vp, vp], i32),
         "moa_group_destroy": ([vp], i32),
@@ -282,3 +288,26 @@ def moa_group_launch(group, stream=None):
 
 def moa_group_destroy(group):
     _check(lib().moa_group_destroy(group), "moa_group_destroy")
+
+
+# ---------------------------------------------------------------- autotuner --
+
+def moa_autotune(desc: moa_gemm_desc, reps: int = 3, stream=None):
+    """Times every instantiation for desc's shape class; returns (plan, best_ms)."""
+    info = moa_plan_info()
+    ms = ctypes.c_double()
+    _check(lib().moa_autotune(ctypes.byref(desc), reps, _stream_handle(stream), ctypes.byref(info),
+                              ctypes.byref(ms)), "moa_autotune")
+    return {f: getattr(info, f) for f, _ in moa_plan_info._fields_}, ms.value
+
+
+def moa_autotune_save(path: str):
+    _check(lib().moa_autotune_save(path.encode()), "moa_autotune_save")
+
+
+def moa_autotune_load(path: str):
+    _check(lib().moa_autotune_load(path.encode()), "moa_autotune_load")
+
+
+def moa_autotune_clear():
+    _check(lib().moa_autotune_clear(), "moa_autotune_clear")

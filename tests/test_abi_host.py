@@ -109,7 +109,7 @@ def test_descriptor_layout_matches_header():
     # int64 m,n,p; int32 dtype,path; 3 pointers; int32 accumulate; uint32 flags
     assert ctypes.sizeof(moa.moa_gemm_desc) == 3 * 8 + 2 * 4 + 3 * 8 + 2 * 4
     assert moa.moa_gemm_desc.A.offset == 32
-    assert ctypes.sizeof(moa.moa_plan_info) == 11 * 4 + 4 + 3 * 8
+    assert ctypes.sizeof(moa.moa_plan_info) == 11 * 4 + 4 + 3 * 8 + 2 * 4
 
 
 def test_grouped_overlap_rejected_before_launch():
@@ -138,3 +138,27 @@ def test_serve_argument_errors_before_device():
     assert L.moa_serve_poll(None, 1, None) == moa.MOA_ERR_INVALID
     assert L.moa_serve_drain(None) == moa.MOA_ERR_INVALID
     assert L.moa_serve_destroy(None) == moa.MOA_OK
+
+
+def test_autotune_table_save_load_and_validation(tmp_path):
+    moa.moa_autotune_clear()
+    f = tmp_path / "tune.txt"
+    # a hand-written record: FP64 ONF, 1 term, 2^8 x 2^8 x 2^8 class -> variant 2
+    f.write_text("# moa autotune v1\n0 1 1 8 8 8 2 0.5\n")
+    moa.moa_autotune_load(str(f))
+    q = moa.moa_plan_query(_desc(256, 256, 256, moa.MOA_F64))
+    assert q["tuned"] == 1 and q["variant"] == 2
+    q_other = moa.moa_plan_query(_desc(1000, 256, 256, moa.MOA_F64))   # another class
+    assert q_other["tuned"] == 0
+    forced = moa.moa_plan_query(_desc(256, 256, 256, moa.MOA_F64, flags=moa.MOA_FLAG_VARIANT(0)))
+    assert forced["tuned"] == 0 and forced["variant"] == 0
+    g = tmp_path / "out.txt"
+    moa.moa_autotune_save(str(g))
+    assert "0 1 1 8 8 8 2" in g.read_text()
+    bad = tmp_path / "bad.txt"
+    bad.write_text("0 1 1 8 8 8 9 0.5\n")                      # variant out of range
+    with pytest.raises(moa.MoaError):
+        moa.moa_autotune_load(str(bad))
+    moa.moa_autotune_clear()
+    assert moa.moa_plan_query(_desc(256, 256, 256, moa.MOA_F64))["tuned"] == 0
+    assert moa.lib().moa_autotune(None, 1, None, None, None) == moa.MOA_ERR_INVALID

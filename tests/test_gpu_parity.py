@@ -225,3 +225,21 @@ def test_streams_are_respected():
         Dt = Ct * 2
     s.synchronize()
     assert np.array_equal(Dt.cpu().numpy(), 2 * O.gemm_f32_fma(A, B))
+
+
+def test_autotune_records_a_variant_and_results_stay_bitwise():
+    m, n, p = 300, 257, 520
+    A, B = inputs.normal_f32(m, n, p, seed=77)
+    At, Bt = dev(A), dev(B)
+    Ct = torch.empty((m, p), device=DEV)
+    desc = moa.make_desc(At, Bt, Ct, path="onf")
+    moa.moa_autotune_clear()
+    try:
+        plan, ms = moa.moa_autotune(desc, reps=2)
+        assert plan["tuned"] == 1 and 0 <= plan["variant"] < 4 and ms > 0
+        Ct.fill_(float("nan"))
+        moa.moa_gemm(At, Bt, Ct, path="onf")
+        torch.cuda.synchronize()
+        assert np.array_equal(Ct.cpu().numpy(), O.gemm_f32_fma(A, B))
+    finally:
+        moa.moa_autotune_clear()
