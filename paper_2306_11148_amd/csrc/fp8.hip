@@ -191,6 +191,9 @@ __device__ __forceinline__ i32x8_t frag32(const uint8_t *p) {
 }
 
 constexpr int BK8 = 128;                 // k per slab (bytes of E4M3)
+// E8M0 block scale 2^(127-127) = 1 for both operands of the scaled
+// matrix-core step (0 would mean 2^-127).
+constexpr int kScaleOne = 0x7f;
 constexpr int BM = 128, BN = 128, WM = 64, WN = 64;
 
 template <bool TWO>
@@ -299,12 +302,12 @@ __global__ __launch_bounds__(256) void fp8_gemm_kernel(
 #pragma unroll
                 for (int b = 0; b < FN; ++b) {
                     acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                        ah[a], bh[b], acc[a][b], 0, 0, 0, 0, 0, 0);
+                        ah[a], bh[b], acc[a][b], 0, 0, 0, kScaleOne, 0, kScaleOne);
                     if (TWO) {
                         acx[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                            ah[a], bl[b], acx[a][b], 0, 0, 0, 0, 0, 0);
+                            ah[a], bl[b], acx[a][b], 0, 0, 0, kScaleOne, 0, kScaleOne);
                         acx[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                            al[a], bh[b], acx[a][b], 0, 0, 0, 0, 0, 0);
+                            al[a], bh[b], acx[a][b], 0, 0, 0, kScaleOne, 0, kScaleOne);
                     }
                 }
         }

@@ -53,6 +53,10 @@ __device__ __forceinline__ int64_t rec_off(int64_t r, int64_t s, int64_t S) {
 }
 __host__ __device__ inline int64_t padded_rows(int64_t rows) { return (rows + GROUP - 1) / GROUP * GROUP; }
 constexpr int NSTAGE = 3;                 // LDS ring depth (3 measured faster than 4 or 5)
+// Two slabs per barrier (needs a 4-buffer ring): at even steps wait for the
+// two slabs loaded at the previous barrier, refill the two buffers freed
+// since, then run two slabs without a barrier.
+constexpr bool PAIRED = false;
 
 typedef __attribute__((address_space(3))) void lds_void_t;
 
@@ -115,66 +119,95 @@ __global__ __launch_bounds__(256) void pack_rows_kernel(const float *__restrict_
 
 // Columns of X (K x cols, row-major) -> records (transposed). Block (bx, by)
 // covers columns 64 bx .. 64 bx + 63 and slabs 4 by .. 4 by + 3; it goes
-// through LDS so that reads of X rows are contiguous and each thread writes
-// one whole 64-byte record (a wave: 64 columns of one slab = four whole
-// record tiles). Columns past `cols` get zero records. All 256 threads must
-// call it together.
+// through LDS so that reads of X rows are contiguous and every wave store
+// writes one whole KiB record tile. Columns past `cols` get zero records.
+// All 256 threads must call it together.
+// Columns of X (K x cols, row-major) -> records (transposed), 64 columns x
+// 64 k (4 slabs) per block through LDS: reads of X rows are contiguous
+// float4s and each thread writes one whole 64-byte record. Columns past
+// `cols` get zero records. All 256 threads must take part.
+struct ColBlockRegs { float4 v[4]; };
+
+__device__ __forceinline__ void pack_cols_load(const float *__restrict__ X, int64_t K, int64_t cols,
+                                               int64_t bx, int64_t by, int vec, ColBlockRegs &r) {
+    const int t = threadIdx.x;
+    const int jq = (t & 15) * 4;                 // four columns 4 (t%16) .. +3
+    const int64_t j = bx * 64 + jq;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t k = by * 4 * SLAB + (t >> 4) + 16 * i;
+        float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+        if (k < K) {
+            if (vec && j + 4 <= cols) {
+                v = *reinterpret_cast<const float4 *>(X + k * cols + j);
+            } else {
+                float *e = reinterpret_cast<float *>(&v);
+#pragma unroll
+                for (int q = 0; q < 4; ++q)
+                    if (j + q < cols) e[q] = X[k * cols + j + q];
+            }
+        }
+        r.v[i] = v;
+    }
+}
+
+// Stores a loaded block to LDS, then (after a barrier) writes its records.
+__device__ __forceinline__ void pack_cols_emit(const ColBlockRegs &r, int64_t cols, int64_t S,
+                                               uint16_t *__restrict__ P, int64_t bx, int64_t by,
+                                               float (*tile)[64 + 4]) {
+    const int t = threadIdx.x;
+#pragma unroll
+    for (int i = 0; i < 4; ++i)
+        *reinterpret_cast<float4 *>(&tile[(t >> 4) + 16 * i][(t & 15) * 4]) = r.v[i];
+    __syncthreads();
+    const int jj = t & 63, part = t >> 6;
+    const int64_t j = bx * 64 + jj, s = by * 4 + part;
+    if (j < padded_rows(cols) && s < S) {
+        uint4 h[2], l[2];
+#pragma unroll
+        for (int c = 0; c < 2; ++c) {
+            const int kb = part * SLAB + c * 8;
+            split_pair(tile[kb + 0][jj], tile[kb + 1][jj], &h[c].x, &l[c].x);
+            split_pair(tile[kb + 2][jj], tile[kb + 3][jj], &h[c].y, &l[c].y);
+            split_pair(tile[kb + 4][jj], tile[kb + 5][jj], &h[c].z, &l[c].z);
+            split_pair(tile[kb + 6][jj], tile[kb + 7][jj], &h[c].w, &l[c].w);
+        }
+        uint4 *rec = reinterpret_cast<uint4 *>(P + rec_off(j, s, S));
+        rec[0] = h[0];
+        rec[1] = h[1];
+        rec[2] = l[0];
+        rec[3] = l[1];
+    }
+    __syncthreads();                             // tile free for the next block
+}
+
 __device__ __forceinline__ void pack_cols_block(const float *__restrict__ X, int64_t K, int64_t cols,
                                                 int64_t S, uint16_t *__restrict__ P, int64_t bx,
                                                 int64_t by, float (*tile)[64 + 4], int vec) {
-    const int64_t j0 = bx * 64;
-    const int64_t s0 = by * 4;
-    const int t = threadIdx.x;
-    {
-        // thread -> (k row kk = t/16 + 16 i, four columns 4 (t%16) .. +3)
-        const int jq = (t & 15) * 4;
-        const int64_t j = j0 + jq;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int kk = (t >> 4) + 16 * i;
-            const int64_t k = s0 * SLAB + kk;
-            float4 v = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-            if (k < K) {
-                if (vec && j + 4 <= cols) {
-                    v = *reinterpret_cast<const float4 *>(X + k * cols + j);
-                } else {
-                    float *e = reinterpret_cast<float *>(&v);
-#pragma unroll
-                    for (int q = 0; q < 4; ++q)
-                        if (j + q < cols) e[q] = X[k * cols + j + q];
-                }
-            }
-            *reinterpret_cast<float4 *>(&tile[kk][jq]) = v;
-        }
-    }
-    __syncthreads();
-    const int jj = t & 63, part = t >> 6;
-    const int64_t j = j0 + jj, s = s0 + part;
-    if (j >= padded_rows(cols) || s >= S) return;
-    uint4 h[2], l[2];
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-        const int kb = part * SLAB + c * 8;
-        split_pair(tile[kb + 0][jj], tile[kb + 1][jj], &h[c].x, &l[c].x);
-        split_pair(tile[kb + 2][jj], tile[kb + 3][jj], &h[c].y, &l[c].y);
-        split_pair(tile[kb + 4][jj], tile[kb + 5][jj], &h[c].z, &l[c].z);
-        split_pair(tile[kb + 6][jj], tile[kb + 7][jj], &h[c].w, &l[c].w);
-    }
-    uint4 *rec = reinterpret_cast<uint4 *>(P + rec_off(j, s, S));
-    rec[0] = h[0];
-    rec[1] = h[1];
-    rec[2] = l[0];
-    rec[3] = l[1];
+    ColBlockRegs r;
+    pack_cols_load(X, K, cols, bx, by, vec, r);
+    pack_cols_emit(r, cols, S, P, bx, by, tile);
 }
+
+// Each workgroup walks up to COL_BLOCKS consecutive 64-k blocks of one
+// 64-column strip, loading block b+1 while it writes block b.
+constexpr int COL_BLOCKS = 4;
 
 __global__ __launch_bounds__(256) void pack_cols_kernel(const float *__restrict__ X, int64_t K,
                                                         int64_t cols, int64_t S, int vec,
                                                         uint16_t *__restrict__ P) {
     __shared__ __attribute__((aligned(16))) float tile[4 * SLAB][64 + 4];
     const int64_t by_count = (S + 3) / 4;
-    for (int64_t by = blockIdx.y; by < by_count; by += gridDim.y) {
-        pack_cols_block(X, K, cols, S, P, blockIdx.x, by, tile, vec);
-        __syncthreads();
+    const int64_t bx = blockIdx.x;
+    for (int64_t by0 = (int64_t)blockIdx.y * COL_BLOCKS; by0 < by_count; by0 += (int64_t)gridDim.y * COL_BLOCKS) {
+        const int64_t by_end = min(by0 + COL_BLOCKS, by_count);
+        ColBlockRegs cur, next;
+        pack_cols_load(X, K, cols, bx, by0, vec, cur);
+        for (int64_t by = by0; by < by_end; ++by) {
+            if (by + 1 < by_end) pack_cols_load(X, K, cols, bx, by + 1, vec, next);
+            pack_cols_emit(cur, cols, S, P, bx, by, tile);
+            cur = next;
+        }
     }
 }
 
@@ -323,7 +356,7 @@ __device__ __forceinline__ void split_tile(const uint16_t *__restrict__ Ap,
         mma(cur);
     };
 
-    if (S > 0) {
+    if (S > 0 && !PAIRED) {
         for (int q = 0; q < NSTAGE - 1; ++q)
             if (q < S) issue(q);
         wait_loads(min((int64_t)NSTAGE - 2, S - 1));   // slab 0 has landed
@@ -336,6 +369,28 @@ __device__ __forceinline__ void split_tile(const uint16_t *__restrict__ Ap,
             step(t + 1, f1, f0);
         }
         if (t < S) step(t, f0, f1);
+    } else if (S > 0) {
+        static_assert(!PAIRED || NSTAGE == 4, "paired barriers use a 4-buffer ring");
+        for (int q = 0; q < 3; ++q)
+            if (q < S) issue(q);
+        wait_loads(min((int64_t)2, S - 1));            // slab 0 has landed
+        ring_barrier();
+        Frags f0, f1;
+        read_frags(0, f0);
+        for (int64_t t = 0; t < S; t += 2) {
+            if (t + 1 < S) {
+                wait_loads(0);                         // slabs t+1, t+2 have landed
+                ring_barrier();
+                if (t + 3 < S) issue(t + 3);           // into the buffers of slabs t-1 and t,
+                if (t + 4 < S) issue(t + 4);           // whose fragments are in registers
+                read_frags(t + 1, f1);
+            }
+            mma(f0);
+            if (t + 1 < S) {
+                if (t + 2 < S) read_frags(t + 2, f0);
+                mma(f1);
+            }
+        }
     }
 
     // Epilogue: register r of lane l holds C[8(r/4) + 4(l/32) + r%4][l%32] of
@@ -516,7 +571,7 @@ hipError_t launch_split_pack(const moa_gemm_desc &d, void *ws, hipStream_t st) {
     if (blocks > 65536) blocks = 65536;
     hipLaunchKernelGGL(pack_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, d.m, d.n, S, vec, Ap);
     const int vec_b = (d.p % 4 == 0) && ((uintptr_t)B % 16 == 0);
-    const int64_t by = (S + 3) / 4;
+    const int64_t by = ((S + 3) / 4 + COL_BLOCKS - 1) / COL_BLOCKS;
     hipLaunchKernelGGL(pack_cols_kernel, dim3((unsigned)((d.p + 63) / 64), (unsigned)(by < 65535 ? by : 65535)),
                        dim3(256), 0, st, B, d.n, d.p, S, vec_b, Bp);
     return hipGetLastError();
