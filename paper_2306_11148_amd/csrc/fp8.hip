@@ -10,17 +10,35 @@
 // With the residual term r = x 2^e - q (exact in FP32) kept as
 // l = RNE_e4m3(2^4 r):
 //   C[i,j] = 2^-(e_i+f_j) (sum qA qB + 2^-4 (sum qA lB + sum lA qB))
+// The factor 2^-4 is the E8M0 block scale of the residual operand of the
+// scaled matrix-core step, so all three sums share one FP32 accumulator.
 //
-// Conditioning kernels (HBM-bound): row amax of A and column amax of B
-// (atomic max on the bit patterns of |x|, which order like unsigned ints),
-// then quantisation of A in place order and of B into a k-contiguous
-// (transposed) copy, both in a stream-ordered workspace. The GEMM kernel uses
-// the blocking of Fig. 2 with v_mfma_f32_32x32x64_f8f6f4 steps.
+// Conditioning (HBM-bound): row exponents of A (one wave per row), column
+// amax of B (atomic max on the bit patterns of |x|, which order like
+// unsigned ints), then quantisation straight into record tiles (layout in
+// ring_gemm.h): record (r, s) holds the 64 codes of k = 64s .. 64s+63 of row r
+// of A, or of column r of B (B is transposed on the way). The two-term path
+// keeps the residual codes in a second record array per operand. The
+// contraction is the record-tile ring of ring_gemm.h with
+// v_mfma_scale_f32_32x32x64_f8f6f4 steps.
 #include "moa_internal.h"
+#include "ring_gemm.h"
 #include "tile_common.h"
 
 namespace moa {
 namespace {
+
+using ring::GROUP;
+using ring::padded_rows;
+using ring::REC_BYTES;
+
+constexpr int SLAB8 = 64;                // k per record: 64 E4M3 codes
+static_assert(REC_BYTES == SLAB8, "one record holds one slab of codes");
+// E8M0 block scales of the scaled matrix-core step: 2^(x - 127).
+constexpr int kScaleOne = 0x7f;          // 2^0 (0 would mean 2^-127)
+constexpr int kScaleLo = 0x7f - 4;       // 2^-4: residual codes carry a factor 2^4
+
+typedef int i32x4_t __attribute__((ext_vector_type(4)));
 
 __device__ __forceinline__ int pow2_exponent(float amax) {
     if (!(amax > 0.0f)) return 0;
@@ -63,70 +81,156 @@ __global__ void fill_u32_kernel(uint32_t *x, int64_t count) {
     if (t < count) x[t] = 0u;
 }
 
-// One wave per row of A: amax of |A[i, :]| -> amax bits.
-__global__ __launch_bounds__(256) void row_amax_kernel(const float *__restrict__ A, int64_t m,
-                                                       int64_t n, uint32_t *__restrict__ amax) {
+// One wave per row of A: e_i from amax |A[i, :]|.
+__global__ __launch_bounds__(256) void row_exp_kernel(const float *__restrict__ A, int64_t m, int64_t n,
+                                                      int vec, int32_t *__restrict__ e) {
     const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (i >= m) return;
     const float *row = A + i * n;
     float mx = 0.0f;
-    for (int64_t k = lane; k < n; k += 64) mx = fmaxf(mx, fabsf(row[k]));
+    if (vec) {
+        const float4 *r4 = reinterpret_cast<const float4 *>(row);
+        for (int64_t k = lane; k < n / 4; k += 64) {
+            const float4 v = r4[k];
+            mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
+        }
+    } else {
+        for (int64_t k = lane; k < n; k += 64) mx = fmaxf(mx, fabsf(row[k]));
+    }
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) mx = fmaxf(mx, __shfl_xor(mx, off, 64));
-    if (lane == 0) amax[i] = __float_as_uint(mx);
+    if (lane == 0) e[i] = pow2_exponent(mx);
 }
 
-// Column amax of B: each thread takes one column over a 64-row band.
+// Column amax of B: each thread takes one column over a band of 256 rows.
+constexpr int COL_BAND = 256;
 __global__ __launch_bounds__(256) void col_amax_kernel(const float *__restrict__ B, int64_t n,
                                                        int64_t p, uint32_t *__restrict__ amax) {
     const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t k0 = (int64_t)blockIdx.y * 64;
+    const int64_t k0 = (int64_t)blockIdx.y * COL_BAND;
     if (j >= p) return;
     float mx = 0.0f;
-    const int64_t k1 = min(n, k0 + 64);
+    const int64_t k1 = min(n, k0 + COL_BAND);
+#pragma unroll 16
     for (int64_t k = k0; k < k1; ++k) mx = fmaxf(mx, fabsf(B[k * p + j]));
     atomicMax(&amax[j], __float_as_uint(mx));
 }
 
+// --------------------------------------------------- record conditioning --
+
+// Rows of A -> records. Chunk q = 16 codes of one record (4 per record);
+// consecutive threads fill one KiB record tile contiguously.
+template <bool TWO>
+__global__ __launch_bounds__(256) void pack_rows_fp8_kernel(const float *__restrict__ A, int64_t m,
+                                                            int64_t n, int64_t S, int vec,
+                                                            const int32_t *__restrict__ e,
+                                                            uint8_t *__restrict__ qa,
+                                                            uint8_t *__restrict__ la) {
+    const int64_t chunks = padded_rows(m) * S * 4;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < chunks; q += (int64_t)gridDim.x * 256) {
+        const int c = (int)(q & 3);
+        const int64_t rr = (q >> 2) % GROUP;
+        const int64_t gs = (q >> 2) / GROUP;
+        const int64_t s = gs % S, g = gs / S;
+        const int64_t r = g * GROUP + rr;
+        const int64_t k = s * SLAB8 + c * 16;
+        float x[16];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) x[t] = 0.0f;
+        if (r < m) {
+            const float *src = A + r * n + k;
+            if (vec && k + 16 <= n) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const float4 v = reinterpret_cast<const float4 *>(src)[u];
+                    x[4 * u] = v.x; x[4 * u + 1] = v.y; x[4 * u + 2] = v.z; x[4 * u + 3] = v.w;
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < 16; ++t)
+                    if (k + t < n) x[t] = src[t];
+            }
+            const int er = e[r];
+#pragma unroll
+            for (int t = 0; t < 16; ++t) x[t] = ldexpf(x[t], er);
+        }
+        uint32_t hi[4], lo[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+        for (int u = 0; u < 4; ++u) quant4(x + 4 * u, TWO, &hi[u], &lo[u]);
+        const int64_t at = ring::rec_byte(r, s, S) + c * 16;
+        *reinterpret_cast<uint4 *>(qa + at) = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+        if (TWO) *reinterpret_cast<uint4 *>(la + at) = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+    }
+}
+
+// Columns of B -> records (transposed). One thread per column j and slab s
+// reads the 64 values B[64s .. 64s+63][j] (a wave's loads of one row are 256
+// contiguous bytes) and writes the whole 64-byte record; a workgroup takes
+// 256 adjacent columns. Column exponents come from the column amax; the
+// workgroups of slab row blockIdx.y == 0 also store them. Columns past p get
+// zero records.
+template <bool TWO>
+__global__ __launch_bounds__(256) void pack_cols_fp8_kernel(const float *__restrict__ B, int64_t n,
+                                                            int64_t p, int64_t S,
+                                                            const uint32_t *__restrict__ amax,
+                                                            int32_t *__restrict__ f_out,
+                                                            uint8_t *__restrict__ qb,
+                                                            uint8_t *__restrict__ lb) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= padded_rows(p)) return;
+    const bool live = j < p;
+    const int fj = live ? pow2_exponent(__uint_as_float(amax[j])) : 0;
+    if (live && blockIdx.y == 0) f_out[j] = fj;
+    for (int64_t s = blockIdx.y; s < S; s += gridDim.y) {
+        const int64_t k0 = s * SLAB8;
+        float x[SLAB8];
+#pragma unroll
+        for (int t = 0; t < SLAB8; ++t) x[t] = (live && k0 + t < n) ? ldexpf(B[(k0 + t) * p + j], fj) : 0.0f;
+        uint32_t hi[16], lo[16] = {};
+#pragma unroll
+        for (int u = 0; u < 16; ++u) quant4(x + 4 * u, TWO, &hi[u], &lo[u]);
+        uint4 *dq = reinterpret_cast<uint4 *>(qb + ring::rec_byte(j, s, S));
+#pragma unroll
+        for (int c = 0; c < 4; ++c) dq[c] = make_uint4(hi[4 * c], hi[4 * c + 1], hi[4 * c + 2], hi[4 * c + 3]);
+        if (TWO) {
+            uint4 *dl = reinterpret_cast<uint4 *>(lb + ring::rec_byte(j, s, S));
+#pragma unroll
+            for (int c = 0; c < 4; ++c) dl[c] = make_uint4(lo[4 * c], lo[4 * c + 1], lo[4 * c + 2], lo[4 * c + 3]);
+        }
+    }
+}
+
+// ------------------------------------------- row-major codes (exposed API) --
+
 // qA (row-major, like A): 4 consecutive elements per thread.
 __global__ __launch_bounds__(256) void quant_rows_kernel(const float *__restrict__ A, int64_t m,
-                                                         int64_t n, const uint32_t *__restrict__ amax,
-                                                         int two_term, int32_t *__restrict__ e_out,
-                                                         uint8_t *__restrict__ q,
+                                                         int64_t n, const int32_t *__restrict__ e,
+                                                         int two_term, uint8_t *__restrict__ q,
                                                          uint8_t *__restrict__ l) {
     const int64_t i = blockIdx.x;
     const int64_t k = ((int64_t)blockIdx.y * 256 + threadIdx.x) * 4;
-    const int e = pow2_exponent(__uint_as_float(amax[i]));
-    if (blockIdx.y == 0 && threadIdx.x == 0 && e_out) e_out[i] = e;
     if (k >= n) return;
+    const int ei = e[i];
     float v[4];
 #pragma unroll
-    for (int t = 0; t < 4; ++t) v[t] = (k + t < n) ? ldexpf(A[i * n + k + t], e) : 0.0f;
+    for (int t = 0; t < 4; ++t) v[t] = (k + t < n) ? ldexpf(A[i * n + k + t], ei) : 0.0f;
     uint32_t hi, lo = 0;
     quant4(v, two_term != 0, &hi, &lo);
-    uint8_t *qd = q + i * n + k;
-    uint8_t *ld = l ? l + i * n + k : nullptr;
 #pragma unroll
     for (int t = 0; t < 4; ++t)
         if (k + t < n) {
-            qd[t] = (uint8_t)(hi >> (8 * t));
-            if (two_term) ld[t] = (uint8_t)(lo >> (8 * t));
+            q[i * n + k + t] = (uint8_t)(hi >> (8 * t));
+            if (two_term) l[i * n + k + t] = (uint8_t)(lo >> (8 * t));
         }
 }
 
-// qB for B (n x p). transposed == 0: row-major n x p like B (the exposed
-// conditioning call). transposed != 0: p x n, k-contiguous per column (the
-// GEMM operand). A 64 x 64 block per workgroup goes through LDS so that both
-// the reads of B rows and the writes of the transposed rows are contiguous.
+// qB (row-major, like B): 4 consecutive columns x 4 rows per thread.
 __global__ __launch_bounds__(256) void quant_cols_kernel(const float *__restrict__ B, int64_t n,
                                                          int64_t p, const uint32_t *__restrict__ amax,
-                                                         int two_term, int transposed,
-                                                         int32_t *__restrict__ f_out,
+                                                         int two_term, int32_t *__restrict__ f_out,
                                                          uint8_t *__restrict__ q,
                                                          uint8_t *__restrict__ l) {
-    __shared__ uint8_t tq[64][64 + 4];
-    __shared__ uint8_t tl[64][64 + 4];
     const int64_t k0 = (int64_t)blockIdx.y * 64, jb = (int64_t)blockIdx.x * 64;
     const int tx = threadIdx.x & 15;      // 4 columns each
     const int ty = threadIdx.x >> 4;      // 16 rows, 4 passes
@@ -135,266 +239,184 @@ __global__ __launch_bounds__(256) void quant_cols_kernel(const float *__restrict
 #pragma unroll
     for (int t = 0; t < 4; ++t) {
         f[t] = (j + t < p) ? pow2_exponent(__uint_as_float(amax[j + t])) : 0;
-        if (f_out && blockIdx.y == 0 && ty == 0 && j + t < p) f_out[j + t] = f[t];
+        if (blockIdx.y == 0 && ty == 0 && j + t < p) f_out[j + t] = f[t];
     }
 #pragma unroll
     for (int pass = 0; pass < 4; ++pass) {
-        const int kk = ty + 16 * pass;
-        const int64_t k = k0 + kk;
+        const int64_t k = k0 + ty + 16 * pass;
+        if (k >= n) continue;
         float v[4];
 #pragma unroll
-        for (int t = 0; t < 4; ++t)
-            v[t] = (k < n && j + t < p) ? ldexpf(B[k * p + j + t], f[t]) : 0.0f;
+        for (int t = 0; t < 4; ++t) v[t] = (j + t < p) ? ldexpf(B[k * p + j + t], f[t]) : 0.0f;
         uint32_t hi, lo = 0;
         quant4(v, two_term != 0, &hi, &lo);
-        if (!transposed) {
-            if (k < n) {
 #pragma unroll
-                for (int t = 0; t < 4; ++t)
-                    if (j + t < p) {
-                        q[k * p + j + t] = (uint8_t)(hi >> (8 * t));
-                        if (two_term) l[k * p + j + t] = (uint8_t)(lo >> (8 * t));
-                    }
+        for (int t = 0; t < 4; ++t)
+            if (j + t < p) {
+                q[k * p + j + t] = (uint8_t)(hi >> (8 * t));
+                if (two_term) l[k * p + j + t] = (uint8_t)(lo >> (8 * t));
             }
-        } else {
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                tq[tx * 4 + t][kk] = (uint8_t)(hi >> (8 * t));
-                tl[tx * 4 + t][kk] = (uint8_t)(lo >> (8 * t));
-            }
-        }
-    }
-    if (!transposed) return;
-    __syncthreads();
-    // write 64 columns x 64 k: thread -> (column jj, 16-byte run of k)
-    const int jj = threadIdx.x >> 2, run = (threadIdx.x & 3) * 16;
-    const int64_t jo = jb + jj;
-    if (jo >= p) return;
-    for (int b = 0; b < 16; ++b) {
-        const int64_t k = k0 + run + b;
-        if (k < n) {
-            q[jo * n + k] = tq[jj][run + b];
-            if (two_term) l[jo * n + k] = tl[jj][run + b];
-        }
     }
 }
 
-// ---------------------------------------------------------------- GEMM ----
-// 32 consecutive E4M3 codes of one fragment row from LDS (16-byte aligned).
-__device__ __forceinline__ i32x8_t frag32(const uint8_t *p) {
-    const uint4 lo = *reinterpret_cast<const uint4 *>(p);
-    const uint4 hi = *reinterpret_cast<const uint4 *>(p + 16);
-    i32x8_t v;
-    v[0] = (int)lo.x; v[1] = (int)lo.y; v[2] = (int)lo.z; v[3] = (int)lo.w;
-    v[4] = (int)hi.x; v[5] = (int)hi.y; v[6] = (int)hi.z; v[7] = (int)hi.w;
-    return v;
-}
+// ---------------------------------------------------------- contraction --
 
-constexpr int BK8 = 128;                 // k per slab (bytes of E4M3)
-// E8M0 block scale 2^(127-127) = 1 for both operands of the scaled
-// matrix-core step (0 would mean 2^-127).
-constexpr int kScaleOne = 0x7f;
-constexpr int BM = 128, BN = 128, WM = 64, WN = 64;
-
-template <bool TWO>
-__global__ __launch_bounds__(256) void fp8_gemm_kernel(
-    const uint8_t *__restrict__ qA, const uint8_t *__restrict__ lA, const int32_t *__restrict__ e,
-    const uint8_t *__restrict__ qBt, const uint8_t *__restrict__ lBt, const int32_t *__restrict__ f,
-    float *__restrict__ C, int64_t m, int64_t n, int64_t p, int accumulate, int tiles_m,
-    int tiles_n, int vec) {
-    // LDS row: [hi: 128 codes][lo: 128 codes, two-term only][16-byte pad]
-    constexpr int ROWB = (TWO ? 2 * BK8 : BK8) + 16;
-    constexpr int FM = WM / 32, FN = WN / 32, WAVES_N = BN / WN;
-    constexpr int CHUNKS = (BM + BN) * (BK8 / 16);   // 16-byte chunks per plane
-    constexpr int CPT = CHUNKS / 256;
-    __shared__ __attribute__((aligned(16))) uint8_t lds[2][(BM + BN) * ROWB];
-
-    const int t = threadIdx.x, lane = t & 63, wave = t >> 6;
-    const int wm = wave / WAVES_N, wn = wave % WAVES_N;
-    int tm, tn;
-    tile_coords(xcd_remap(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, &tm, &tn);
-    const int64_t i0 = (int64_t)tm * BM, j0 = (int64_t)tn * BN;
-
-    uint4 rh[CPT], rl[TWO ? CPT : 1];
-    auto load = [&](int64_t k0) {
-#pragma unroll
-        for (int s = 0; s < CPT; ++s) {
-            const int cid = t + 256 * s;
-            const int row = cid % (BM + BN), kc = cid / (BM + BN);
-            const bool is_a = row < BM;
-            const int64_t r = is_a ? i0 + row : j0 + (row - BM);
-            const int64_t lim = is_a ? m : p;
-            const uint8_t *src = is_a ? qA : qBt;
-            const uint8_t *srcl = is_a ? lA : lBt;
-            const int64_t k = k0 + kc * 16;
-            uint4 h = make_uint4(0, 0, 0, 0), lo = make_uint4(0, 0, 0, 0);
-            if (r < lim) {
-                if (vec && k + 16 <= n) {
-                    h = *reinterpret_cast<const uint4 *>(src + r * n + k);
-                    if (TWO) lo = *reinterpret_cast<const uint4 *>(srcl + r * n + k);
-                } else {
-                    uint8_t *hb = reinterpret_cast<uint8_t *>(&h);
-                    uint8_t *lb = reinterpret_cast<uint8_t *>(&lo);
-                    for (int b = 0; b < 16; ++b)
-                        if (k + b < n) {
-                            hb[b] = src[r * n + k + b];
-                            if (TWO) lb[b] = srcl[r * n + k + b];
-                        }
-                }
-            }
-            rh[s] = h;
-            if (TWO) rl[s] = lo;
-        }
-    };
-    auto store = [&](int buf) {
-#pragma unroll
-        for (int s = 0; s < CPT; ++s) {
-            const int cid = t + 256 * s;
-            const int row = cid % (BM + BN), kc = cid / (BM + BN);
-            *reinterpret_cast<uint4 *>(&lds[buf][row * ROWB + kc * 16]) = rh[s];
-            if (TWO) *reinterpret_cast<uint4 *>(&lds[buf][row * ROWB + BK8 + kc * 16]) = rl[s];
-        }
+// Fragments of 32 records x 32 codes: lane l reads row base + l%32, logical
+// chunks 2(l/32) and 2(l/32) + 1 (k = 32(l/32) .. +31 of the slab); A and B
+// use the same k assignment, which is all the step's dot product needs.
+template <bool TWO> struct Fp8Mode {
+    static constexpr bool SCALED = true;
+    template <int FM, int FN> struct Frags {
+        i32x8_t ah[FM], bh[FN], al[TWO ? FM : 1], bl[TWO ? FN : 1];
     };
 
-    f32x16_t acc[FM][FN], acx[TWO ? FM : 1][TWO ? FN : 1];
-#pragma unroll
-    for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int b = 0; b < FN; ++b)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
-    if (TWO) {
-#pragma unroll
-        for (int a = 0; a < (TWO ? FM : 1); ++a)
-#pragma unroll
-            for (int b = 0; b < (TWO ? FN : 1); ++b)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) acx[a][b][r] = 0.0f;
+    static __device__ __forceinline__ i32x8_t frag(const uint8_t *buf, int row, int half) {
+        const i32x4_t x = ring::lds_chunk<i32x4_t>(buf, row, 2 * half);
+        const i32x4_t y = ring::lds_chunk<i32x4_t>(buf, row, 2 * half + 1);
+        return __builtin_shufflevector(x, y, 0, 1, 2, 3, 4, 5, 6, 7);
     }
 
-    const int64_t nslabs = (n + BK8 - 1) / BK8;
-    if (nslabs > 0) {
-        load(0);
-        store(0);
-        __syncthreads();
+    // LDS rows: [A hi (BM)][A lo (BM)][B hi (BN)][B lo (BN)] (lo: two-term only)
+    template <int BM, int BN, int FM, int FN>
+    static __device__ __forceinline__ void read(const uint8_t *buf, int a_row, int b_row, int half,
+                                                Frags<FM, FN> &f) {
+#pragma unroll
+        for (int a = 0; a < FM; ++a) {
+            f.ah[a] = frag(buf, a_row + a * 32, half);
+            if constexpr (TWO) f.al[a] = frag(buf, a_row + BM + a * 32, half);
+        }
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+            f.bh[b] = frag(buf, b_row + b * 32, half);
+            if constexpr (TWO) f.bl[b] = frag(buf, b_row + BN + b * 32, half);
+        }
     }
-    const int frag_row = lane & 31, frag_k = (lane >> 5) * 32;
-    for (int64_t s = 0; s < nslabs; ++s) {
-        const int buf = (int)(s & 1);
-        if (s + 1 < nslabs) load((s + 1) * BK8);
-        const uint8_t *la = &lds[buf][(wm * WM + frag_row) * ROWB + frag_k];
-        const uint8_t *lb = &lds[buf][(BM + wn * WN + frag_row) * ROWB + frag_k];
-#pragma unroll
-        for (int ks = 0; ks < BK8; ks += 64) {
-            i32x8_t ah[FM], bh[FN], al[TWO ? FM : 1], bl[TWO ? FN : 1];
-#pragma unroll
-            for (int a = 0; a < FM; ++a) {
-                ah[a] = frag32(la + a * 32 * ROWB + ks);
-                if (TWO) al[a] = frag32(la + a * 32 * ROWB + BK8 + ks);
-            }
-#pragma unroll
-            for (int b = 0; b < FN; ++b) {
-                bh[b] = frag32(lb + b * 32 * ROWB + ks);
-                if (TWO) bl[b] = frag32(lb + b * 32 * ROWB + BK8 + ks);
-            }
+
+    // every element sees, per slab in ascending order: 2^-4 lA.qB, 2^-4 qA.lB
+    // (two-term only), then qA.qB
+    template <int FM, int FN>
+    static __device__ __forceinline__ void mma(const Frags<FM, FN> &f, f32x16_t (&acc)[FM][FN]) {
+        if constexpr (TWO) {
 #pragma unroll
             for (int a = 0; a < FM; ++a)
 #pragma unroll
-                for (int b = 0; b < FN; ++b) {
+                for (int b = 0; b < FN; ++b)
                     acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                        ah[a], bh[b], acc[a][b], 0, 0, 0, kScaleOne, 0, kScaleOne);
-                    if (TWO) {
-                        acx[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                            ah[a], bl[b], acx[a][b], 0, 0, 0, kScaleOne, 0, kScaleOne);
-                        acx[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
-                            al[a], bh[b], acx[a][b], 0, 0, 0, kScaleOne, 0, kScaleOne);
-                    }
-                }
+                        f.al[a], f.bh[b], acc[a][b], 0, 0, 0, kScaleLo, 0, kScaleOne);
+#pragma unroll
+            for (int a = 0; a < FM; ++a)
+#pragma unroll
+                for (int b = 0; b < FN; ++b)
+                    acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                        f.ah[a], f.bl[b], acc[a][b], 0, 0, 0, kScaleOne, 0, kScaleLo);
         }
-        if (s + 1 < nslabs) store(buf ^ 1);
-        __syncthreads();
+#pragma unroll
+        for (int a = 0; a < FM; ++a)
+#pragma unroll
+            for (int b = 0; b < FN; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_scale_f32_32x32x64_f8f6f4(
+                    f.ah[a], f.bh[b], acc[a][b], 0, 0, 0, kScaleOne, 0, kScaleOne);
     }
+};
 
-#pragma unroll
-    for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int b = 0; b < FN; ++b) {
-            const int64_t j = j0 + wn * WN + b * 32 + (lane & 31);
-            if (j >= p) continue;
-            const int fj = f[j];
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t i = i0 + wm * WM + a * 32 + mfma32_row(r, lane);
-                if (i < m) {
-                    float v = acc[a][b][r];
-                    if (TWO) v += ldexpf(acx[a][b][r], -4);
-                    v = ldexpf(v, -(e[i] + fj));
-                    if (accumulate) v += C[i * p + j];
-                    C[i * p + j] = v;
-                }
-            }
-        }
+struct Fp8Shape { int bm, bn, wm, wn; };
+constexpr Fp8Shape kOne[] = {{128, 128, 64, 64}, {256, 256, 128, 64}};
+constexpr Fp8Shape kTwo[] = {{128, 128, 64, 64}, {128, 128, 64, 32}};
+constexpr int kOneCount = sizeof(kOne) / sizeof(kOne[0]);
+constexpr int kTwoCount = sizeof(kTwo) / sizeof(kTwo[0]);
+
+template <int BM, int BN, int WM, int WN, bool TWO>
+hipError_t launch_shape(const ring::Operands &op, hipStream_t st) {
+    constexpr int NREC = TWO ? 2 : 1;
+    const int tiles_m = (int)((op.m + BM - 1) / BM);
+    const int tiles_n = (int)((op.p + BN - 1) / BN);
+    hipLaunchKernelGGL((ring::single_kernel<BM, BN, WM, WN, NREC, Fp8Mode<TWO>>), dim3(tiles_m * tiles_n),
+                       dim3(ring::Cfg<BM, BN, WM, WN, NREC>::THREADS), 0, st, op, tiles_m, tiles_n);
+    return hipGetLastError();
 }
 
 int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
 struct Fp8Workspace {
-    uint32_t *amaxA, *amaxB;
+    uint32_t *amaxB;
     int32_t *e, *f;
-    uint8_t *qA, *lA, *qBt, *lBt;
+    uint8_t *qA, *lA, *qB, *lB;
 };
 
 Fp8Workspace carve(void *ws, int64_t m, int64_t n, int64_t p, bool two) {
+    const int64_t S = (n + SLAB8 - 1) / SLAB8;
     char *c = static_cast<char *>(ws);
     Fp8Workspace w;
-    w.amaxA = reinterpret_cast<uint32_t *>(c); c += align256(4 * m);
     w.amaxB = reinterpret_cast<uint32_t *>(c); c += align256(4 * p);
     w.e = reinterpret_cast<int32_t *>(c); c += align256(4 * m);
     w.f = reinterpret_cast<int32_t *>(c); c += align256(4 * p);
-    w.qA = reinterpret_cast<uint8_t *>(c); c += align256(m * n);
-    w.qBt = reinterpret_cast<uint8_t *>(c); c += align256(n * p);
-    w.lA = two ? reinterpret_cast<uint8_t *>(c) : nullptr; c += two ? align256(m * n) : 0;
-    w.lBt = two ? reinterpret_cast<uint8_t *>(c) : nullptr;
+    w.qA = reinterpret_cast<uint8_t *>(c); c += align256(ring::array_bytes(m, S));
+    w.qB = reinterpret_cast<uint8_t *>(c); c += align256(ring::array_bytes(p, S));
+    w.lA = two ? reinterpret_cast<uint8_t *>(c) : nullptr; c += two ? align256(ring::array_bytes(m, S)) : 0;
+    w.lB = two ? reinterpret_cast<uint8_t *>(c) : nullptr;
     return w;
 }
 
-hipError_t conditioning(const float *A, int64_t m, int64_t n, const float *B, int64_t p, bool two,
-                        uint32_t *amaxA, uint32_t *amaxB, int32_t *e, uint8_t *qA, uint8_t *lA,
-                        int32_t *f, uint8_t *qB, uint8_t *lB, bool transposed, hipStream_t st) {
-    if (m > 0) hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, st, amaxA, m);
+// Exponents of A's rows and amax of B's columns (shared by both layouts).
+void scales(const float *A, int64_t m, int64_t n, const float *B, int64_t p, int32_t *e, uint32_t *amaxB,
+            hipStream_t st) {
     if (p > 0) hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((p + 255) / 256)), dim3(256), 0, st, amaxB, p);
-    if (m > 0 && n > 0)
-        hipLaunchKernelGGL(row_amax_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, A, m, n, amaxA);
+    const int vec = (n % 4 == 0) && ((uintptr_t)A % 16 == 0);
+    if (m > 0) hipLaunchKernelGGL(row_exp_kernel, dim3((unsigned)((m + 3) / 4)), dim3(256), 0, st, A, m, n, vec, e);
     if (p > 0 && n > 0)
-        hipLaunchKernelGGL(col_amax_kernel, dim3((unsigned)((p + 255) / 256), (unsigned)((n + 63) / 64)),
+        hipLaunchKernelGGL(col_amax_kernel, dim3((unsigned)((p + 255) / 256), (unsigned)((n + COL_BAND - 1) / COL_BAND)),
                            dim3(256), 0, st, B, n, p, amaxB);
-    if (m > 0)
-        hipLaunchKernelGGL(quant_rows_kernel, dim3((unsigned)m, (unsigned)((n + 1023) / 1024 > 0 ? (n + 1023) / 1024 : 1)),
-                           dim3(256), 0, st, A, m, n, amaxA, (int)two, e, qA, lA);
-    if (p > 0)
-        hipLaunchKernelGGL(quant_cols_kernel, dim3((unsigned)((p + 63) / 64), (unsigned)((n + 63) / 64 > 0 ? (n + 63) / 64 : 1)),
-                           dim3(256), 0, st, B, n, p, amaxB, (int)two, (int)transposed, f, qB, lB);
+}
+
+hipError_t pack_records(const moa_gemm_desc &d, bool two, const Fp8Workspace &w, hipStream_t st) {
+    const float *A = static_cast<const float *>(d.A);
+    const float *B = static_cast<const float *>(d.B);
+    const int64_t S = (d.n + SLAB8 - 1) / SLAB8;
+    scales(A, d.m, d.n, B, d.p, w.e, w.amaxB, st);
+    if (d.m > 0 && S > 0) {
+        const int vec = (d.n % 4 == 0) && ((uintptr_t)A % 16 == 0);
+        int64_t blocks = (padded_rows(d.m) * S * 4 + 255) / 256;
+        if (blocks > 65536) blocks = 65536;
+        if (two)
+            hipLaunchKernelGGL(pack_rows_fp8_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, st, A, d.m, d.n, S,
+                               vec, w.e, w.qA, w.lA);
+        else
+            hipLaunchKernelGGL(pack_rows_fp8_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, st, A, d.m, d.n, S,
+                               vec, w.e, w.qA, w.lA);
+    }
+    if (d.p > 0) {   // also when S == 0: the epilogue reads the column exponents
+        const dim3 grid((unsigned)((padded_rows(d.p) + 255) / 256), (unsigned)(S < 1 ? 1 : S > 65535 ? 65535 : S));
+        if (two)
+            hipLaunchKernelGGL(pack_cols_fp8_kernel<true>, grid, dim3(256), 0, st, B, d.n, d.p, S, w.amaxB, w.f,
+                               w.qB, w.lB);
+        else
+            hipLaunchKernelGGL(pack_cols_fp8_kernel<false>, grid, dim3(256), 0, st, B, d.n, d.p, S, w.amaxB, w.f,
+                               w.qB, w.lB);
+    }
     return hipGetLastError();
 }
 
 }  // namespace
 
-void fp8_shape(bool two, Plan *p) {
-    p->variant = two ? 1 : 0;
-    p->tile_m = BM;
-    p->tile_n = BN;
-    p->tile_k = BK8;
-    p->wave_m = WM;
-    p->wave_n = WN;
+int fp8_variant_count(bool two) { return two ? kTwoCount : kOneCount; }
+
+void fp8_shape(bool two, int v, Plan *p) {
+    const Fp8Shape s = two ? kTwo[v] : kOne[v];
+    p->variant = v;
+    p->tile_m = s.bm;
+    p->tile_n = s.bn;
+    p->tile_k = SLAB8;
+    p->wave_m = s.wm;
+    p->wave_n = s.wn;
     p->lane_m = p->lane_n = 0;
-    p->threads = 256;
-    p->lds_bytes = 2 * (BM + BN) * ((two ? 2 * BK8 : BK8) + 16);
+    p->threads = (s.bm / s.wm) * (s.bn / s.wn) * 64;
+    p->lds_bytes = ring::NSTAGE * (two ? 2 : 1) * (s.bm + s.bn) * REC_BYTES;
 }
 
 int64_t fp8_workspace_bytes(int64_t m, int64_t n, int64_t p, bool two) {
-    int64_t b = align256(4 * m) * 2 + align256(4 * p) * 2 + align256(m * n) + align256(n * p);
-    if (two) b += align256(m * n) + align256(n * p);
-    return b;
+    const int64_t S = (n + SLAB8 - 1) / SLAB8;
+    const int64_t rec = align256(ring::array_bytes(m, S)) + align256(ring::array_bytes(p, S));
+    return align256(4 * p) * 2 + align256(4 * m) + (two ? 2 : 1) * rec;
 }
 
 hipError_t launch_fp8(const moa_gemm_desc &d, const Plan &plan, void *ws, hipStream_t st) {
@@ -403,28 +425,43 @@ hipError_t launch_fp8(const moa_gemm_desc &d, const Plan &plan, void *ws, hipStr
     hipError_t err;
     {
         TraceScope ts(MOA_K_FP8_QUANT, st);
-        err = conditioning(static_cast<const float *>(d.A), d.m, d.n, static_cast<const float *>(d.B),
-                           d.p, two, w.amaxA, w.amaxB, w.e, w.qA, w.lA, w.f, w.qBt, w.lBt, true, st);
+        err = pack_records(d, two, w, st);
     }
     if (err != hipSuccess) return err;
     TraceScope ts(two ? MOA_K_FP8_2TERM : MOA_K_FP8, st);
-    const int tiles_m = (int)((d.m + BM - 1) / BM), tiles_n = (int)((d.p + BN - 1) / BN);
-    const int vec = (d.n % 16 == 0);
-    float *C = static_cast<float *>(d.C);
-    if (two)
-        hipLaunchKernelGGL(fp8_gemm_kernel<true>, dim3(tiles_m * tiles_n), dim3(256), 0, st, w.qA, w.lA,
-                           w.e, w.qBt, w.lBt, w.f, C, d.m, d.n, d.p, d.accumulate, tiles_m, tiles_n, vec);
-    else
-        hipLaunchKernelGGL(fp8_gemm_kernel<false>, dim3(tiles_m * tiles_n), dim3(256), 0, st, w.qA, w.lA,
-                           w.e, w.qBt, w.lBt, w.f, C, d.m, d.n, d.p, d.accumulate, tiles_m, tiles_n, vec);
-    (void)plan;
-    return hipGetLastError();
+    ring::Operands op;
+    op.a0 = w.qA; op.a1 = w.lA;
+    op.b0 = w.qB; op.b1 = w.lB;
+    op.C = static_cast<float *>(d.C);
+    op.row_exp = w.e;
+    op.col_exp = w.f;
+    op.m = d.m; op.p = d.p;
+    op.S = (d.n + SLAB8 - 1) / SLAB8;
+    op.accumulate = d.accumulate;
+    if (two) {
+        switch (plan.variant) {
+        case 0: return launch_shape<128, 128, 64, 64, true>(op, st);
+        default: return launch_shape<128, 128, 64, 32, true>(op, st);
+        }
+    }
+    switch (plan.variant) {
+    case 0: return launch_shape<128, 128, 64, 64, false>(op, st);
+    default: return launch_shape<256, 256, 128, 64, false>(op, st);
+    }
 }
 
 hipError_t launch_quantise_fp8(const float *A, int64_t m, int64_t n, const float *B, int64_t p,
                                bool two, int32_t *e, uint8_t *qA, uint8_t *lA, int32_t *f,
                                uint8_t *qB, uint8_t *lB, uint32_t *amax, hipStream_t st) {
-    return conditioning(A, m, n, B, p, two, amax, amax + m, e, qA, lA, f, qB, lB, false, st);
+    uint32_t *amaxB = amax + m;
+    scales(A, m, n, B, p, e, amaxB, st);
+    if (m > 0 && n > 0)
+        hipLaunchKernelGGL(quant_rows_kernel, dim3((unsigned)m, (unsigned)((n + 1023) / 1024)), dim3(256), 0, st, A,
+                           m, n, e, (int)two, qA, lA);
+    if (p > 0)
+        hipLaunchKernelGGL(quant_cols_kernel, dim3((unsigned)((p + 63) / 64), (unsigned)((n + 63) / 64 > 0 ? (n + 63) / 64 : 1)),
+                           dim3(256), 0, st, B, n, p, amaxB, (int)two, f, qB, lB);
+    return hipGetLastError();
 }
 
 }  // namespace moa

@@ -117,7 +117,8 @@ hipError_t split_grouped_enqueue(void *workspace, int count, int64_t tiles, hipS
 
 hipError_t launch_fp8(const moa_gemm_desc &d, const Plan &plan, void *workspace,
                       hipStream_t stream);
-void fp8_shape(bool two_term, Plan *p);
+void fp8_shape(bool two_term, int variant, Plan *p);
+int fp8_variant_count(bool two_term);
 int64_t fp8_workspace_bytes(int64_t m, int64_t n, int64_t p, bool two_term);
 
 hipError_t launch_split_only(const float *X, int64_t count, uint16_t *hi, uint16_t *lo,

@@ -56,6 +56,7 @@ int variant_count(const moa_gemm_desc &d, moa_path path) {
     switch (path) {
     case MOA_PATH_ONF: return onf_variant_count((moa_dtype)d.dtype);
     case MOA_PATH_SPLIT_BF16: return split_bf16_variant_count();
+    case MOA_PATH_FP8_SCALED: return fp8_variant_count((d.flags & MOA_FLAG_FP8_TWO_TERM) != 0);
     default: return 1;
     }
 }
@@ -88,6 +89,7 @@ moa_status autotune_load(const char *path) {
         }
         moa_gemm_desc probe{};
         probe.dtype = k[0];
+        probe.flags = k[2] == 2 ? MOA_FLAG_FP8_TWO_TERM : 0;
         if (k[1] < MOA_PATH_ONF || k[1] > MOA_PATH_FP8_SCALED || (k[0] != MOA_F64 && k[0] != MOA_F32) ||
             t.variant < 0 || t.variant >= variant_count(probe, (moa_path)k[1])) {
             std::fclose(f);
@@ -186,9 +188,27 @@ moa_status make_plan(const moa_gemm_desc &d, Plan *out) {
     case MOA_PATH_FP8_SCALED: {
         const bool two = (d.flags & MOA_FLAG_FP8_TWO_TERM) != 0;
         pl.kernel = two ? K_FP8_2TERM : K_FP8;
-        if (forced > 0) return fail(MOA_ERR_INVALID, "variant %d out of range (FP8 has 1)", forced);
-        fp8_shape(two, &pl);
+        const int nv = fp8_variant_count(two);
+        int v = 0;
+        if (forced >= 0) {
+            if (forced >= nv) return fail(MOA_ERR_INVALID, "variant %d out of range (FP8 has %d)", forced, nv);
+            v = forced;
+        } else if ((v = tuned_variant(d, pl.path)) >= 0) {
+            pl.tuned = true;
+        } else {
+            v = 0;
+            for (int c = nv - 1; c >= 0; --c) {
+                Plan t;
+                fp8_shape(two, c, &t);
+                if (tiles_for(d.m, d.p, t.tile_m, t.tile_n) >= kNumCUs) { v = c; break; }
+            }
+        }
+        fp8_shape(two, v, &pl);
         pl.workspace_bytes = fp8_workspace_bytes(d.m, d.n, d.p, two);
+        // 256 record rows of (n/64) 64-byte records must stay below 2^31 bytes
+        // (32-bit buffer offsets of one tile).
+        if ((d.n + 63) / 64 > 131071)
+            return fail(MOA_ERR_SHAPE, "n = %lld exceeds the FP8 offset range", (long long)d.n);
         break;
     }
     default:

@@ -1,0 +1,244 @@
+// Blocked matrix-core contraction over conditioned "record tiles", shared by
+// the split-BF16 and scaled-FP8 paths.
+//
+// Conditioned operands: for every row i of A and every column j of B, the k
+// extent is cut into slabs (the sigma loop broken into blocks, section
+// "Dimension Lifting to Machine Coordinates" of the paper) and slab s of that
+// row becomes one 64-byte record. Records are stored in tiles of 16 rows x 1
+// slab: record (r, s) lives at byte ((r / 16) * S + s) * 1024 + (r mod 16) * 64,
+// so 16 records are one contiguous KiB of whole cache lines. Row counts are
+// padded to a multiple of 16 with zero records. A path may keep NREC record
+// arrays per operand (e.g. a high and a low term).
+//
+// Contraction (Fig. 2 blocking): a workgroup owns a BM x BN block of C and
+// walks the S slabs; per slab the NREC*(BM+BN) records go straight from HBM
+// into LDS (buffer_load ... lds, no register staging) through a ring of
+// NSTAGE buffers, and the slab's block products are summed in registers (the
+// "addition loop" over blocks). The fragments of slab t+1 are read from LDS
+// while the matrix-core steps of slab t issue.
+//
+// LDS holds one 64-byte row per record. gfx950's LDS serves a 16-byte read for
+// 16 lanes per cycle out of a 256-byte window (64 banks), i.e. four
+// consecutive rows at once: chunk c of row r is stored at chunk position
+// c ^ ((r / 4) mod 4), so the 16 rows of a read cycle hit 16 distinct bank
+// groups. The direct loads stay linear (lane L writes bytes 16L .. 16L+15 of
+// its wave's KiB window = 16 rows), so each lane fetches the logical chunk
+// that belongs at its physical position.
+#pragma once
+
+#include "moa_internal.h"
+#include "tile_common.h"
+
+namespace moa {
+namespace ring {
+
+constexpr int REC_BYTES = 64;             // bytes per record
+constexpr int GROUP = 16;                 // rows per record tile
+constexpr int NSTAGE = 3;                 // LDS ring depth (3 measured faster than 4 or 5)
+
+__host__ __device__ inline int64_t padded_rows(int64_t rows) { return (rows + GROUP - 1) / GROUP * GROUP; }
+
+// byte offset of record (r, s) in a record array with S slabs per row
+__host__ __device__ inline int64_t rec_byte(int64_t r, int64_t s, int64_t S) {
+    return ((r / GROUP) * S + s) * (GROUP * REC_BYTES) + (r % GROUP) * REC_BYTES;
+}
+
+// bytes of one record array for `rows` rows and S slabs
+__host__ __device__ inline int64_t array_bytes(int64_t rows, int64_t S) { return padded_rows(rows) * S * REC_BYTES; }
+
+typedef __attribute__((address_space(3))) void lds_void_t;
+typedef __attribute__((address_space(1))) float global_f32;
+typedef __attribute__((address_space(1))) const int32_t global_i32;
+
+// gfx9 s_waitcnt immediate: at most n vector-memory operations of this wave
+// outstanding (expcnt and lgkmcnt not waited on).
+constexpr int waitcnt_vm(int n) { return (n & 0xF) | (((n >> 4) & 3) << 14) | (0x7 << 4) | (0xF << 8); }
+
+// Workgroup barrier without the release fence of __syncthreads(): that fence
+// would also wait for the direct loads still in flight for later slabs. Each
+// wave first waits (s_waitcnt) for its own loads of the slab it is about to
+// read; LDS reads are complete before their values are used. The "memory"
+// clobber keeps the compiler from moving LDS accesses across the barrier.
+__device__ __forceinline__ void ring_barrier() { asm volatile("s_barrier" ::: "memory"); }
+
+template <int BM, int BN, int WM, int WN, int NREC> struct Cfg {
+    static constexpr int WAVES_M = BM / WM, WAVES_N = BN / WN, NW = WAVES_M * WAVES_N;
+    static constexpr int THREADS = NW * 64;
+    static constexpr int FM = WM / 32, FN = WN / 32;
+    static constexpr int ROWS = NREC * (BM + BN);         // records per slab
+    static constexpr int STAGE = ROWS * REC_BYTES;        // bytes per LDS buffer
+    static constexpr int LDS = NSTAGE * STAGE;
+    static constexpr int LPW = ROWS / 16 / NW;            // KiB direct loads per wave per slab
+    static_assert(ROWS % (16 * NW) == 0, "whole loads per wave");
+    static_assert(BM % (16 * LPW) == 0 && BN % (16 * LPW) == 0, "a wave loads rows of one array");
+};
+
+// The conditioned operands of one product.
+struct Operands {
+    const uint8_t *a0, *a1;               // record arrays of A (a1 only when NREC == 2)
+    const uint8_t *b0, *b1;               // record arrays of B
+    float *C;
+    const int32_t *row_exp;               // scaled modes: C[i][j] = 2^-(row_exp[i] + col_exp[j]) acc
+    const int32_t *col_exp;
+    int64_t m, p, S;
+    int accumulate;
+};
+
+// Fragment read of 16 bytes from LDS: logical chunk `chunk` of row `row`.
+template <class V>
+__device__ __forceinline__ V lds_chunk(const uint8_t *buf, int row, int chunk) {
+    static_assert(sizeof(V) == 16, "one 16-byte chunk");
+    return *reinterpret_cast<const V *>(buf + row * REC_BYTES + ((chunk ^ ((row >> 2) & 3)) << 4));
+}
+
+// One BM x BN block of C at (i0, j0). Mode supplies
+//   template <int FM, int FN> struct Frags         fragments of one slab
+//   template <int BM, int BN, int FM, int FN>
+//   static void read(buf, a_row, b_row, half, Frags &)   LDS -> registers
+//   template <int FM, int FN> static void mma(const Frags &, acc)
+//   static constexpr bool SCALED                   apply row/col exponents
+// and the LDS rows of a slab are [A array 0 (BM)] .. [A array NREC-1]
+// [B array 0 (BN)] .. [B array NREC-1].
+// `lds` is the workgroup's ring; on entry no wave may still be reading it, on
+// exit every wave has finished.
+template <int BM, int BN, int WM, int WN, int NREC, class Mode>
+__device__ __forceinline__ void tile(const Operands &op, int64_t i0, int64_t j0, uint8_t *lds) {
+    using G = Cfg<BM, BN, WM, WN, NREC>;
+    constexpr int WAVES_N = G::WAVES_N, FM = G::FM, FN = G::FN;
+    constexpr int STAGE = G::STAGE, LPW = G::LPW;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wm = wave / WAVES_N, wn = wave % WAVES_N;
+    const int S = (int)op.S;                 // the planner keeps S below 2^17
+
+    // LDS rows of a slab: [A array 0 (BM)] .. [A array NREC-1] [B array 0 (BN)] ..
+    // Wave w loads rows 16*LPW*w .. +16*LPW-1, all inside one array.
+    static_assert(NREC == 1 || NREC == 2, "one or two record arrays per operand");
+    const int64_t tile_row = S * GROUP * REC_BYTES;       // bytes per row tile (16 rows, all slabs)
+    const int row_first = wave * LPW * 16;
+    const bool loads_a = row_first < NREC * BM;
+    const int arr = NREC == 1 ? 0 : loads_a ? row_first / BM : (row_first - NREC * BM) / BN;
+    const int row_in = loads_a ? row_first - arr * BM : row_first - NREC * BM - arr * BN;
+    const int64_t org = loads_a ? i0 : j0;
+    const int64_t lim = loads_a ? op.m : op.p;
+    const int64_t tiles = min((int64_t)(loads_a ? BM : BN), padded_rows(lim) - org) / GROUP;
+    const uint8_t *base = loads_a ? (NREC == 1 || arr == 0 ? op.a0 : op.a1)
+                                  : (NREC == 1 || arr == 0 ? op.b0 : op.b1);
+    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(base + (org / GROUP) * tile_row), (short)0, (int)(tiles * tile_row), 0x00020000);
+    // lane L lands at row 16Q + L/4, physical chunk L%4, and fetches logical
+    // chunk (L%4) ^ ((row/4) mod 4) = (L%4) ^ (L/16). Records past m (or p)
+    // lie beyond the resource's range and load as zeros (their outputs are
+    // not stored).
+    const int voff = (lane >> 2) * REC_BYTES + (((lane & 3) ^ (lane >> 4)) << 4);
+    auto issue = [&](int s) {
+        uint8_t *buf = lds + (s % NSTAGE) * STAGE + row_first * REC_BYTES;
+#pragma unroll
+        for (int q = 0; q < LPW; ++q)
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                rsrc, (lds_void_t *)(buf + q * 16 * REC_BYTES), 16, voff,
+                (int)((row_in / GROUP + q) * tile_row) + s * GROUP * REC_BYTES, 0, 0);
+    };
+
+    const int frow = lane & 31, fhalf = lane >> 5;
+    typename Mode::template Frags<FM, FN> f0, f1;
+    auto read = [&](int s, typename Mode::template Frags<FM, FN> &f) {
+        const uint8_t *buf = lds + (s % NSTAGE) * STAGE;
+        Mode::template read<BM, BN, FM, FN>(buf, wm * WM + frow, NREC * BM + wn * WN + frow, fhalf, f);
+    };
+
+    f32x16_t acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = f32x16_t{};
+
+    // Wait until at most `stages` slabs of this wave's loads are in flight.
+    auto wait_loads = [&](int stages) {
+        switch (stages <= 0 ? 0 : stages >= 2 ? 2 : stages) {
+        case 0: __builtin_amdgcn_s_waitcnt(waitcnt_vm(0)); break;
+        case 1: __builtin_amdgcn_s_waitcnt(waitcnt_vm(LPW)); break;
+        default: __builtin_amdgcn_s_waitcnt(waitcnt_vm(2 * LPW)); break;
+        }
+    };
+    static_assert(NSTAGE >= 3 && NSTAGE <= 4, "wait_loads covers up to 2 slabs in flight");
+
+    // One step (slab t + 1 exists): make slab t+1 visible (its loads landed
+    // in every wave), refill the buffer slab t-1 used with slab t+NSTAGE-1,
+    // read slab t+1's fragments, then issue slab t's products. The read is
+    // unconditional so that the two fragment sets keep fixed registers.
+    auto step = [&](int t, const typename Mode::template Frags<FM, FN> &cur,
+                    typename Mode::template Frags<FM, FN> &next) {
+        // issued so far: slabs up to t + NSTAGE - 2; t + 1 must have landed
+        wait_loads(min(NSTAGE - 3, S - t - 2));
+        ring_barrier();
+        if (t + NSTAGE - 1 < S) issue(t + NSTAGE - 1);
+        read(t + 1, next);
+        Mode::template mma<FM, FN>(cur, acc);
+    };
+
+    if (S > 0) {
+        for (int q = 0; q < NSTAGE - 1; ++q)
+            if (q < S) issue(q);
+        wait_loads(min(NSTAGE - 2, S - 1));            // slab 0 has landed
+        ring_barrier();
+        read(0, f0);
+        int t = 0;
+        for (; t + 2 < S; t += 2) {
+            step(t, f0, f1);
+            step(t + 1, f1, f0);
+        }
+        if (t + 1 < S) {                               // two slabs left
+            step(t, f0, f1);
+            f0 = f1;
+        }
+        Mode::template mma<FM, FN>(f0, acc);           // the last slab
+    }
+
+    // Epilogue: register r of lane l holds C[8(r/4) + 4(l/32) + r%4][l%32] of
+    // each 32x32 block; 32 lanes write one 128-byte run of a row of C. C is
+    // addressed as global memory: a generic (flat) access could alias LDS and
+    // would have to wait for the direct loads still in flight.
+    global_f32 *C = (global_f32 *)op.C;
+    const global_i32 *row_exp = (const global_i32 *)op.row_exp;
+    const global_i32 *col_exp = (const global_i32 *)op.col_exp;
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+            const int64_t j = j0 + wn * WN + b * 32 + (lane & 31);
+            if (j >= op.p) continue;
+            const int fj = Mode::SCALED ? col_exp[j] : 0;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t i = i0 + wm * WM + a * 32 + mfma32_row(r, lane);
+                if (i < op.m) {
+                    float v = acc[a][b][r];
+                    if constexpr (Mode::SCALED) v = ldexpf(v, -(row_exp[i] + fj));
+                    if (op.accumulate) v += C[i * op.p + j];
+                    C[i * op.p + j] = v;
+                }
+            }
+        }
+}
+
+// Tile-id -> block mapping of a single-product launch (XCD-aware bands).
+__device__ __forceinline__ void block_of(int tiles_m, int tiles_n, int *tm, int *tn) {
+    tile_coords(xcd_remap(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, tm, tn);
+    // the integer divisions above run on the vector ALU; pin the (uniform)
+    // results to scalar registers so everything derived from them stays scalar
+    *tm = __builtin_amdgcn_readfirstlane(*tm);
+    *tn = __builtin_amdgcn_readfirstlane(*tn);
+}
+
+template <int BM, int BN, int WM, int WN, int NREC, class Mode>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void single_kernel(Operands op, int tiles_m,
+                                                                            int tiles_n) {
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[Cfg<BM, BN, WM, WN, NREC>::LDS];
+    int tm, tn;
+    block_of(tiles_m, tiles_n, &tm, &tn);
+    tile<BM, BN, WM, WN, NREC, Mode>(op, (int64_t)tm * BM, (int64_t)tn * BN, lds);
+}
+
+}  // namespace ring
+}  // namespace moa

@@ -5,78 +5,41 @@
 //
 // Two stages.
 //
-// 1. Conditioning (HBM-bound): A and B are rewritten as "slab records". The k
-//    extent is cut into slabs of 16 (the sigma loop broken into blocks,
-//    section "Dimension Lifting to Machine Coordinates"); for every row i of
-//    A and every column j of B, slab s becomes one contiguous 64-byte record
+// 1. Conditioning (HBM-bound): A and B are rewritten as record tiles (layout
+//    in ring_gemm.h). The k extent is cut into slabs of 16 (the sigma loop
+//    broken into blocks, section "Dimension Lifting to Machine Coordinates");
+//    for every row i of A and every column j of B, slab s becomes one
+//    contiguous 64-byte record
 //        [hi of x[16s .. 16s+15] (16 bf16)][lo of the same (16 bf16)]
 //    zero-padded past n. B is transposed on the way (column j of B becomes
-//    record row j), so both operands are k-contiguous. Records are stored in
-//    tiles of 16 rows x 1 slab: record (r, s) lives at byte
-//        ((r / 16) * S + s) * 1024 + (r mod 16) * 64,
-//    so the 16 records a wave moves into LDS in one load are one contiguous
-//    KiB of whole cache lines. Row counts are padded to a multiple of 16 with
-//    zero records.
+//    record row j), so both operands are k-contiguous.
 //
-// 2. Contraction (matrix-core bound), the blocked form of Fig. 2: each
-//    workgroup owns a BM x BN block of C and walks the S slabs; per slab the
-//    BM + BN records go straight from HBM into LDS (buffer_load ... lds, no
-//    register staging) through a ring of NSTAGE buffers, so loads run
-//    NSTAGE - 1 slabs ahead of the matrix cores. The block products of the slabs are
-//    summed in registers (the "addition loop" over blocks). The fragments of
-//    slab t+1 are read from LDS while the matrix-core steps of slab t issue.
-//
-// LDS holds one 64-byte row per record. gfx950's LDS serves a 16-byte read
-// for 16 lanes per cycle out of a 256-byte bank window (64 banks), i.e. four
-// consecutive rows at once. Chunk c of row r is stored at chunk position
-// c ^ ((r / 4) mod 4): the 16 rows of one fragment-read cycle then occupy 16
-// distinct 16-byte bank groups. The direct loads stay linear (lane L writes
-// bytes 16L .. 16L+15 of its wave's 1 KiB window = 16 rows), so each lane
-// fetches the logical chunk that belongs at its physical position.
+// 2. Contraction (matrix-core bound): the record-tile ring of ring_gemm.h
+//    (blocked form of Fig. 2) with three BF16 matrix-core steps per slab and
+//    block pair, FP32 accumulation.
 #include <algorithm>
 #include <vector>
 
 #include "moa_internal.h"
+#include "ring_gemm.h"
 #include "tile_common.h"
 
 namespace moa {
 namespace {
 
-constexpr int SLAB = 16;                  // k per record
-constexpr int REC = 2 * SLAB;             // bf16 per record (hi + lo)
-constexpr int REC_BYTES = REC * 2;        // 64
-constexpr int GROUP = 16;                 // rows per record tile (1 KiB per slab)
+using ring::GROUP;
+using ring::padded_rows;
+using ring::REC_BYTES;
 
-// bf16 offset of record (r, s) in a record array with S slabs per row
-__device__ __forceinline__ int64_t rec_off(int64_t r, int64_t s, int64_t S) {
-    return ((r / GROUP) * S + s) * (GROUP * REC) + (r % GROUP) * REC;
-}
-__host__ __device__ inline int64_t padded_rows(int64_t rows) { return (rows + GROUP - 1) / GROUP * GROUP; }
-constexpr int NSTAGE = 3;                 // LDS ring depth (3 measured faster than 4 or 5)
-// Two slabs per barrier (needs a 4-buffer ring): at even steps wait for the
-// two slabs loaded at the previous barrier, refill the two buffers freed
-// since, then run two slabs without a barrier.
-constexpr bool PAIRED = false;
-
-typedef __attribute__((address_space(3))) void lds_void_t;
-
-// gfx9 s_waitcnt immediate that waits until at most n vector-memory
-// operations of this wave are outstanding (expcnt and lgkmcnt not waited on).
-constexpr int waitcnt_vm(int n) { return (n & 0xF) | (((n >> 4) & 3) << 14) | (0x7 << 4) | (0xF << 8); }
-
-// Workgroup barrier without the release fence of __syncthreads(): that fence
-// would also wait for the direct loads still in flight for later slabs. Each
-// wave first waits (s_waitcnt) for its own loads of the slab it is about to
-// read; LDS reads are complete before their values are used. The "memory"
-// clobber keeps the compiler from moving LDS accesses across the barrier.
-__device__ __forceinline__ void ring_barrier() { asm volatile("s_barrier" ::: "memory"); }
+constexpr int SLAB = 16;                  // k per record: [hi 16 bf16][lo 16 bf16] = 64 bytes
+static_assert(REC_BYTES == 2 * SLAB * 2, "one record holds hi and lo of one slab");
 
 // ---------------------------------------------------------------- stage 1 --
 
 // Rows of X (rows x K, row-major) -> records: chunk q = 8 k values of one
 // record (2 chunks per record).
 __device__ __forceinline__ void pack_rows_chunk(const float *__restrict__ X, int64_t rows, int64_t K,
-                                                int64_t S, int vec, uint16_t *__restrict__ P,
+                                                int64_t S, int vec, uint8_t *__restrict__ P,
                                                 int64_t q) {
     // q -> (row tile g, slab s, row rr in the tile, chunk c): consecutive
     // threads fill one KiB tile contiguously
@@ -104,24 +67,19 @@ __device__ __forceinline__ void pack_rows_chunk(const float *__restrict__ X, int
     split_pair(x[2], x[3], &hi.y, &lo.y);
     split_pair(x[4], x[5], &hi.z, &lo.z);
     split_pair(x[6], x[7], &hi.w, &lo.w);
-    uint16_t *rec = P + rec_off(r, s, S);
-    *reinterpret_cast<uint4 *>(rec + c * 8) = hi;
-    *reinterpret_cast<uint4 *>(rec + SLAB + c * 8) = lo;
+    uint8_t *rec = P + ring::rec_byte(r, s, S);
+    *reinterpret_cast<uint4 *>(rec + c * 16) = hi;          // hi: bytes 0 .. 31
+    *reinterpret_cast<uint4 *>(rec + 32 + c * 16) = lo;     // lo: bytes 32 .. 63
 }
 
 __global__ __launch_bounds__(256) void pack_rows_kernel(const float *__restrict__ X, int64_t rows,
                                                         int64_t K, int64_t S, int vec,
-                                                        uint16_t *__restrict__ P) {
+                                                        uint8_t *__restrict__ P) {
     const int64_t chunks = padded_rows(rows) * S * 2;
     for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < chunks; q += (int64_t)gridDim.x * 256)
         pack_rows_chunk(X, rows, K, S, vec, P, q);
 }
 
-// Columns of X (K x cols, row-major) -> records (transposed). Block (bx, by)
-// covers columns 64 bx .. 64 bx + 63 and slabs 4 by .. 4 by + 3; it goes
-// through LDS so that reads of X rows are contiguous and every wave store
-// writes one whole KiB record tile. Columns past `cols` get zero records.
-// All 256 threads must call it together.
 // Columns of X (K x cols, row-major) -> records (transposed), 64 columns x
 // 64 k (4 slabs) per block through LDS: reads of X rows are contiguous
 // float4s and each thread writes one whole 64-byte record. Columns past
@@ -153,7 +111,7 @@ __device__ __forceinline__ void pack_cols_load(const float *__restrict__ X, int6
 
 // Stores a loaded block to LDS, then (after a barrier) writes its records.
 __device__ __forceinline__ void pack_cols_emit(const ColBlockRegs &r, int64_t cols, int64_t S,
-                                               uint16_t *__restrict__ P, int64_t bx, int64_t by,
+                                               uint8_t *__restrict__ P, int64_t bx, int64_t by,
                                                float (*tile)[64 + 4]) {
     const int t = threadIdx.x;
 #pragma unroll
@@ -172,7 +130,7 @@ __device__ __forceinline__ void pack_cols_emit(const ColBlockRegs &r, int64_t co
             split_pair(tile[kb + 4][jj], tile[kb + 5][jj], &h[c].z, &l[c].z);
             split_pair(tile[kb + 6][jj], tile[kb + 7][jj], &h[c].w, &l[c].w);
         }
-        uint4 *rec = reinterpret_cast<uint4 *>(P + rec_off(j, s, S));
+        uint4 *rec = reinterpret_cast<uint4 *>(P + ring::rec_byte(j, s, S));
         rec[0] = h[0];
         rec[1] = h[1];
         rec[2] = l[0];
@@ -182,7 +140,7 @@ __device__ __forceinline__ void pack_cols_emit(const ColBlockRegs &r, int64_t co
 }
 
 __device__ __forceinline__ void pack_cols_block(const float *__restrict__ X, int64_t K, int64_t cols,
-                                                int64_t S, uint16_t *__restrict__ P, int64_t bx,
+                                                int64_t S, uint8_t *__restrict__ P, int64_t bx,
                                                 int64_t by, float (*tile)[64 + 4], int vec) {
     ColBlockRegs r;
     pack_cols_load(X, K, cols, bx, by, vec, r);
@@ -195,7 +153,7 @@ constexpr int COL_BLOCKS = 4;
 
 __global__ __launch_bounds__(256) void pack_cols_kernel(const float *__restrict__ X, int64_t K,
                                                         int64_t cols, int64_t S, int vec,
-                                                        uint16_t *__restrict__ P) {
+                                                        uint8_t *__restrict__ P) {
     __shared__ __attribute__((aligned(16))) float tile[4 * SLAB][64 + 4];
     const int64_t by_count = (S + 3) / 4;
     const int64_t bx = blockIdx.x;
@@ -213,104 +171,31 @@ __global__ __launch_bounds__(256) void pack_cols_kernel(const float *__restrict_
 
 // ---------------------------------------------------------------- stage 2 --
 
-// Geometry of one block configuration.
-template <int BM, int BN, int WM, int WN> struct TileCfg {
-    static constexpr int WAVES_M = BM / WM, WAVES_N = BN / WN, NW = WAVES_M * WAVES_N;
-    static constexpr int THREADS = NW * 64;
-    static constexpr int FM = WM / 32, FN = WN / 32;
-    static constexpr int ROWS = BM + BN;                  // records per slab
-    static constexpr int STAGE = ROWS * REC_BYTES;        // bytes per LDS buffer
-    static constexpr int LDS = NSTAGE * STAGE;
-    static constexpr int LPW = ROWS / 16 / NW;            // 1 KiB direct loads per wave per slab
-    static_assert(ROWS % (16 * NW) == 0 && BM % 16 == 0, "whole loads per wave");
-};
+// Fragments of 32 records (rows) x 8 k: lane l reads row base + l%32; its hi
+// values are logical chunk l/32 of the record, its lo values chunk 2 + l/32.
+struct SplitMode {
+    static constexpr bool SCALED = false;
+    template <int FM, int FN> struct Frags { bf16x8_t ah[FM], al[FM], bh[FN], bl[FN]; };
 
-// One BM x BN block of C at (i0, j0): the whole k walk and the epilogue.
-// `lds` is the workgroup's ring of NSTAGE buffers. On entry no wave may still
-// be reading `lds` (the caller's barrier); on exit every wave has finished.
-template <int BM, int BN, int WM, int WN>
-__device__ __forceinline__ void split_tile(const uint16_t *__restrict__ Ap,
-                                           const uint16_t *__restrict__ Bp, float *__restrict__ C,
-                                           int64_t m, int64_t p, int64_t S, int accumulate,
-                                           int64_t i0, int64_t j0, uint8_t *lds) {
-    using G = TileCfg<BM, BN, WM, WN>;
-    constexpr int WAVES_N = G::WAVES_N, FM = G::FM, FN = G::FN;
-    constexpr int STAGE = G::STAGE, LPW = G::LPW;
-    const int t = threadIdx.x, lane = t & 63;
-    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
-    const int wm = wave / WAVES_N, wn = wave % WAVES_N;
-
-    // Direct loads through two buffer resources based at this tile's first
-    // record row of A and of B. Load Q = wave*LPW + q fills LDS rows
-    // 16Q .. 16Q+15: lane L lands at row 16Q + L/4, physical chunk L%4, and
-    // fetches logical chunk (L%4) ^ ((row/4) mod 4) = (L%4) ^ (L/16). The row
-    // block and the slab go in the uniform soffset. Records past m (or p) lie
-    // beyond the resource's range and load as zeros (their outputs are not
-    // stored).
-    const int64_t tile_row = S * GROUP * REC_BYTES;   // bytes per row tile (16 rows, all slabs)
-    const int64_t tiles_a = min((int64_t)BM, padded_rows(m) - i0) / GROUP;
-    const int64_t tiles_b = min((int64_t)BN, padded_rows(p) - j0) / GROUP;
-    const __amdgpu_buffer_rsrc_t rsrc_a = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(reinterpret_cast<const uint8_t *>(Ap) + (i0 / GROUP) * tile_row), (short)0,
-        (int)(tiles_a * tile_row), 0x00020000);
-    const __amdgpu_buffer_rsrc_t rsrc_b = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(reinterpret_cast<const uint8_t *>(Bp) + (j0 / GROUP) * tile_row), (short)0,
-        (int)(tiles_b * tile_row), 0x00020000);
-    const int voff = (lane >> 2) * REC_BYTES + (((lane & 3) ^ (lane >> 4)) << 4);
-    // Each wave's LPW loads cover 16*LPW consecutive rows that are either
-    // all rows of A or all rows of B, so every load names one resource.
-    static_assert(BM % (16 * LPW) == 0, "a wave loads A rows or B rows, not both");
-    const bool loads_a = wave * LPW * 16 < BM;
-    const int row_base = loads_a ? wave * LPW * 16 : wave * LPW * 16 - BM;
-    auto issue = [&](int64_t s) {
-        uint8_t *buf = lds + (int)(s % NSTAGE) * STAGE + wave * LPW * 16 * REC_BYTES;
-        if (loads_a) {
-#pragma unroll
-            for (int q = 0; q < LPW; ++q)
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                    rsrc_a, (lds_void_t *)(buf + q * 16 * REC_BYTES), 16, voff,
-                    (int)((row_base / GROUP + q) * tile_row + s * GROUP * REC_BYTES), 0, 0);
-        } else {
-#pragma unroll
-            for (int q = 0; q < LPW; ++q)
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                    rsrc_b, (lds_void_t *)(buf + q * 16 * REC_BYTES), 16, voff,
-                    (int)((row_base / GROUP + q) * tile_row + s * GROUP * REC_BYTES), 0, 0);
-        }
-    };
-
-    // Fragment of 32 records (rows) x 8 k: lane l reads logical chunk c of
-    // row base + l%32; hi is chunk l/32, lo is chunk 2 + l/32.
-    const int frow = lane & 31, fhalf = lane >> 5;
-    auto frag = [&](const uint8_t *buf, int row, int chunk) {
-        return *reinterpret_cast<const bf16x8_t *>(buf + row * REC_BYTES +
-                                                   ((chunk ^ ((row >> 2) & 3)) << 4));
-    };
-    struct Frags { bf16x8_t ah[FM], al[FM], bh[FN], bl[FN]; };
-    auto read_frags = [&](int64_t s, Frags &f) {
-        const uint8_t *buf = lds + (int)(s % NSTAGE) * STAGE;
+    template <int BM, int BN, int FM, int FN>
+    static __device__ __forceinline__ void read(const uint8_t *buf, int a_row, int b_row, int half,
+                                                Frags<FM, FN> &f) {
 #pragma unroll
         for (int a = 0; a < FM; ++a) {
-            const int row = wm * WM + a * 32 + frow;
-            f.ah[a] = frag(buf, row, fhalf);
-            f.al[a] = frag(buf, row, 2 + fhalf);
+            f.ah[a] = ring::lds_chunk<bf16x8_t>(buf, a_row + a * 32, half);
+            f.al[a] = ring::lds_chunk<bf16x8_t>(buf, a_row + a * 32, 2 + half);
         }
 #pragma unroll
         for (int b = 0; b < FN; ++b) {
-            const int row = BM + wn * WN + b * 32 + frow;
-            f.bh[b] = frag(buf, row, fhalf);
-            f.bl[b] = frag(buf, row, 2 + fhalf);
+            f.bh[b] = ring::lds_chunk<bf16x8_t>(buf, b_row + b * 32, half);
+            f.bl[b] = ring::lds_chunk<bf16x8_t>(buf, b_row + b * 32, 2 + half);
         }
-    };
+    }
 
-    f32x16_t acc[FM][FN];
-#pragma unroll
-    for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int b = 0; b < FN; ++b) acc[a][b] = f32x16_t{};
-
-    // term-major order: consecutive matrix-core steps are independent
-    auto mma = [&](const Frags &f) {
+    // term-major order: consecutive matrix-core steps are independent; every
+    // element sees lo.hi, hi.lo, hi.hi of each slab, slabs in ascending order
+    template <int FM, int FN>
+    static __device__ __forceinline__ void mma(const Frags<FM, FN> &f, f32x16_t (&acc)[FM][FN]) {
 #pragma unroll
         for (int a = 0; a < FM; ++a)
 #pragma unroll
@@ -326,105 +211,19 @@ __device__ __forceinline__ void split_tile(const uint16_t *__restrict__ Ap,
 #pragma unroll
             for (int b = 0; b < FN; ++b)
                 acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(f.ah[a], f.bh[b], acc[a][b], 0, 0, 0);
-    };
-
-    // One step: make slab t+1 visible, refill the buffer slab t-1 used with
-    // slab t+3, read slab t+1's fragments, then issue slab t's products.
-    // Wait until at most `stages` slabs of this wave's loads are still in
-    // flight (the immediate of s_waitcnt must be a constant).
-    auto wait_loads = [&](int64_t stages) {
-        switch (stages <= 0 ? 0 : stages >= 3 ? 3 : (int)stages) {
-        case 0: __builtin_amdgcn_s_waitcnt(waitcnt_vm(0)); break;
-        case 1: __builtin_amdgcn_s_waitcnt(waitcnt_vm(LPW)); break;
-        case 2: __builtin_amdgcn_s_waitcnt(waitcnt_vm(2 * LPW)); break;
-        default: __builtin_amdgcn_s_waitcnt(waitcnt_vm(3 * LPW)); break;
-        }
-    };
-    static_assert(NSTAGE >= 3 && NSTAGE <= 5, "wait_loads covers up to 3 slabs in flight");
-
-    // One step: make slab t+1 visible (its loads landed in every wave), refill
-    // the buffer slab t-1 used with slab t+NSTAGE-1, read slab t+1's
-    // fragments, then issue slab t's products.
-    auto step = [&](int64_t t, const Frags &cur, Frags &next) {
-        if (t + 1 < S) {
-            // issued so far: slabs up to t + NSTAGE - 2; t + 1 must have landed
-            wait_loads(min((int64_t)NSTAGE - 3, S - t - 2));
-            ring_barrier();
-            if (t + NSTAGE - 1 < S) issue(t + NSTAGE - 1);
-            read_frags(t + 1, next);
-        }
-        mma(cur);
-    };
-
-    if (S > 0 && !PAIRED) {
-        for (int q = 0; q < NSTAGE - 1; ++q)
-            if (q < S) issue(q);
-        wait_loads(min((int64_t)NSTAGE - 2, S - 1));   // slab 0 has landed
-        ring_barrier();
-        Frags f0, f1;
-        read_frags(0, f0);
-        int64_t t = 0;
-        for (; t + 1 < S; t += 2) {
-            step(t, f0, f1);
-            step(t + 1, f1, f0);
-        }
-        if (t < S) step(t, f0, f1);
-    } else if (S > 0) {
-        static_assert(!PAIRED || NSTAGE == 4, "paired barriers use a 4-buffer ring");
-        for (int q = 0; q < 3; ++q)
-            if (q < S) issue(q);
-        wait_loads(min((int64_t)2, S - 1));            // slab 0 has landed
-        ring_barrier();
-        Frags f0, f1;
-        read_frags(0, f0);
-        for (int64_t t = 0; t < S; t += 2) {
-            if (t + 1 < S) {
-                wait_loads(0);                         // slabs t+1, t+2 have landed
-                ring_barrier();
-                if (t + 3 < S) issue(t + 3);           // into the buffers of slabs t-1 and t,
-                if (t + 4 < S) issue(t + 4);           // whose fragments are in registers
-                read_frags(t + 1, f1);
-            }
-            mma(f0);
-            if (t + 1 < S) {
-                if (t + 2 < S) read_frags(t + 2, f0);
-                mma(f1);
-            }
-        }
     }
+};
 
-    // Epilogue: register r of lane l holds C[8(r/4) + 4(l/32) + r%4][l%32] of
-    // each 32x32 block; 32 lanes write one 128-byte run of a row of C.
-#pragma unroll
-    for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int b = 0; b < FN; ++b) {
-            const int64_t j = j0 + wn * WN + b * 32 + (lane & 31);
-            if (j >= p) continue;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t i = i0 + wm * WM + a * 32 + mfma32_row(r, lane);
-                if (i < m) {
-                    float v = acc[a][b][r];
-                    if (accumulate) v += C[i * p + j];
-                    C[i * p + j] = v;
-                }
-            }
-        }
-}
-
-template <int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void split_bf16_kernel(
-    const uint16_t *__restrict__ Ap, const uint16_t *__restrict__ Bp, float *__restrict__ C,
-    int64_t m, int64_t p, int64_t S, int accumulate, int tiles_m, int tiles_n) {
-    __shared__ __attribute__((aligned(1024))) uint8_t lds[TileCfg<BM, BN, WM, WN>::LDS];
-    int tm, tn;
-    tile_coords(xcd_remap(blockIdx.x, tiles_m * tiles_n), tiles_m, tiles_n, 8, &tm, &tn);
-    // the integer divisions above run on the vector ALU; pin the (uniform)
-    // results to scalar registers so everything derived from them stays scalar
-    tm = __builtin_amdgcn_readfirstlane(tm);
-    tn = __builtin_amdgcn_readfirstlane(tn);
-    split_tile<BM, BN, WM, WN>(Ap, Bp, C, m, p, S, accumulate, (int64_t)tm * BM, (int64_t)tn * BN, lds);
+ring::Operands split_operands(const uint8_t *Ap, const uint8_t *Bp, float *C, int64_t m, int64_t p,
+                              int64_t S, int accumulate) {
+    ring::Operands op;
+    op.a0 = Ap; op.a1 = nullptr;
+    op.b0 = Bp; op.b1 = nullptr;
+    op.C = C;
+    op.row_exp = op.col_exp = nullptr;
+    op.m = m; op.p = p; op.S = S;
+    op.accumulate = accumulate;
+    return op;
 }
 
 // ------------------------------------------------------- grouped (persistent)
@@ -438,7 +237,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void split_bf16_kernel(
 struct GroupMember {
     const float *A, *B;
     float *C;
-    uint16_t *Ap, *Bp;                  // records of this member in the workspace
+    uint8_t *Ap, *Bp;                   // records of this member in the workspace
     int64_t m, n, p, S;
     int64_t first_tile;                 // first work-list id of this member
     int32_t tiles_n, accumulate;
@@ -457,7 +256,7 @@ template <int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void split_grouped_kernel(
     const GroupMember *__restrict__ g, int count, int64_t total_tiles,
     unsigned long long *__restrict__ counter) {
-    __shared__ __attribute__((aligned(1024))) uint8_t lds[TileCfg<BM, BN, WM, WN>::LDS];
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[ring::Cfg<BM, BN, WM, WN, 1>::LDS];
     __shared__ int64_t s_tile;
     for (;;) {
         __syncthreads();                // nobody still reads lds or s_tile
@@ -469,9 +268,15 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void split_grouped_kern
         const GroupMember &d = g[k];
         const int64_t local = tile - d.first_tile;
         const int64_t tm = local / d.tiles_n, tn = local - tm * d.tiles_n;
-        split_tile<BM, BN, WM, WN>(d.Ap, d.Bp, d.C, d.m, d.p, d.S, d.accumulate,
-                                   __builtin_amdgcn_readfirstlane((int)tm) * (int64_t)BM,
-                                   __builtin_amdgcn_readfirstlane((int)tn) * (int64_t)BN, lds);
+        ring::Operands op;
+        op.a0 = d.Ap; op.a1 = nullptr;
+        op.b0 = d.Bp; op.b1 = nullptr;
+        op.C = d.C;
+        op.row_exp = op.col_exp = nullptr;
+        op.m = d.m; op.p = d.p; op.S = d.S;
+        op.accumulate = d.accumulate;
+        ring::tile<BM, BN, WM, WN, 1, SplitMode>(op, __builtin_amdgcn_readfirstlane((int)tm) * (int64_t)BM,
+                                                 __builtin_amdgcn_readfirstlane((int)tn) * (int64_t)BN, lds);
     }
 }
 
@@ -525,14 +330,13 @@ struct SplitShape { int bm, bn, wm, wn; };
 constexpr SplitShape kSplit[] = {{128, 128, 64, 64}, {256, 256, 128, 64}};
 
 template <int BM, int BN, int WM, int WN>
-hipError_t launch_shape(const moa_gemm_desc &d, const uint16_t *Ap, const uint16_t *Bp, int64_t S,
+hipError_t launch_shape(const moa_gemm_desc &d, const uint8_t *Ap, const uint8_t *Bp, int64_t S,
                         hipStream_t st) {
-    float *C = static_cast<float *>(d.C);
+    const ring::Operands op = split_operands(Ap, Bp, static_cast<float *>(d.C), d.m, d.p, S, d.accumulate);
     const int tiles_m = (int)((d.m + BM - 1) / BM);
     const int tiles_n = (int)((d.p + BN - 1) / BN);
-    constexpr int threads = (BM / WM) * (BN / WN) * 64;
-    hipLaunchKernelGGL((split_bf16_kernel<BM, BN, WM, WN>), dim3(tiles_m * tiles_n), dim3(threads), 0,
-                       st, Ap, Bp, C, d.m, d.p, S, d.accumulate, tiles_m, tiles_n);
+    hipLaunchKernelGGL((ring::single_kernel<BM, BN, WM, WN, 1, SplitMode>), dim3(tiles_m * tiles_n),
+                       dim3(ring::Cfg<BM, BN, WM, WN, 1>::THREADS), 0, st, op, tiles_m, tiles_n);
     return hipGetLastError();
 }
 
@@ -542,7 +346,7 @@ int split_bf16_variant_count() { return (int)(sizeof(kSplit) / sizeof(kSplit[0])
 
 int64_t split_bf16_workspace_bytes(int64_t m, int64_t n, int64_t p) {
     const int64_t S = (n + SLAB - 1) / SLAB;
-    return (padded_rows(m) + padded_rows(p)) * S * REC_BYTES;
+    return ring::array_bytes(m, S) + ring::array_bytes(p, S);
 }
 
 void split_bf16_shape(int v, Plan *p) {
@@ -555,13 +359,13 @@ void split_bf16_shape(int v, Plan *p) {
     p->wave_n = s.wn;
     p->lane_m = p->lane_n = 0;
     p->threads = (s.bm / s.wm) * (s.bn / s.wn) * 64;
-    p->lds_bytes = NSTAGE * (s.bm + s.bn) * REC_BYTES;
+    p->lds_bytes = ring::NSTAGE * (s.bm + s.bn) * REC_BYTES;
 }
 
 hipError_t launch_split_pack(const moa_gemm_desc &d, void *ws, hipStream_t st) {
     const int64_t S = (d.n + SLAB - 1) / SLAB;
-    uint16_t *Ap = static_cast<uint16_t *>(ws);
-    uint16_t *Bp = Ap + padded_rows(d.m) * S * REC;
+    uint8_t *Ap = static_cast<uint8_t *>(ws);
+    uint8_t *Bp = Ap + ring::array_bytes(d.m, S);
     const float *A = static_cast<const float *>(d.A);
     const float *B = static_cast<const float *>(d.B);
     if (S == 0) return hipSuccess;
@@ -586,8 +390,8 @@ hipError_t launch_split_bf16(const moa_gemm_desc &d, const Plan &plan, void *ws,
     if (e != hipSuccess) return e;
     TraceScope ts(MOA_K_SPLIT_BF16, st);
     const int64_t S = (d.n + SLAB - 1) / SLAB;
-    const uint16_t *Ap = static_cast<const uint16_t *>(ws);
-    const uint16_t *Bp = Ap + padded_rows(d.m) * S * REC;
+    const uint8_t *Ap = static_cast<const uint8_t *>(ws);
+    const uint8_t *Bp = Ap + ring::array_bytes(d.m, S);
     switch (plan.variant) {
     case 0: return launch_shape<128, 128, 64, 64>(d, Ap, Bp, S, st);
     default: return launch_shape<256, 256, 128, 64>(d, Ap, Bp, S, st);
@@ -631,8 +435,8 @@ int64_t split_grouped_layout(const moa_gemm_desc *const *members, int count, voi
         g.C = static_cast<float *>(d.C);
         g.m = d.m; g.n = d.n; g.p = d.p;
         g.S = (d.n + SLAB - 1) / SLAB;
-        g.Ap = reinterpret_cast<uint16_t *>(rec);
-        g.Bp = g.Ap + padded_rows(d.m) * g.S * REC;
+        g.Ap = reinterpret_cast<uint8_t *>(rec);
+        g.Bp = g.Ap + ring::array_bytes(d.m, g.S);
         rec += align256(split_bf16_workspace_bytes(d.m, d.n, d.p));
         g.first_tile = tiles;
         g.tiles_n = (int32_t)((d.p + GB_N - 1) / GB_N);
@@ -661,7 +465,7 @@ hipError_t split_grouped_enqueue(void *ws, int count, int64_t tiles, hipStream_t
     TraceScope ts(MOA_K_SPLIT_GROUPED, st);
     if (grid > 0)
         hipLaunchKernelGGL((split_grouped_kernel<GB_M, GB_N, GW_M, GW_N>), dim3((unsigned)grid),
-                           dim3(TileCfg<GB_M, GB_N, GW_M, GW_N>::THREADS), 0, st, dev_members, count,
+                           dim3(ring::Cfg<GB_M, GB_N, GW_M, GW_N, 1>::THREADS), 0, st, dev_members, count,
                            tiles, counter);
     return hipGetLastError();
 }

@@ -70,6 +70,30 @@ def test_plan_static_components_and_shapes():
     assert f8["workspace_bytes"] >= 100 * 200 + 200 * 300
 
 
+def test_fp8_plan_variants():
+    """FP8 block variants: 64-code slabs, LDS ring of three slabs of records
+    (two record arrays per operand for the two-term form), largest block with
+    a workgroup per CU by default."""
+    F8 = moa.MOA_PATH_FP8_SCALED
+    TWO = moa.MOA_FLAG_FP8_TWO_TERM
+    one = [moa.moa_plan_query(_desc(1000, 300, 1000, path=F8, flags=moa.MOA_FLAG_VARIANT(v))) for v in range(2)]
+    assert [(q["tile_m"], q["tile_n"], q["tile_k"]) for q in one] == [(128, 128, 64), (256, 256, 64)]
+    assert [q["lds_bytes"] for q in one] == [3 * 256 * 64, 3 * 512 * 64]
+    two = [moa.moa_plan_query(_desc(1000, 300, 1000, path=F8, flags=TWO | moa.MOA_FLAG_VARIANT(v)))
+           for v in range(2)]
+    assert [q["threads"] for q in two] == [256, 512]
+    assert all(q["lds_bytes"] == 3 * 2 * 256 * 64 for q in two)
+    assert call(_desc(8, 8, 8, path=F8, flags=moa.MOA_FLAG_VARIANT(2))) == moa.MOA_ERR_INVALID
+    # records: padded rows x ceil(n / 64) x 64 bytes per operand (twice for two terms)
+    q1 = moa.moa_plan_query(_desc(100, 200, 300, path=F8))
+    q2 = moa.moa_plan_query(_desc(100, 200, 300, path=F8, flags=TWO))
+    rec = (112 + 304) * 4 * 64
+    assert rec <= q1["workspace_bytes"] < rec + 8 * 1024
+    assert 2 * rec <= q2["workspace_bytes"] < 2 * rec + 8 * 1024
+    big = moa.moa_plan_query(_desc(8192, 8192, 8192, path=F8))
+    assert big["tile_m"] == 256 and big["workgroups"] == 1024
+
+
 def call(d):
     return moa.lib().moa_gemm(ctypes.byref(d), None)
 

@@ -130,6 +130,29 @@ def test_fp8_against_quantised_product(shape, two):
     assert O.rel_err(C, Q) <= 1e-4
 
 
+@pytest.mark.parametrize("two", [False, True])
+def test_fp8_every_variant_same_bits(two):
+    """Every block variant gives the same bits (each element sees the same
+    slab sequence of matrix-core steps) and meets the quantised-product bar;
+    the shape has ragged edges in m, n and p."""
+    m, n, p = 300, 1000, 259
+    A, B = inputs.row_col_scaled_f32(m, n, p, seed=41)
+    flag = moa.MOA_FLAG_FP8_TWO_TERM if two else 0
+    outs = [run(A, B, "fp8", flags=flag | moa.MOA_FLAG_VARIANT(v)) for v in range(2)]
+    assert np.array_equal(outs[0], outs[1])
+    Q = O.fp8_gemm_2term(A, B) if two else O.fp8_gemm(A, B)
+    assert O.rel_err(outs[0], Q) <= 1e-4
+
+
+@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("two", [False, True])
+def test_fp8_variants_integer_exact(variant, two):
+    A, B = inputs.integer_valued(260, 200, 300, seed=8, dtype=np.float32)
+    flag = (moa.MOA_FLAG_FP8_TWO_TERM if two else 0) | moa.MOA_FLAG_VARIANT(variant)
+    C = run(A, B, "fp8", flags=flag)
+    assert np.array_equal(C.astype(np.float64), O.gemm_f64(A.astype(np.float64), B.astype(np.float64)))
+
+
 def test_split_conditioning_bitwise():
     A, _ = inputs.row_col_scaled_f32(37, 1001, 1, seed=9)
     X = dev(A)
