@@ -91,6 +91,7 @@ __global__ __launch_bounds__(256) void row_exp_kernel(const float *__restrict__ 
     float mx = 0.0f;
     if (vec) {
         const float4 *r4 = reinterpret_cast<const float4 *>(row);
+#pragma unroll 8
         for (int64_t k = lane; k < n / 4; k += 64) {
             const float4 v = r4[k];
             mx = fmaxf(mx, fmaxf(fmaxf(fabsf(v.x), fabsf(v.y)), fmaxf(fabsf(v.z), fabsf(v.w))));
@@ -164,39 +165,80 @@ __global__ __launch_bounds__(256) void pack_rows_fp8_kernel(const float *__restr
     }
 }
 
-// Columns of B -> records (transposed). One thread per column j and slab s
-// reads the 64 values B[64s .. 64s+63][j] (a wave's loads of one row are 256
-// contiguous bytes) and writes the whole 64-byte record; a workgroup takes
-// 256 adjacent columns. Column exponents come from the column amax; the
-// workgroups of slab row blockIdx.y == 0 also store them. Columns past p get
+// Columns of B -> records (transposed), 64 columns x one slab (64 k) per
+// workgroup step. Thread t reads rows 4(t/16) .. +3 of columns 4(t%16) .. +3
+// (each row of the block is 256 contiguous bytes), quantises them, turns the
+// 4 x 4 codes around in registers and stores one dword per column into an LDS
+// tile (row stride 17 dwords: the 64 lanes of a store hit 64 distinct banks).
+// Then thread t writes bytes 16(t%4) .. +15 of the record of column t/4, so a
+// wave stores one whole KiB record tile. Column exponents come from the column
+// amax; workgroups with blockIdx.y == 0 also store them. Columns past p get
 // zero records.
+constexpr int TSTRIDE = 17;
+
+__device__ __forceinline__ uint32_t byte_column(const uint32_t w[4], int c) {
+    const int sh = 8 * c;
+    return ((w[0] >> sh) & 0xFFu) | (((w[1] >> sh) & 0xFFu) << 8) | (((w[2] >> sh) & 0xFFu) << 16) |
+           (((w[3] >> sh) & 0xFFu) << 24);
+}
+
 template <bool TWO>
 __global__ __launch_bounds__(256) void pack_cols_fp8_kernel(const float *__restrict__ B, int64_t n,
-                                                            int64_t p, int64_t S,
+                                                            int64_t p, int64_t S, int vec,
                                                             const uint32_t *__restrict__ amax,
                                                             int32_t *__restrict__ f_out,
                                                             uint8_t *__restrict__ qb,
                                                             uint8_t *__restrict__ lb) {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (j >= padded_rows(p)) return;
-    const bool live = j < p;
-    const int fj = live ? pow2_exponent(__uint_as_float(amax[j])) : 0;
-    if (live && blockIdx.y == 0) f_out[j] = fj;
+    __shared__ uint32_t tq[64 * TSTRIDE];
+    __shared__ uint32_t tl[TWO ? 64 * TSTRIDE : 1];
+    const int t = threadIdx.x;
+    const int cg = t & 15, kq = t >> 4;
+    const int64_t j0 = (int64_t)blockIdx.x * 64;
+    const int64_t j = j0 + 4 * cg;                 // this thread's first column
+    int fcol[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        fcol[u] = (j + u < p) ? pow2_exponent(__uint_as_float(amax[j + u])) : 0;
+        if (blockIdx.y == 0 && kq == 0 && j + u < p) f_out[j + u] = fcol[u];
+    }
+    const int jj = t >> 2, c = t & 3;              // writer: column j0 + jj, chunk c
+    const bool writes = j0 + jj < padded_rows(p);
     for (int64_t s = blockIdx.y; s < S; s += gridDim.y) {
-        const int64_t k0 = s * SLAB8;
-        float x[SLAB8];
+        uint32_t wq[4], wl[4] = {0u, 0u, 0u, 0u};
 #pragma unroll
-        for (int t = 0; t < SLAB8; ++t) x[t] = (live && k0 + t < n) ? ldexpf(B[(k0 + t) * p + j], fj) : 0.0f;
-        uint32_t hi[16], lo[16] = {};
+        for (int i = 0; i < 4; ++i) {
+            const int64_t k = s * SLAB8 + 4 * kq + i;
+            float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+            if (k < n) {
+                const float *row = B + k * p + j;
+                if (vec && j + 4 <= p) {
+                    const float4 x = *reinterpret_cast<const float4 *>(row);
+                    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+                } else {
 #pragma unroll
-        for (int u = 0; u < 16; ++u) quant4(x + 4 * u, TWO, &hi[u], &lo[u]);
-        uint4 *dq = reinterpret_cast<uint4 *>(qb + ring::rec_byte(j, s, S));
+                    for (int u = 0; u < 4; ++u)
+                        if (j + u < p) v[u] = row[u];
+                }
+            }
 #pragma unroll
-        for (int c = 0; c < 4; ++c) dq[c] = make_uint4(hi[4 * c], hi[4 * c + 1], hi[4 * c + 2], hi[4 * c + 3]);
-        if (TWO) {
-            uint4 *dl = reinterpret_cast<uint4 *>(lb + ring::rec_byte(j, s, S));
+            for (int u = 0; u < 4; ++u) v[u] = ldexpf(v[u], fcol[u]);
+            quant4(v, TWO, &wq[i], &wl[i]);
+        }
+        __syncthreads();                           // the previous step's reads of the tiles are done
 #pragma unroll
-            for (int c = 0; c < 4; ++c) dl[c] = make_uint4(lo[4 * c], lo[4 * c + 1], lo[4 * c + 2], lo[4 * c + 3]);
+        for (int u = 0; u < 4; ++u) {
+            tq[(4 * cg + u) * TSTRIDE + kq] = byte_column(wq, u);
+            if (TWO) tl[(4 * cg + u) * TSTRIDE + kq] = byte_column(wl, u);
+        }
+        __syncthreads();
+        if (writes) {
+            const uint32_t *r = tq + jj * TSTRIDE + 4 * c;
+            const int64_t at = ring::rec_byte(j0 + jj, s, S) + 16 * c;
+            *reinterpret_cast<uint4 *>(qb + at) = make_uint4(r[0], r[1], r[2], r[3]);
+            if (TWO) {
+                const uint32_t *q = tl + jj * TSTRIDE + 4 * c;
+                *reinterpret_cast<uint4 *>(lb + at) = make_uint4(q[0], q[1], q[2], q[3]);
+            }
         }
     }
 }
@@ -319,19 +361,23 @@ template <bool TWO> struct Fp8Mode {
     }
 };
 
-struct Fp8Shape { int bm, bn, wm, wn; };
-constexpr Fp8Shape kOne[] = {{128, 128, 64, 64}, {256, 256, 128, 64}};
-constexpr Fp8Shape kTwo[] = {{128, 128, 64, 64}, {128, 128, 64, 32}};
+struct Fp8Shape { int bm, bn, wm, wn, stages; };
+constexpr Fp8Shape kOne[] = {{128, 128, 64, 64, 3}, {256, 256, 128, 64, 3}, {256, 256, 128, 64, 4},
+                             {256, 256, 128, 64, 5}};
+// Deeper rings pay off here: a slab carries 64 k, so a step is short next
+// to the latency of its loads.
+constexpr Fp8Shape kTwo[] = {{128, 128, 64, 64, 3}, {128, 128, 64, 32, 3}, {128, 128, 64, 32, 5},
+                             {128, 128, 64, 32, 4}};
 constexpr int kOneCount = sizeof(kOne) / sizeof(kOne[0]);
 constexpr int kTwoCount = sizeof(kTwo) / sizeof(kTwo[0]);
 
-template <int BM, int BN, int WM, int WN, bool TWO>
+template <int BM, int BN, int WM, int WN, bool TWO, int NST = ring::NSTAGE>
 hipError_t launch_shape(const ring::Operands &op, hipStream_t st) {
     constexpr int NREC = TWO ? 2 : 1;
     const int tiles_m = (int)((op.m + BM - 1) / BM);
     const int tiles_n = (int)((op.p + BN - 1) / BN);
-    hipLaunchKernelGGL((ring::single_kernel<BM, BN, WM, WN, NREC, Fp8Mode<TWO>>), dim3(tiles_m * tiles_n),
-                       dim3(ring::Cfg<BM, BN, WM, WN, NREC>::THREADS), 0, st, op, tiles_m, tiles_n);
+    hipLaunchKernelGGL((ring::single_kernel<BM, BN, WM, WN, NREC, Fp8Mode<TWO>, NST>), dim3(tiles_m * tiles_n),
+                       dim3(ring::Cfg<BM, BN, WM, WN, NREC, NST>::THREADS), 0, st, op, tiles_m, tiles_n);
     return hipGetLastError();
 }
 
@@ -385,13 +431,14 @@ hipError_t pack_records(const moa_gemm_desc &d, bool two, const Fp8Workspace &w,
                                vec, w.e, w.qA, w.lA);
     }
     if (d.p > 0) {   // also when S == 0: the epilogue reads the column exponents
-        const dim3 grid((unsigned)((padded_rows(d.p) + 255) / 256), (unsigned)(S < 1 ? 1 : S > 65535 ? 65535 : S));
+        const int vec = (d.p % 4 == 0) && ((uintptr_t)B % 16 == 0);
+        const dim3 grid((unsigned)((d.p + 63) / 64), (unsigned)(S < 1 ? 1 : S > 65535 ? 65535 : S));
         if (two)
-            hipLaunchKernelGGL(pack_cols_fp8_kernel<true>, grid, dim3(256), 0, st, B, d.n, d.p, S, w.amaxB, w.f,
-                               w.qB, w.lB);
+            hipLaunchKernelGGL(pack_cols_fp8_kernel<true>, grid, dim3(256), 0, st, B, d.n, d.p, S, vec, w.amaxB,
+                               w.f, w.qB, w.lB);
         else
-            hipLaunchKernelGGL(pack_cols_fp8_kernel<false>, grid, dim3(256), 0, st, B, d.n, d.p, S, w.amaxB, w.f,
-                               w.qB, w.lB);
+            hipLaunchKernelGGL(pack_cols_fp8_kernel<false>, grid, dim3(256), 0, st, B, d.n, d.p, S, vec, w.amaxB,
+                               w.f, w.qB, w.lB);
     }
     return hipGetLastError();
 }
@@ -410,7 +457,7 @@ void fp8_shape(bool two, int v, Plan *p) {
     p->wave_n = s.wn;
     p->lane_m = p->lane_n = 0;
     p->threads = (s.bm / s.wm) * (s.bn / s.wn) * 64;
-    p->lds_bytes = ring::NSTAGE * (two ? 2 : 1) * (s.bm + s.bn) * REC_BYTES;
+    p->lds_bytes = s.stages * (two ? 2 : 1) * (s.bm + s.bn) * REC_BYTES;
 }
 
 int64_t fp8_workspace_bytes(int64_t m, int64_t n, int64_t p, bool two) {
@@ -441,12 +488,16 @@ hipError_t launch_fp8(const moa_gemm_desc &d, const Plan &plan, void *ws, hipStr
     if (two) {
         switch (plan.variant) {
         case 0: return launch_shape<128, 128, 64, 64, true>(op, st);
-        default: return launch_shape<128, 128, 64, 32, true>(op, st);
+        case 1: return launch_shape<128, 128, 64, 32, true>(op, st);
+        case 2: return launch_shape<128, 128, 64, 32, true, 5>(op, st);
+        default: return launch_shape<128, 128, 64, 32, true, 4>(op, st);
         }
     }
     switch (plan.variant) {
     case 0: return launch_shape<128, 128, 64, 64, false>(op, st);
-    default: return launch_shape<256, 256, 128, 64, false>(op, st);
+    case 1: return launch_shape<256, 256, 128, 64, false>(op, st);
+    case 2: return launch_shape<256, 256, 128, 64, false, 4>(op, st);
+    default: return launch_shape<256, 256, 128, 64, false, 5>(op, st);
     }
 }
 

@@ -34,7 +34,7 @@ namespace ring {
 
 constexpr int REC_BYTES = 64;             // bytes per record
 constexpr int GROUP = 16;                 // rows per record tile
-constexpr int NSTAGE = 3;                 // LDS ring depth (3 measured faster than 4 or 5)
+constexpr int NSTAGE = 3;                 // default LDS ring depth (slabs in LDS at once)
 
 __host__ __device__ inline int64_t padded_rows(int64_t rows) { return (rows + GROUP - 1) / GROUP * GROUP; }
 
@@ -61,13 +61,13 @@ constexpr int waitcnt_vm(int n) { return (n & 0xF) | (((n >> 4) & 3) << 14) | (0
 // clobber keeps the compiler from moving LDS accesses across the barrier.
 __device__ __forceinline__ void ring_barrier() { asm volatile("s_barrier" ::: "memory"); }
 
-template <int BM, int BN, int WM, int WN, int NREC> struct Cfg {
+template <int BM, int BN, int WM, int WN, int NREC, int NST = NSTAGE> struct Cfg {
     static constexpr int WAVES_M = BM / WM, WAVES_N = BN / WN, NW = WAVES_M * WAVES_N;
     static constexpr int THREADS = NW * 64;
     static constexpr int FM = WM / 32, FN = WN / 32;
     static constexpr int ROWS = NREC * (BM + BN);         // records per slab
     static constexpr int STAGE = ROWS * REC_BYTES;        // bytes per LDS buffer
-    static constexpr int LDS = NSTAGE * STAGE;
+    static constexpr int LDS = NST * STAGE;
     static constexpr int LPW = ROWS / 16 / NW;            // KiB direct loads per wave per slab
     static_assert(ROWS % (16 * NW) == 0, "whole loads per wave");
     static_assert(BM % (16 * LPW) == 0 && BN % (16 * LPW) == 0, "a wave loads rows of one array");
@@ -101,9 +101,9 @@ __device__ __forceinline__ V lds_chunk(const uint8_t *buf, int row, int chunk) {
 // [B array 0 (BN)] .. [B array NREC-1].
 // `lds` is the workgroup's ring; on entry no wave may still be reading it, on
 // exit every wave has finished.
-template <int BM, int BN, int WM, int WN, int NREC, class Mode>
+template <int BM, int BN, int WM, int WN, int NREC, class Mode, int NSTAGE = ring::NSTAGE>
 __device__ __forceinline__ void tile(const Operands &op, int64_t i0, int64_t j0, uint8_t *lds) {
-    using G = Cfg<BM, BN, WM, WN, NREC>;
+    using G = Cfg<BM, BN, WM, WN, NREC, NSTAGE>;
     constexpr int WAVES_N = G::WAVES_N, FM = G::FM, FN = G::FN;
     constexpr int STAGE = G::STAGE, LPW = G::LPW;
     const int t = threadIdx.x, lane = t & 63;
@@ -155,13 +155,15 @@ __device__ __forceinline__ void tile(const Operands &op, int64_t i0, int64_t j0,
 
     // Wait until at most `stages` slabs of this wave's loads are in flight.
     auto wait_loads = [&](int stages) {
-        switch (stages <= 0 ? 0 : stages >= 2 ? 2 : stages) {
+        switch (stages <= 0 ? 0 : stages >= 3 ? 3 : stages) {
         case 0: __builtin_amdgcn_s_waitcnt(waitcnt_vm(0)); break;
         case 1: __builtin_amdgcn_s_waitcnt(waitcnt_vm(LPW)); break;
-        default: __builtin_amdgcn_s_waitcnt(waitcnt_vm(2 * LPW)); break;
+        case 2: __builtin_amdgcn_s_waitcnt(waitcnt_vm(2 * LPW)); break;
+        default: __builtin_amdgcn_s_waitcnt(waitcnt_vm(3 * LPW)); break;
         }
     };
-    static_assert(NSTAGE >= 3 && NSTAGE <= 4, "wait_loads covers up to 2 slabs in flight");
+    static_assert(NSTAGE >= 3 && NSTAGE <= 5, "wait_loads covers up to 3 slabs in flight");
+    static_assert(3 * LPW <= 63, "vmcnt counts up to 63 operations");
 
     // One step (slab t + 1 exists): make slab t+1 visible (its loads landed
     // in every wave), refill the buffer slab t-1 used with slab t+NSTAGE-1,
@@ -231,13 +233,13 @@ __device__ __forceinline__ void block_of(int tiles_m, int tiles_n, int *tm, int 
     *tn = __builtin_amdgcn_readfirstlane(*tn);
 }
 
-template <int BM, int BN, int WM, int WN, int NREC, class Mode>
+template <int BM, int BN, int WM, int WN, int NREC, class Mode, int NST = NSTAGE>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void single_kernel(Operands op, int tiles_m,
                                                                             int tiles_n) {
-    __shared__ __attribute__((aligned(1024))) uint8_t lds[Cfg<BM, BN, WM, WN, NREC>::LDS];
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[Cfg<BM, BN, WM, WN, NREC, NST>::LDS];
     int tm, tn;
     block_of(tiles_m, tiles_n, &tm, &tn);
-    tile<BM, BN, WM, WN, NREC, Mode>(op, (int64_t)tm * BM, (int64_t)tn * BN, lds);
+    tile<BM, BN, WM, WN, NREC, Mode, NST>(op, (int64_t)tm * BM, (int64_t)tn * BN, lds);
 }
 
 }  // namespace ring

@@ -326,17 +326,18 @@ __global__ __launch_bounds__(256) void split_only_kernel(const float *__restrict
     }
 }
 
-struct SplitShape { int bm, bn, wm, wn; };
-constexpr SplitShape kSplit[] = {{128, 128, 64, 64}, {256, 256, 128, 64}};
+struct SplitShape { int bm, bn, wm, wn, stages; };
+// (deeper rings were measured no faster for this path at N = 8192)
+constexpr SplitShape kSplit[] = {{128, 128, 64, 64, 3}, {256, 256, 128, 64, 3}};
 
-template <int BM, int BN, int WM, int WN>
+template <int BM, int BN, int WM, int WN, int NST>
 hipError_t launch_shape(const moa_gemm_desc &d, const uint8_t *Ap, const uint8_t *Bp, int64_t S,
                         hipStream_t st) {
     const ring::Operands op = split_operands(Ap, Bp, static_cast<float *>(d.C), d.m, d.p, S, d.accumulate);
     const int tiles_m = (int)((d.m + BM - 1) / BM);
     const int tiles_n = (int)((d.p + BN - 1) / BN);
-    hipLaunchKernelGGL((ring::single_kernel<BM, BN, WM, WN, 1, SplitMode>), dim3(tiles_m * tiles_n),
-                       dim3(ring::Cfg<BM, BN, WM, WN, 1>::THREADS), 0, st, op, tiles_m, tiles_n);
+    hipLaunchKernelGGL((ring::single_kernel<BM, BN, WM, WN, 1, SplitMode, NST>), dim3(tiles_m * tiles_n),
+                       dim3(ring::Cfg<BM, BN, WM, WN, 1, NST>::THREADS), 0, st, op, tiles_m, tiles_n);
     return hipGetLastError();
 }
 
@@ -359,7 +360,7 @@ void split_bf16_shape(int v, Plan *p) {
     p->wave_n = s.wn;
     p->lane_m = p->lane_n = 0;
     p->threads = (s.bm / s.wm) * (s.bn / s.wn) * 64;
-    p->lds_bytes = ring::NSTAGE * (s.bm + s.bn) * REC_BYTES;
+    p->lds_bytes = s.stages * (s.bm + s.bn) * REC_BYTES;
 }
 
 hipError_t launch_split_pack(const moa_gemm_desc &d, void *ws, hipStream_t st) {
@@ -393,8 +394,8 @@ hipError_t launch_split_bf16(const moa_gemm_desc &d, const Plan &plan, void *ws,
     const uint8_t *Ap = static_cast<const uint8_t *>(ws);
     const uint8_t *Bp = Ap + ring::array_bytes(d.m, S);
     switch (plan.variant) {
-    case 0: return launch_shape<128, 128, 64, 64>(d, Ap, Bp, S, st);
-    default: return launch_shape<256, 256, 128, 64>(d, Ap, Bp, S, st);
+    case 0: return launch_shape<128, 128, 64, 64, 3>(d, Ap, Bp, S, st);
+    default: return launch_shape<256, 256, 128, 64, 3>(d, Ap, Bp, S, st);
     }
 }
 

@@ -83,7 +83,7 @@ def test_fp8_plan_variants():
            for v in range(2)]
     assert [q["threads"] for q in two] == [256, 512]
     assert all(q["lds_bytes"] == 3 * 2 * 256 * 64 for q in two)
-    assert call(_desc(8, 8, 8, path=F8, flags=moa.MOA_FLAG_VARIANT(2))) == moa.MOA_ERR_INVALID
+    assert call(_desc(8, 8, 8, path=F8, flags=moa.MOA_FLAG_VARIANT(9))) == moa.MOA_ERR_INVALID
     # records: padded rows x ceil(n / 64) x 64 bytes per operand (twice for two terms)
     q1 = moa.moa_plan_query(_desc(100, 200, 300, path=F8))
     q2 = moa.moa_plan_query(_desc(100, 200, 300, path=F8, flags=TWO))
