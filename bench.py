@@ -108,18 +108,31 @@ class Energy:
         return out
 
 
-def measured_traffic(kernel_source: str, record: str):
-    """HBM bytes per launch from the committed counter record, or None when the
-    kernel source has changed since the counters were taken."""
+# the split-BF16 contraction kernel is built from these sources
+SPLIT_KERNEL_SOURCES = ("paper_2306_11148_amd/csrc/split_bf16.hip", "paper_2306_11148_amd/csrc/ring_gemm.h",
+                        "paper_2306_11148_amd/csrc/tile_common.h")
+
+
+def measured_traffic(kernel_sources, record: str):
+    """HBM bytes per launch from the committed counter record, or None when any
+    of the kernel's source files has changed since the counters were taken
+    (sha256 over the files' bytes concatenated in the listed order)."""
     import hashlib
     try:
         rec = json.load(open(os.path.join(ROOT, record)))
-        sha = hashlib.sha256(open(os.path.join(ROOT, kernel_source), "rb").read()).hexdigest()
+        h = hashlib.sha256()
+        for src in kernel_sources:
+            h.update(open(os.path.join(ROOT, src), "rb").read())
     except (OSError, ValueError):
         return None
-    if rec.get("kernel_source_sha256") != sha:
+    if rec.get("kernel_source_sha256") != h.hexdigest() or rec.get("kernel_sources") != list(kernel_sources):
         return None
     return rec.get("hbm_bytes_per_launch")
+
+
+def progress(msg: str):
+    """One line on stderr as each section of the run starts."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
 def timed_loop(fn, reps, torch):
@@ -472,6 +485,7 @@ def main():
         if s != 0:
             raise RuntimeError(moa.moa_last_error())
 
+    progress(f"split-BF16 N={N}: {args.warmup} warm-up + {args.steps} timed steps")
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -493,11 +507,14 @@ def main():
     issued = 3 * flops / (ms * 1e-3) / 1e12
     issued_kernel = 3 * flops / (kernel_ms * 1e-3) / 1e12
 
+    progress(f"ONF N={N}: {args.onf_steps} timed steps")
     onf()
     per_onf, total_onf = timed_loop(onf, args.onf_steps, torch)
     ms_onf = total_onf / args.onf_steps
     tflops_onf = flops / (ms_onf * 1e-3) / 1e12
 
+    if not args.no_energy:
+        progress("energy per call (split-BF16, ONF)")
     energy = None if args.no_energy else Energy()
     e_split = energy_per_call(step, args.energy_seconds, ms, energy, torch)
     e_onf = energy_per_call(onf, args.energy_seconds, ms_onf, energy, torch)
@@ -510,8 +527,14 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
 
+    if not args.no_grouped:
+        progress("grouped products")
     grouped = None if args.no_grouped else grouped_section(torch, moa, inputs)
+    if not args.no_precision:
+        progress("precision workload")
     precision, precision_keep = (None, None) if args.no_precision else precision_section(torch, moa, inputs)
+    if not args.no_serving:
+        progress("serving loop")
     serving = None if args.no_serving else serving_section(torch, moa, inputs, args.serve_rate,
                                                              args.serve_seconds)
 
@@ -520,6 +543,7 @@ def main():
     cpu = None
     err_split = err_onf = None
     if not args.no_cpu_baseline:
+        progress(f"CPU oracle baseline (about {args.cpu_seconds:.0f} s)")
         onf_rows = np.arange(0, N, max(1, N // 64))
         cpu, errs = cpu_baseline(A_h, B_h, C_h, N, args.cpu_seconds, (onf_rows, onf_h[onf_rows]),
                                  precision_keep)
@@ -549,10 +573,9 @@ def main():
                        "min": round(min(per), 4), "max": round(max(per), 4)},
         "roofline": {"bound": "mfma", "achieved": round(issued_kernel, 2), "peak": BF16_PEAK_TF,
                      "unit": "TFLOP/s", "frac": round(issued_kernel / BF16_PEAK_TF, 4),
-                     "traffic": measured_traffic("paper_2306_11148_amd/csrc/split_bf16.hip",
-                                                 "profiles/split_bf16_N8192_traffic.json")
+                     "traffic": measured_traffic(SPLIT_KERNEL_SOURCES, "profiles/split_bf16_N8192_traffic.json")
                      if N == 8192 else None,
-                     "kernel": "split_bf16_kernel",
+                     "kernel": "ring::single_kernel<256, 256, 128, 64, 1, SplitMode, 3> (split-BF16 contraction)",
                      "work_per_launch": "3 * 2 N^3 BF16 matrix-core flop (hi.hi + hi.lo + lo.hi)",
                      "avg_kernel_ms": round(kernel_ms, 4),
                      "kernel_timing": "HIP events on the launch stream (library tracing)",
