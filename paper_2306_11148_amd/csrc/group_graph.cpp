@@ -53,7 +53,7 @@ moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group
         if (s != MOA_OK) return s;
         auto *g = new moa_group();
         hipError_t e = hipSuccess;
-        int64_t tiles = 0;
+        GroupedWork work{0, 0};
         const int cnt = (int)split.size();
         if (cnt > 0) {
             e = hipMalloc(&g->ws, (size_t)split_grouped_workspace_bytes(split.data(), cnt));
@@ -62,7 +62,7 @@ moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group
                 return fail(MOA_ERR_NOMEM, "group workspace: %s", hipGetErrorString(e));
             }
             std::vector<char> host((size_t)split_grouped_desc_bytes(cnt));
-            tiles = split_grouped_layout(split.data(), cnt, g->ws, host.data());
+            work = split_grouped_layout(split.data(), cnt, g->ws, host.data());
             e = hipMemcpy(static_cast<char *>(g->ws) + 256, host.data(), host.size(), hipMemcpyHostToDevice);
             if (e != hipSuccess) {
                 release(g);
@@ -75,7 +75,7 @@ moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group
             return hip_fail(e, "capture stream");
         }
         e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-        if (e == hipSuccess && cnt > 0) e = split_grouped_enqueue(g->ws, cnt, tiles, cs);
+        if (e == hipSuccess && cnt > 0) e = split_grouped_enqueue(g->ws, cnt, work, cs);
         moa_status rs = MOA_OK;
         for (size_t k = 0; e == hipSuccess && rs == MOA_OK && k < single.size(); ++k)
             rs = run_gemm(single[k], cs);

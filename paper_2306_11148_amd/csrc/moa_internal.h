@@ -108,12 +108,17 @@ int64_t split_grouped_workspace_bytes(const moa_gemm_desc *const *members, int c
 int64_t split_grouped_desc_bytes(int count);
 hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, void *workspace,
                                 void *host_staging, hipStream_t stream);
-// The two halves of launch_split_grouped: host layout (returns the tile
-// count; the member array to upload is in host_staging) and the device
-// sequence, which allocates, copies and clears nothing (graph-capturable).
-int64_t split_grouped_layout(const moa_gemm_desc *const *members, int count, void *workspace,
-                             void *host_staging);
-hipError_t split_grouped_enqueue(void *workspace, int count, int64_t tiles, hipStream_t stream);
+// The two halves of launch_split_grouped: host layout (returns the sizes of
+// the contraction and conditioning work lists; the member array to upload is
+// in host_staging) and the device sequence, which allocates, copies and clears
+// nothing (graph-capturable).
+struct GroupedWork {
+    int64_t tiles;                      // contraction tiles over all members
+    int64_t pack_items;                 // conditioning items over all members
+};
+GroupedWork split_grouped_layout(const moa_gemm_desc *const *members, int count, void *workspace,
+                                 void *host_staging);
+hipError_t split_grouped_enqueue(void *workspace, int count, const GroupedWork &work, hipStream_t stream);
 
 hipError_t launch_fp8(const moa_gemm_desc &d, const Plan &plan, void *workspace,
                       hipStream_t stream);

@@ -239,8 +239,11 @@ struct GroupMember {
     float *C;
     uint8_t *Ap, *Bp;                   // records of this member in the workspace
     int64_t m, n, p, S;
-    int64_t first_tile;                 // first work-list id of this member
+    int64_t first_tile;                 // first contraction work-list id of this member
+    int64_t pack_first;                 // first conditioning work-list id of this member
     int32_t tiles_n, accumulate;
+    int32_t row_items;                  // conditioning items: row_items chunk blocks of A,
+    int32_t col_blocks_x;               // then col_blocks_x * ceil(S/4) 64 x 64 blocks of B
 };
 
 __device__ __forceinline__ int find_member(const GroupMember *__restrict__ g, int count, int64_t tile) {
@@ -280,29 +283,36 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void split_grouped_kern
     }
 }
 
-// Grouped conditioning: each workgroup walks a share of every member's
-// chunks (rows of A) and 64 x 64 blocks (columns of B).
-__global__ __launch_bounds__(256) void grouped_pack_rows_kernel(const GroupMember *__restrict__ g,
-                                                                int count) {
-    for (int k = blockIdx.y; k < count; k += gridDim.y) {
-        const GroupMember d = g[k];
-        const int vec = (d.n % 8 == 0) && ((uintptr_t)d.A % 16 == 0);
-        const int64_t chunks = padded_rows(d.m) * d.S * 2;
-        for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < chunks; q += (int64_t)gridDim.x * 256)
-            pack_rows_chunk(d.A, d.m, d.n, d.S, vec, d.Ap, q);
+// Grouped conditioning: one work list over every member, each member
+// contributing row items (256 chunks of A each) followed by 64-column x 64-k
+// blocks of B; workgroups stride through the list, so large and small members
+// share the machine evenly.
+constexpr int PACK_ROW_ITEM = 256;      // chunks per row item (one per thread)
+
+__device__ __forceinline__ int find_pack_member(const GroupMember *__restrict__ g, int count, int64_t item) {
+    int lo = 0, hi = count - 1;         // last member with pack_first <= item
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (g[mid].pack_first <= item) lo = mid; else hi = mid - 1;
     }
+    return lo;
 }
 
-__global__ __launch_bounds__(256) void grouped_pack_cols_kernel(const GroupMember *__restrict__ g,
-                                                                int count) {
+__global__ __launch_bounds__(256) void grouped_pack_kernel(const GroupMember *__restrict__ g, int count,
+                                                           int64_t total) {
     __shared__ __attribute__((aligned(16))) float tile[4 * SLAB][64 + 4];
-    for (int k = blockIdx.y; k < count; k += gridDim.y) {
-        const GroupMember d = g[k];
-        const int vec = (d.p % 4 == 0) && ((uintptr_t)d.B % 16 == 0);
-        const int64_t bx = (d.p + 63) / 64, by = (d.S + 3) / 4;
-        for (int64_t b = blockIdx.x; b < bx * by; b += gridDim.x) {
-            __syncthreads();
-            pack_cols_block(d.B, d.n, d.p, d.S, d.Bp, b % bx, b / bx, tile, vec);
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        const int k = __builtin_amdgcn_readfirstlane(find_pack_member(g, count, item));
+        const GroupMember &d = g[k];
+        const int64_t local = item - d.pack_first;
+        if (local < d.row_items) {
+            const int vec = (d.n % 8 == 0) && ((uintptr_t)d.A % 16 == 0);
+            const int64_t q = local * PACK_ROW_ITEM + threadIdx.x;
+            if (q < padded_rows(d.m) * d.S * 2) pack_rows_chunk(d.A, d.m, d.n, d.S, vec, d.Ap, q);
+        } else {
+            const int vec = (d.p % 4 == 0) && ((uintptr_t)d.B % 16 == 0);
+            const int64_t b = local - d.row_items;
+            pack_cols_block(d.B, d.n, d.p, d.S, d.Bp, b % d.col_blocks_x, b / d.col_blocks_x, tile, vec);
         }
     }
 }
@@ -417,8 +427,8 @@ int64_t split_grouped_desc_bytes(int count) { return (int64_t)count * (int64_t)s
 // Lays out the members (longest k walk first: the tail of the work list holds
 // the cheapest tiles) in `host_staging` and the workspace; returns the tile
 // count. The device member array is at ws + 256, the claim counter at ws.
-int64_t split_grouped_layout(const moa_gemm_desc *const *members, int count, void *ws,
-                             void *host_staging) {
+GroupedWork split_grouped_layout(const moa_gemm_desc *const *members, int count, void *ws,
+                                 void *host_staging) {
     std::vector<int> order(count);
     for (int k = 0; k < count; ++k) order[k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -427,7 +437,7 @@ int64_t split_grouped_layout(const moa_gemm_desc *const *members, int count, voi
     char *base = static_cast<char *>(ws);
     char *rec = base + 256 + align256((int64_t)count * (int64_t)sizeof(GroupMember));
     GroupMember *h = static_cast<GroupMember *>(host_staging);
-    int64_t tiles = 0;
+    int64_t tiles = 0, items = 0;
     for (int q = 0; q < count; ++q) {
         const moa_gemm_desc &d = *members[order[q]];
         GroupMember g;
@@ -443,24 +453,29 @@ int64_t split_grouped_layout(const moa_gemm_desc *const *members, int count, voi
         g.tiles_n = (int32_t)((d.p + GB_N - 1) / GB_N);
         g.accumulate = d.accumulate;
         tiles += ((d.m + GB_M - 1) / GB_M) * g.tiles_n;
+        g.pack_first = items;
+        g.row_items = (int32_t)((padded_rows(d.m) * g.S * 2 + PACK_ROW_ITEM - 1) / PACK_ROW_ITEM);
+        g.col_blocks_x = (int32_t)((d.p + 63) / 64);
+        items += g.row_items + (int64_t)g.col_blocks_x * ((g.S + 3) / 4);
         h[q] = g;
     }
-    return tiles;
+    return {tiles, items};
 }
 
 // The device part of a grouped launch: reset the claim counter, condition
 // every member, run the persistent contraction. Contains no allocation, copy
 // or memset, so it can be captured in a graph and replayed.
-hipError_t split_grouped_enqueue(void *ws, int count, int64_t tiles, hipStream_t st) {
+hipError_t split_grouped_enqueue(void *ws, int count, const GroupedWork &work, hipStream_t st) {
+    const int64_t tiles = work.tiles;
     char *base = static_cast<char *>(ws);
     unsigned long long *counter = reinterpret_cast<unsigned long long *>(base);
     const GroupMember *dev_members = reinterpret_cast<const GroupMember *>(base + 256);
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, st, counter);
-    const unsigned gy = (unsigned)std::min(count, 65535);
-    {
+    if (work.pack_items > 0) {
         TraceScope ts(MOA_K_SPLIT_PACK, st);
-        hipLaunchKernelGGL(grouped_pack_rows_kernel, dim3(32, gy), dim3(256), 0, st, dev_members, count);
-        hipLaunchKernelGGL(grouped_pack_cols_kernel, dim3(16, gy), dim3(256), 0, st, dev_members, count);
+        const int64_t g = std::min<int64_t>(work.pack_items, 8 * kNumCUs);
+        hipLaunchKernelGGL(grouped_pack_kernel, dim3((unsigned)g), dim3(256), 0, st, dev_members, count,
+                           work.pack_items);
     }
     const int64_t grid = std::min<int64_t>(tiles, 2 * kNumCUs);   // two 64 KiB-LDS blocks per CU
     TraceScope ts(MOA_K_SPLIT_GROUPED, st);
@@ -474,12 +489,12 @@ hipError_t split_grouped_enqueue(void *ws, int count, int64_t tiles, hipStream_t
 hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, void *ws,
                                 void *host_staging, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    const int64_t tiles = split_grouped_layout(members, count, ws, host_staging);
+    const GroupedWork work = split_grouped_layout(members, count, ws, host_staging);
     char *base = static_cast<char *>(ws);
     hipError_t e = hipMemcpyAsync(base + 256, host_staging, (size_t)count * sizeof(GroupMember),
                                   hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return e;
-    return split_grouped_enqueue(ws, count, tiles, st);
+    return split_grouped_enqueue(ws, count, work, st);
 }
 
 hipError_t launch_split_only(const float *X, int64_t count, uint16_t *hi, uint16_t *lo,
