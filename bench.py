@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=5000.0)
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-rates", type=str, default=None,
+                    help="comma-separated offered loads (req/s): run only the serving loop at each, "
+                         "one JSON line per rate")
     ap.add_argument("--no-grouped", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--block-sweep", type=str, default=None,
@@ -459,6 +462,12 @@ def main():
         return
     if args.block_sweep:
         block_sweep(args, torch, moa)
+        return
+    if args.serve_rates:
+        for rate in [float(x) for x in args.serve_rates.split(",")]:
+            progress(f"serving loop at {rate:.0f} req/s for {args.serve_seconds:.1f} s")
+            print(json.dumps({"serving_sweep": serving_section(torch, moa, inputs, rate, args.serve_seconds)}),
+                  flush=True)
         return
     N = args.n
     A_h, B_h = inputs.normal_f32(N, N, N, seed=N)

@@ -131,9 +131,11 @@ moa_status moa_gemm(const moa_gemm_desc *desc, void *stream);
 
 /* `count` independent products. Members on the split-BF16 path (including
  * F32 with MOA_PATH_AUTO) are conditioned together and contracted by ONE
- * persistent launch that walks a shared tile list; members on other paths
- * run as single launches on the same stream. No ordering among members. Each
- * result is bitwise the result moa_gemm gives for the same descriptor.
+ * persistent launch that walks a shared tile list; scaled-FP8 members
+ * likewise, one persistent launch per term count; members on the ONF and
+ * FP32 matrix-core paths run as single launches on the same stream. No
+ * ordering among members. Each result is bitwise the result moa_gemm gives
+ * for the same descriptor.
  * Descriptors are read on the host during the call; the array may be reused
  * when the call returns.
  * Errors: as moa_gemm, checked for every member before anything launches;
@@ -146,13 +148,12 @@ moa_status moa_gemm_grouped(const moa_gemm_desc *descs, int64_t count,
  * validates the members as moa_gemm_grouped does, allocates a workspace owned
  * by the group, uploads the member list once and captures the whole grouped
  * launch sequence (conditioning + one persistent contraction for split-BF16
- * members, single launches for ONF and FP32 matrix-core members) in a HIP
- * graph. Each moa_group_launch replays it on `stream` (asynchronously) with
- * the operand pointers given at creation; results are bitwise those of
- * moa_gemm. Members on the FP8 path (per-call scratch) are refused with
- * MOA_ERR_UNSUPPORTED. Creation synchronizes with the device; replays of one
- * group must not overlap each other. moa_group_destroy waits for the group's
- * outstanding work and frees it. */
+ * members and one per FP8 term count, single launches for ONF and FP32
+ * matrix-core members) in a HIP graph. Each moa_group_launch replays it on
+ * `stream` (asynchronously) with the operand pointers given at creation;
+ * results are bitwise those of moa_gemm. Creation synchronizes with the
+ * device; replays of one group must not overlap each other.
+ * moa_group_destroy waits for the group's outstanding work and frees it. */
 typedef struct moa_group moa_group;
 moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group **out);
 moa_status moa_group_launch(moa_group *group, void *stream);
@@ -230,7 +231,8 @@ typedef enum moa_kernel {
     MOA_K_SPLIT_PACK = 7,     /* split-BF16 operand conditioning */
     MOA_K_FP8_QUANT = 8,      /* FP8 operand conditioning */
     MOA_K_SPLIT_GROUPED = 9,  /* grouped persistent split-BF16 contraction */
-    MOA_K_COUNT = 10
+    MOA_K_FP8_GROUPED = 10,   /* grouped persistent scaled-FP8 contraction */
+    MOA_K_COUNT = 11
 } moa_kernel;
 
 typedef struct moa_trace_stat {

@@ -12,8 +12,6 @@ namespace moa {
 
 namespace {
 thread_local std::string t_last_error;
-std::mutex g_pool_mu;
-bool g_pool_ready[64];
 }  // namespace
 
 void set_last_error(const std::string &msg) { t_last_error = msg; }
@@ -73,37 +71,6 @@ moa_status validate(const moa_gemm_desc &d, bool need_ptrs) {
     if (((uintptr_t)d.A % align) || ((uintptr_t)d.B % align) || ((uintptr_t)d.C % align))
         return fail(MOA_ERR_INVALID, "matrix pointers must be aligned to the element size");
     return MOA_OK;
-}
-
-moa_status scratch_alloc(void **ptr, int64_t bytes, hipStream_t stream) {
-    *ptr = nullptr;
-    if (bytes <= 0) return MOA_OK;
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    if (dev >= 0 && dev < 64) {
-        std::lock_guard<std::mutex> lk(g_pool_mu);
-        if (!g_pool_ready[dev]) {
-            // Keep freed scratch in the pool: repeated calls then allocate
-            // without a trip to the driver.
-            hipMemPool_t pool;
-            if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
-                uint64_t thr = UINT64_MAX;
-                (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr);
-            }
-            g_pool_ready[dev] = true;
-        }
-    }
-    e = hipMallocAsync(ptr, (size_t)bytes, stream);
-    if (e != hipSuccess) {
-        (void)hipGetLastError();
-        return fail(MOA_ERR_NOMEM, "scratch of %lld bytes: %s", (long long)bytes, hipGetErrorString(e));
-    }
-    return MOA_OK;
-}
-
-void scratch_free(void *ptr, hipStream_t stream) {
-    if (ptr) (void)hipFreeAsync(ptr, stream);
 }
 
 moa_status run_gemm(const moa_gemm_desc &d, hipStream_t stream) {

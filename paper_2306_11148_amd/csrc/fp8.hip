@@ -21,6 +21,9 @@
 // keeps the residual codes in a second record array per operand. The
 // contraction is the record-tile ring of ring_gemm.h with
 // v_mfma_scale_f32_32x32x64_f8f6f4 steps.
+#include <algorithm>
+#include <vector>
+
 #include "moa_internal.h"
 #include "ring_gemm.h"
 #include "tile_common.h"
@@ -81,12 +84,9 @@ __global__ void fill_u32_kernel(uint32_t *x, int64_t count) {
     if (t < count) x[t] = 0u;
 }
 
-// One wave per row of A: e_i from amax |A[i, :]|.
-__global__ __launch_bounds__(256) void row_exp_kernel(const float *__restrict__ A, int64_t m, int64_t n,
-                                                      int vec, int32_t *__restrict__ e) {
-    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    const int lane = threadIdx.x & 63;
-    if (i >= m) return;
+// One wave: e_i of row i of A from amax |A[i, :]| (all 64 lanes take part).
+__device__ __forceinline__ void row_exp_wave(const float *__restrict__ A, int64_t i, int64_t n, int vec,
+                                             int lane, int32_t *__restrict__ e) {
     const float *row = A + i * n;
     float mx = 0.0f;
     if (vec) {
@@ -104,13 +104,17 @@ __global__ __launch_bounds__(256) void row_exp_kernel(const float *__restrict__ 
     if (lane == 0) e[i] = pow2_exponent(mx);
 }
 
-// Column amax of B: each thread takes one column over a band of 256 rows.
+// One wave per row of A.
+__global__ __launch_bounds__(256) void row_exp_kernel(const float *__restrict__ A, int64_t m, int64_t n,
+                                                      int vec, int32_t *__restrict__ e) {
+    const int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (i < m) row_exp_wave(A, i, n, vec, threadIdx.x & 63, e);
+}
+
+// Column amax of B: one thread per column over a band of COL_BAND rows.
 constexpr int COL_BAND = 256;
-__global__ __launch_bounds__(256) void col_amax_kernel(const float *__restrict__ B, int64_t n,
-                                                       int64_t p, uint32_t *__restrict__ amax) {
-    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int64_t k0 = (int64_t)blockIdx.y * COL_BAND;
-    if (j >= p) return;
+__device__ __forceinline__ void col_amax_thread(const float *__restrict__ B, int64_t n, int64_t p, int64_t j,
+                                                int64_t k0, uint32_t *__restrict__ amax) {
     float mx = 0.0f;
     const int64_t k1 = min(n, k0 + COL_BAND);
 #pragma unroll 16
@@ -118,10 +122,55 @@ __global__ __launch_bounds__(256) void col_amax_kernel(const float *__restrict__
     atomicMax(&amax[j], __float_as_uint(mx));
 }
 
+__global__ __launch_bounds__(256) void col_amax_kernel(const float *__restrict__ B, int64_t n,
+                                                       int64_t p, uint32_t *__restrict__ amax) {
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j < p) col_amax_thread(B, n, p, j, (int64_t)blockIdx.y * COL_BAND, amax);
+}
+
 // --------------------------------------------------- record conditioning --
 
 // Rows of A -> records. Chunk q = 16 codes of one record (4 per record);
-// consecutive threads fill one KiB record tile contiguously.
+// consecutive chunks fill one KiB record tile contiguously.
+template <bool TWO>
+__device__ __forceinline__ void pack_rows_fp8_chunk(const float *__restrict__ A, int64_t m, int64_t n,
+                                                    int64_t S, int vec, const int32_t *__restrict__ e,
+                                                    uint8_t *__restrict__ qa, uint8_t *__restrict__ la,
+                                                    int64_t q) {
+    const int c = (int)(q & 3);
+    const int64_t rr = (q >> 2) % GROUP;
+    const int64_t gs = (q >> 2) / GROUP;
+    const int64_t s = gs % S, g = gs / S;
+    const int64_t r = g * GROUP + rr;
+    const int64_t k = s * SLAB8 + c * 16;
+    float x[16];
+#pragma unroll
+    for (int t = 0; t < 16; ++t) x[t] = 0.0f;
+    if (r < m) {
+        const float *src = A + r * n + k;
+        if (vec && k + 16 <= n) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const float4 v = reinterpret_cast<const float4 *>(src)[u];
+                x[4 * u] = v.x; x[4 * u + 1] = v.y; x[4 * u + 2] = v.z; x[4 * u + 3] = v.w;
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < 16; ++t)
+                if (k + t < n) x[t] = src[t];
+        }
+        const int er = e[r];
+#pragma unroll
+        for (int t = 0; t < 16; ++t) x[t] = ldexpf(x[t], er);
+    }
+    uint32_t hi[4], lo[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int u = 0; u < 4; ++u) quant4(x + 4 * u, TWO, &hi[u], &lo[u]);
+    const int64_t at = ring::rec_byte(r, s, S) + c * 16;
+    *reinterpret_cast<uint4 *>(qa + at) = make_uint4(hi[0], hi[1], hi[2], hi[3]);
+    if (TWO) *reinterpret_cast<uint4 *>(la + at) = make_uint4(lo[0], lo[1], lo[2], lo[3]);
+}
+
 template <bool TWO>
 __global__ __launch_bounds__(256) void pack_rows_fp8_kernel(const float *__restrict__ A, int64_t m,
                                                             int64_t n, int64_t S, int vec,
@@ -129,40 +178,8 @@ __global__ __launch_bounds__(256) void pack_rows_fp8_kernel(const float *__restr
                                                             uint8_t *__restrict__ qa,
                                                             uint8_t *__restrict__ la) {
     const int64_t chunks = padded_rows(m) * S * 4;
-    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < chunks; q += (int64_t)gridDim.x * 256) {
-        const int c = (int)(q & 3);
-        const int64_t rr = (q >> 2) % GROUP;
-        const int64_t gs = (q >> 2) / GROUP;
-        const int64_t s = gs % S, g = gs / S;
-        const int64_t r = g * GROUP + rr;
-        const int64_t k = s * SLAB8 + c * 16;
-        float x[16];
-#pragma unroll
-        for (int t = 0; t < 16; ++t) x[t] = 0.0f;
-        if (r < m) {
-            const float *src = A + r * n + k;
-            if (vec && k + 16 <= n) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    const float4 v = reinterpret_cast<const float4 *>(src)[u];
-                    x[4 * u] = v.x; x[4 * u + 1] = v.y; x[4 * u + 2] = v.z; x[4 * u + 3] = v.w;
-                }
-            } else {
-#pragma unroll
-                for (int t = 0; t < 16; ++t)
-                    if (k + t < n) x[t] = src[t];
-            }
-            const int er = e[r];
-#pragma unroll
-            for (int t = 0; t < 16; ++t) x[t] = ldexpf(x[t], er);
-        }
-        uint32_t hi[4], lo[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-        for (int u = 0; u < 4; ++u) quant4(x + 4 * u, TWO, &hi[u], &lo[u]);
-        const int64_t at = ring::rec_byte(r, s, S) + c * 16;
-        *reinterpret_cast<uint4 *>(qa + at) = make_uint4(hi[0], hi[1], hi[2], hi[3]);
-        if (TWO) *reinterpret_cast<uint4 *>(la + at) = make_uint4(lo[0], lo[1], lo[2], lo[3]);
-    }
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q < chunks; q += (int64_t)gridDim.x * 256)
+        pack_rows_fp8_chunk<TWO>(A, m, n, S, vec, e, qa, la, q);
 }
 
 // Columns of B -> records (transposed), 64 columns x one slab (64 k) per
@@ -182,6 +199,66 @@ __device__ __forceinline__ uint32_t byte_column(const uint32_t w[4], int c) {
            (((w[3] >> sh) & 0xFFu) << 24);
 }
 
+// Column exponents of the 64 columns of block bx (threads 0 .. 63).
+__device__ __forceinline__ void write_col_exps(const uint32_t *__restrict__ amax, int64_t p, int64_t bx,
+                                               int32_t *__restrict__ f_out) {
+    const int64_t j = bx * 64 + threadIdx.x;
+    if (threadIdx.x < 64 && j < p) f_out[j] = pow2_exponent(__uint_as_float(amax[j]));
+}
+
+// Block (bx, s): columns 64 bx .. 64 bx + 63, slab s < S. All 256 threads
+// take part; the LDS tiles are free again when it returns.
+template <bool TWO>
+__device__ __forceinline__ void pack_cols_fp8_block(const float *__restrict__ B, int64_t n, int64_t p,
+                                                    int64_t S, int vec, const uint32_t *__restrict__ amax,
+                                                    uint8_t *__restrict__ qb, uint8_t *__restrict__ lb,
+                                                    int64_t bx, int64_t s, uint32_t *tq, uint32_t *tl) {
+    const int t = threadIdx.x;
+    const int cg = t & 15, kq = t >> 4;
+    const int64_t j0 = bx * 64;
+    const int64_t j = j0 + 4 * cg;                 // this thread's first column
+    int fcol[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) fcol[u] = (j + u < p) ? pow2_exponent(__uint_as_float(amax[j + u])) : 0;
+    uint32_t wq[4], wl[4] = {0u, 0u, 0u, 0u};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t k = s * SLAB8 + 4 * kq + i;
+        float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (k < n) {
+            const float *row = B + k * p + j;
+            if (vec && j + 4 <= p) {
+                const float4 x = *reinterpret_cast<const float4 *>(row);
+                v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    if (j + u < p) v[u] = row[u];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) v[u] = ldexpf(v[u], fcol[u]);
+        quant4(v, TWO, &wq[i], &wl[i]);
+    }
+    __syncthreads();                               // earlier readers of the tiles are done
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        tq[(4 * cg + u) * TSTRIDE + kq] = byte_column(wq, u);
+        if (TWO) tl[(4 * cg + u) * TSTRIDE + kq] = byte_column(wl, u);
+    }
+    __syncthreads();
+    const int jj = t >> 2, c = t & 3;              // writer: column j0 + jj, chunk c
+    if (j0 + jj < padded_rows(p)) {
+        const uint32_t *r = tq + jj * TSTRIDE + 4 * c;
+        const int64_t at = ring::rec_byte(j0 + jj, s, S) + 16 * c;
+        *reinterpret_cast<uint4 *>(qb + at) = make_uint4(r[0], r[1], r[2], r[3]);
+        if (TWO) {
+            const uint32_t *q = tl + jj * TSTRIDE + 4 * c;
+            *reinterpret_cast<uint4 *>(lb + at) = make_uint4(q[0], q[1], q[2], q[3]);
+        }
+    }
+}
+
 template <bool TWO>
 __global__ __launch_bounds__(256) void pack_cols_fp8_kernel(const float *__restrict__ B, int64_t n,
                                                             int64_t p, int64_t S, int vec,
@@ -191,56 +268,9 @@ __global__ __launch_bounds__(256) void pack_cols_fp8_kernel(const float *__restr
                                                             uint8_t *__restrict__ lb) {
     __shared__ uint32_t tq[64 * TSTRIDE];
     __shared__ uint32_t tl[TWO ? 64 * TSTRIDE : 1];
-    const int t = threadIdx.x;
-    const int cg = t & 15, kq = t >> 4;
-    const int64_t j0 = (int64_t)blockIdx.x * 64;
-    const int64_t j = j0 + 4 * cg;                 // this thread's first column
-    int fcol[4];
-#pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        fcol[u] = (j + u < p) ? pow2_exponent(__uint_as_float(amax[j + u])) : 0;
-        if (blockIdx.y == 0 && kq == 0 && j + u < p) f_out[j + u] = fcol[u];
-    }
-    const int jj = t >> 2, c = t & 3;              // writer: column j0 + jj, chunk c
-    const bool writes = j0 + jj < padded_rows(p);
-    for (int64_t s = blockIdx.y; s < S; s += gridDim.y) {
-        uint32_t wq[4], wl[4] = {0u, 0u, 0u, 0u};
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const int64_t k = s * SLAB8 + 4 * kq + i;
-            float v[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-            if (k < n) {
-                const float *row = B + k * p + j;
-                if (vec && j + 4 <= p) {
-                    const float4 x = *reinterpret_cast<const float4 *>(row);
-                    v[0] = x.x; v[1] = x.y; v[2] = x.z; v[3] = x.w;
-                } else {
-#pragma unroll
-                    for (int u = 0; u < 4; ++u)
-                        if (j + u < p) v[u] = row[u];
-                }
-            }
-#pragma unroll
-            for (int u = 0; u < 4; ++u) v[u] = ldexpf(v[u], fcol[u]);
-            quant4(v, TWO, &wq[i], &wl[i]);
-        }
-        __syncthreads();                           // the previous step's reads of the tiles are done
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            tq[(4 * cg + u) * TSTRIDE + kq] = byte_column(wq, u);
-            if (TWO) tl[(4 * cg + u) * TSTRIDE + kq] = byte_column(wl, u);
-        }
-        __syncthreads();
-        if (writes) {
-            const uint32_t *r = tq + jj * TSTRIDE + 4 * c;
-            const int64_t at = ring::rec_byte(j0 + jj, s, S) + 16 * c;
-            *reinterpret_cast<uint4 *>(qb + at) = make_uint4(r[0], r[1], r[2], r[3]);
-            if (TWO) {
-                const uint32_t *q = tl + jj * TSTRIDE + 4 * c;
-                *reinterpret_cast<uint4 *>(lb + at) = make_uint4(q[0], q[1], q[2], q[3]);
-            }
-        }
-    }
+    if (blockIdx.y == 0) write_col_exps(amax, p, blockIdx.x, f_out);
+    for (int64_t s = blockIdx.y; s < S; s += gridDim.y)
+        pack_cols_fp8_block<TWO>(B, n, p, S, vec, amax, qb, lb, blockIdx.x, s, tq, tl);
 }
 
 // ------------------------------------------- row-major codes (exposed API) --
@@ -361,6 +391,83 @@ template <bool TWO> struct Fp8Mode {
     }
 };
 
+// ------------------------------------------------ grouped (persistent) --
+// Independent FP8 products of one term count share one launch sequence:
+// clear (claim counter + every member's column amax), scales (row exponents
+// and column amax of every member), records (every member's rows and column
+// blocks), contraction (persistent workgroups claim tiles of all members from
+// one counter). The scale and record steps each walk one work list over all
+// members, so large and small members share the machine evenly. Every element
+// sees the operation sequence of the single-product path, so results are
+// bitwise those of moa_gemm.
+struct Fp8Member {
+    ring::Operands op;                  // the contraction's view (read by ring::tile in place)
+    const float *A, *B;
+    uint8_t *qa, *la, *qb, *lb;         // record arrays (la, lb: two-term only)
+    int32_t *e, *f;                     // row / column exponents
+    uint32_t *amaxB;                    // column amax (bit patterns)
+    int64_t m, n, p, S;
+    int64_t first_tile;                 // first contraction work-list id
+    int64_t scale_first;                // first scale work-list id
+    int64_t pack_first;                 // first record work-list id
+    int32_t tiles_n, reserved;
+    int32_t row_items;                  // scale items: row_items (4 rows each), then
+    int32_t col_amax_x;                 //   col_amax_x * ceil(n / COL_BAND) column bands
+    int32_t pack_row_items;             // record items: pack_row_items (256 chunks each), then
+    int32_t pack_col_x;                 //   pack_col_x * max(S, 1) 64-column blocks
+    int32_t vec_a, vec_b;
+};
+
+template <int64_t Fp8Member::*F>
+__device__ __forceinline__ int find_member(const Fp8Member *__restrict__ g, int count, int64_t item) {
+    int lo = 0, hi = count - 1;         // last member whose list starts at or before item
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (g[mid].*F <= item) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
+__global__ __launch_bounds__(256) void grouped_scales_kernel(const Fp8Member *__restrict__ g, int count,
+                                                             int64_t total) {
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        const int k = __builtin_amdgcn_readfirstlane(find_member<&Fp8Member::scale_first>(g, count, item));
+        const Fp8Member &d = g[k];
+        const int64_t local = item - d.scale_first;
+        if (local < d.row_items) {
+            const int64_t i = local * 4 + wave;
+            if (i < d.m) row_exp_wave(d.A, i, d.n, d.vec_a, lane, d.e);
+        } else {
+            const int64_t b = local - d.row_items;
+            const int64_t j = (b % d.col_amax_x) * 256 + threadIdx.x;
+            if (j < d.p) col_amax_thread(d.B, d.n, d.p, j, (b / d.col_amax_x) * COL_BAND, d.amaxB);
+        }
+    }
+}
+
+template <bool TWO>
+__global__ __launch_bounds__(256) void grouped_records_kernel(const Fp8Member *__restrict__ g, int count,
+                                                              int64_t total) {
+    __shared__ uint32_t tq[64 * TSTRIDE];
+    __shared__ uint32_t tl[TWO ? 64 * TSTRIDE : 1];
+    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
+        const int k = __builtin_amdgcn_readfirstlane(find_member<&Fp8Member::pack_first>(g, count, item));
+        const Fp8Member &d = g[k];
+        const int64_t local = item - d.pack_first;
+        if (local < d.pack_row_items) {
+            const int64_t q = local * 256 + threadIdx.x;
+            if (q < padded_rows(d.m) * d.S * 4)
+                pack_rows_fp8_chunk<TWO>(d.A, d.m, d.n, d.S, d.vec_a, d.e, d.qa, d.la, q);
+        } else {
+            const int64_t b = local - d.pack_row_items;
+            const int64_t bx = b % d.pack_col_x, s = b / d.pack_col_x;
+            if (s == 0) write_col_exps(d.amaxB, d.p, bx, d.f);
+            if (s < d.S) pack_cols_fp8_block<TWO>(d.B, d.n, d.p, d.S, d.vec_b, d.amaxB, d.qb, d.lb, bx, s, tq, tl);
+        }
+    }
+}
+
 struct Fp8Shape { int bm, bn, wm, wn, stages; };
 constexpr Fp8Shape kOne[] = {{128, 128, 64, 64, 3}, {256, 256, 128, 64, 3}, {256, 256, 128, 64, 4},
                              {256, 256, 128, 64, 5}};
@@ -380,6 +487,33 @@ hipError_t launch_shape(const ring::Operands &op, hipStream_t st) {
                        dim3(ring::Cfg<BM, BN, WM, WN, NREC, NST>::THREADS), 0, st, op, tiles_m, tiles_n);
     return hipGetLastError();
 }
+
+template <bool TWO, int BM, int BN, int WM, int WN, int NST>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void fp8_grouped_kernel(
+    const Fp8Member *__restrict__ g, int count, int64_t total_tiles, unsigned long long *__restrict__ counter) {
+    constexpr int NREC = TWO ? 2 : 1;
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[ring::Cfg<BM, BN, WM, WN, NREC, NST>::LDS];
+    __shared__ int64_t s_tile;
+    for (;;) {
+        __syncthreads();                // nobody still reads lds or s_tile
+        if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(counter, 1ull);
+        __syncthreads();
+        const int64_t tile = s_tile;
+        if (tile >= total_tiles) break;
+        const int k = __builtin_amdgcn_readfirstlane(find_member<&Fp8Member::first_tile>(g, count, tile));
+        const Fp8Member &d = g[k];
+        const int64_t local = tile - d.first_tile;
+        const int64_t tm = local / d.tiles_n, tn = local - tm * d.tiles_n;
+        ring::tile<BM, BN, WM, WN, NREC, Fp8Mode<TWO>, NST>(d.op, __builtin_amdgcn_readfirstlane((int)tm) * (int64_t)BM,
+                                                            __builtin_amdgcn_readfirstlane((int)tn) * (int64_t)BN, lds);
+    }
+}
+
+// Block shapes of the persistent launch: two terms 128 x 128 with 8 waves and
+// a 4-deep ring (128 KiB LDS, one workgroup per CU); one term 128 x 128 with
+// 4 waves and a 3-deep ring (48 KiB, three per CU).
+constexpr int G_BM = 128, G_BN = 128;
+constexpr int G_PER_CU_TWO = 1, G_PER_CU_ONE = 3;
 
 int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
@@ -499,6 +633,129 @@ hipError_t launch_fp8(const moa_gemm_desc &d, const Plan &plan, void *ws, hipStr
     case 2: return launch_shape<256, 256, 128, 64, false, 4>(op, st);
     default: return launch_shape<256, 256, 128, 64, false, 5>(op, st);
     }
+}
+
+int64_t fp8_grouped_desc_bytes(int count) { return (int64_t)count * (int64_t)sizeof(Fp8Member); }
+
+namespace {
+int64_t member_bytes(const moa_gemm_desc &d, bool two) {
+    const int64_t S = (d.n + SLAB8 - 1) / SLAB8;
+    const int64_t rec = align256(ring::array_bytes(d.m, S)) + align256(ring::array_bytes(d.p, S));
+    return align256(4 * d.m) + align256(4 * d.p) + (two ? 2 : 1) * rec;
+}
+int64_t header_bytes(const moa_gemm_desc *const *members, int count) {
+    int64_t cols = 0;
+    for (int k = 0; k < count; ++k) cols += members[k]->p;
+    return align256(8 + 4 * cols);     // claim counter, then every member's column amax
+}
+}  // namespace
+
+int64_t fp8_grouped_workspace_bytes(const moa_gemm_desc *const *members, int count, bool two) {
+    int64_t b = header_bytes(members, count) + align256(fp8_grouped_desc_bytes(count));
+    for (int k = 0; k < count; ++k) b += member_bytes(*members[k], two);
+    return b;
+}
+
+// Workspace: [counter u64 | amax of every member][member table][per member:
+// e, f, record arrays]. Members are listed longest k walk first.
+Fp8GroupWork fp8_grouped_layout(const moa_gemm_desc *const *members, int count, bool two, void *ws,
+                                void *host_staging) {
+    std::vector<int> order(count);
+    for (int k = 0; k < count; ++k) order[k] = k;
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return members[a]->n > members[b]->n; });
+    char *base = static_cast<char *>(ws);
+    uint32_t *amax = reinterpret_cast<uint32_t *>(base + 8);
+    char *cur = base + header_bytes(members, count) + align256(fp8_grouped_desc_bytes(count));
+    Fp8Member *h = static_cast<Fp8Member *>(host_staging);
+    Fp8GroupWork w{0, 0, 0, 2, header_bytes(members, count)};
+    for (int q = 0; q < count; ++q) {
+        const moa_gemm_desc &d = *members[order[q]];
+        Fp8Member g;
+        g.A = static_cast<const float *>(d.A);
+        g.B = static_cast<const float *>(d.B);
+        g.m = d.m; g.n = d.n; g.p = d.p;
+        g.S = (d.n + SLAB8 - 1) / SLAB8;
+        g.amaxB = amax;
+        amax += d.p;
+        w.clear_words += d.p;
+        g.e = reinterpret_cast<int32_t *>(cur); cur += align256(4 * d.m);
+        g.f = reinterpret_cast<int32_t *>(cur); cur += align256(4 * d.p);
+        g.qa = reinterpret_cast<uint8_t *>(cur); cur += align256(ring::array_bytes(d.m, g.S));
+        g.qb = reinterpret_cast<uint8_t *>(cur); cur += align256(ring::array_bytes(d.p, g.S));
+        g.la = g.lb = nullptr;
+        if (two) {
+            g.la = reinterpret_cast<uint8_t *>(cur); cur += align256(ring::array_bytes(d.m, g.S));
+            g.lb = reinterpret_cast<uint8_t *>(cur); cur += align256(ring::array_bytes(d.p, g.S));
+        }
+        g.op.a0 = g.qa; g.op.a1 = g.la;
+        g.op.b0 = g.qb; g.op.b1 = g.lb;
+        g.op.C = static_cast<float *>(d.C);
+        g.op.row_exp = g.e;
+        g.op.col_exp = g.f;
+        g.op.m = d.m; g.op.p = d.p; g.op.S = g.S;
+        g.op.accumulate = d.accumulate;
+        g.vec_a = (d.n % 4 == 0) && ((uintptr_t)d.A % 16 == 0);
+        g.vec_b = (d.p % 4 == 0) && ((uintptr_t)d.B % 16 == 0);
+        g.tiles_n = (int32_t)((d.p + G_BN - 1) / G_BN);
+        g.first_tile = w.tiles;
+        w.tiles += ((d.m + G_BM - 1) / G_BM) * g.tiles_n;
+        g.row_items = (int32_t)((d.m + 3) / 4);
+        g.col_amax_x = (int32_t)((d.p + 255) / 256);
+        g.scale_first = w.scale_items;
+        w.scale_items += g.row_items + (int64_t)g.col_amax_x * ((d.n + COL_BAND - 1) / COL_BAND);
+        g.pack_row_items = (int32_t)((padded_rows(d.m) * g.S * 4 + 255) / 256);
+        g.pack_col_x = (int32_t)((d.p + 63) / 64);
+        g.pack_first = w.pack_items;
+        w.pack_items += g.pack_row_items + (int64_t)g.pack_col_x * (g.S > 0 ? g.S : 1);
+        h[q] = g;
+    }
+    return w;
+}
+
+hipError_t fp8_grouped_enqueue(void *ws, int count, bool two, const Fp8GroupWork &w, hipStream_t st) {
+    char *base = static_cast<char *>(ws);
+    unsigned long long *counter = reinterpret_cast<unsigned long long *>(base);
+    const Fp8Member *dev = reinterpret_cast<const Fp8Member *>(base + w.table_offset);
+    {
+        TraceScope ts(MOA_K_FP8_QUANT, st);
+        hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((w.clear_words + 255) / 256)), dim3(256), 0, st,
+                           reinterpret_cast<uint32_t *>(base), w.clear_words);
+        if (w.scale_items > 0)
+            hipLaunchKernelGGL(grouped_scales_kernel, dim3((unsigned)std::min<int64_t>(w.scale_items, 8 * kNumCUs)),
+                               dim3(256), 0, st, dev, count, w.scale_items);
+        if (w.pack_items > 0) {
+            const dim3 grid((unsigned)std::min<int64_t>(w.pack_items, 8 * kNumCUs));
+            if (two) hipLaunchKernelGGL(grouped_records_kernel<true>, grid, dim3(256), 0, st, dev, count, w.pack_items);
+            else hipLaunchKernelGGL(grouped_records_kernel<false>, grid, dim3(256), 0, st, dev, count, w.pack_items);
+        }
+    }
+    TraceScope ts(MOA_K_FP8_GROUPED, st);
+    if (w.tiles > 0) {
+        if (two) {
+            constexpr int WM = 64, WN = 32, NST = 4;
+            hipLaunchKernelGGL((fp8_grouped_kernel<true, G_BM, G_BN, WM, WN, NST>),
+                               dim3((unsigned)std::min<int64_t>(w.tiles, G_PER_CU_TWO * kNumCUs)),
+                               dim3(ring::Cfg<G_BM, G_BN, WM, WN, 2, NST>::THREADS), 0, st, dev, count, w.tiles,
+                               counter);
+        } else {
+            constexpr int WM = 64, WN = 64, NST = 3;
+            hipLaunchKernelGGL((fp8_grouped_kernel<false, G_BM, G_BN, WM, WN, NST>),
+                               dim3((unsigned)std::min<int64_t>(w.tiles, G_PER_CU_ONE * kNumCUs)),
+                               dim3(ring::Cfg<G_BM, G_BN, WM, WN, 1, NST>::THREADS), 0, st, dev, count, w.tiles,
+                               counter);
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_fp8_grouped(const moa_gemm_desc *const *members, int count, bool two, void *ws,
+                              void *host_staging, hipStream_t st) {
+    if (count <= 0) return hipSuccess;
+    const Fp8GroupWork w = fp8_grouped_layout(members, count, two, ws, host_staging);
+    hipError_t e = hipMemcpyAsync(static_cast<char *>(ws) + w.table_offset, host_staging,
+                                  (size_t)fp8_grouped_desc_bytes(count), hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return e;
+    return fp8_grouped_enqueue(ws, count, two, w, st);
 }
 
 hipError_t launch_quantise_fp8(const float *A, int64_t m, int64_t n, const float *B, int64_t p,

@@ -1,15 +1,18 @@
 // Prepared groups: the grouped launch of a fixed set of products captured
-// once in a HIP graph and replayed. The workspace and the device member list
-// are owned by the group; the captured sequence (counter reset, grouped
-// conditioning, persistent contraction, and single launches of ONF / FP32
-// matrix-core members) allocates, copies and clears nothing, so every replay
-// repeats exactly the same work on the same buffers.
+// once in a HIP graph and replayed. The workspaces and the device member
+// tables are owned by the group; the captured sequence (per persistent
+// launch: counter reset, grouped conditioning, persistent contraction -- one
+// for split-BF16 members and one per FP8 term count -- then single launches
+// of ONF / FP32 matrix-core members) allocates, copies and clears nothing
+// outside kernels, so every replay repeats exactly the same work on the same
+// buffers.
 #include <vector>
 
 #include "moa_internal.h"
 
 struct moa_group {
-    void *ws = nullptr;
+    void *ws = nullptr;                 // split-BF16 members
+    void *ws8[2] = {nullptr, nullptr};  // FP8 members, one and two terms
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -23,6 +26,8 @@ void release(moa_group *g) {
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     if (g->ws) (void)hipFree(g->ws);   // hipFree waits for work using it
+    for (void *w : g->ws8)
+        if (w) (void)hipFree(w);
     delete g;
 }
 
@@ -35,7 +40,7 @@ moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group
         if (!out) return fail(MOA_ERR_INVALID, "null output");
         *out = nullptr;
         if (count < 0 || (count > 0 && !descs)) return fail(MOA_ERR_INVALID, "bad descriptor array");
-        std::vector<const moa_gemm_desc *> split;
+        std::vector<const moa_gemm_desc *> split, fp8[2];
         std::vector<moa_gemm_desc> single;
         for (int64_t k = 0; k < count; ++k) {
             const moa_gemm_desc &d = descs[k];
@@ -45,9 +50,9 @@ moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group
             Plan pl;
             if ((s = make_plan(d, &pl)) != MOA_OK) return s;
             if (pl.path == MOA_PATH_SPLIT_BF16) split.push_back(&d);
+            else if (pl.path == MOA_PATH_FP8_SCALED) fp8[(d.flags & MOA_FLAG_FP8_TWO_TERM) ? 1 : 0].push_back(&d);
             else if (pl.workspace_bytes == 0) single.push_back(d);
-            else return fail(MOA_ERR_UNSUPPORTED, "member %lld needs per-call scratch (FP8): not in a prepared group",
-                             (long long)k);
+            else return fail(MOA_ERR_UNSUPPORTED, "member %lld needs per-call scratch", (long long)k);
         }
         moa_status s = check_group_overlap(descs, count);
         if (s != MOA_OK) return s;
@@ -74,8 +79,30 @@ moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group
             release(g);
             return hip_fail(e, "capture stream");
         }
+        Fp8GroupWork work8[2]{};
+        for (int two = 0; two < 2; ++two) {
+            const int c8 = (int)fp8[two].size();
+            if (c8 == 0) continue;
+            e = hipMalloc(&g->ws8[two], (size_t)fp8_grouped_workspace_bytes(fp8[two].data(), c8, two != 0));
+            if (e != hipSuccess) {
+                (void)hipStreamDestroy(cs);
+                release(g);
+                return fail(MOA_ERR_NOMEM, "group workspace: %s", hipGetErrorString(e));
+            }
+            std::vector<char> host((size_t)fp8_grouped_desc_bytes(c8));
+            work8[two] = fp8_grouped_layout(fp8[two].data(), c8, two != 0, g->ws8[two], host.data());
+            e = hipMemcpy(static_cast<char *>(g->ws8[two]) + work8[two].table_offset, host.data(), host.size(),
+                          hipMemcpyHostToDevice);
+            if (e != hipSuccess) {
+                (void)hipStreamDestroy(cs);
+                release(g);
+                return hip_fail(e, "group member upload");
+            }
+        }
         e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e == hipSuccess && cnt > 0) e = split_grouped_enqueue(g->ws, cnt, work, cs);
+        for (int two = 0; two < 2 && e == hipSuccess; ++two)
+            if (!fp8[two].empty()) e = fp8_grouped_enqueue(g->ws8[two], (int)fp8[two].size(), two != 0, work8[two], cs);
         moa_status rs = MOA_OK;
         for (size_t k = 0; e == hipSuccess && rs == MOA_OK && k < single.size(); ++k)
             rs = run_gemm(single[k], cs);

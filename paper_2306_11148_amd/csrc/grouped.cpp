@@ -2,8 +2,9 @@
 //
 // Members on the split-BF16 path (the path of the batching workload) are
 // conditioned together and contracted by one persistent launch that walks a
-// shared tile list. Members on the other paths run as single launches, in
-// order, on the same stream. The member descriptors of the persistent launch
+// shared tile list; scaled-FP8 members likewise, one sequence per term count.
+// Members on the ONF and FP32 matrix-core paths run as single launches, in
+// order, on the same stream. The member tables of the persistent launches
 // travel to the device through pinned staging buffers that are recycled once
 // the stream has consumed them.
 #include <algorithm>
@@ -90,35 +91,64 @@ moa_status check_group_overlap(const moa_gemm_desc *descs, int64_t count) {
     return MOA_OK;
 }
 
+namespace {
+
+// One persistent launch sequence over `list`: workspace from the stream-ordered
+// pool, member table through pinned staging.
+template <class Bytes, class Launch>
+moa_status run_list(const std::vector<const moa_gemm_desc *> &list, int64_t desc_bytes, Bytes ws_bytes,
+                    Launch launch, hipStream_t stream) {
+    if (list.empty()) return MOA_OK;
+    if (list.size() > (size_t)INT32_MAX) return fail(MOA_ERR_INVALID, "too many members");
+    const int cnt = (int)list.size();
+    void *ws = nullptr;
+    moa_status s = scratch_alloc(&ws, ws_bytes(list.data(), cnt), stream);
+    if (s != MOA_OK) return s;
+    Staging st;
+    s = staging_acquire((size_t)desc_bytes, &st);
+    if (s != MOA_OK) {
+        scratch_free(ws, stream);
+        return s;
+    }
+    const hipError_t e = launch(list.data(), cnt, ws, st.ptr);
+    staging_release(st, stream);
+    scratch_free(ws, stream);
+    if (e != hipSuccess) return hip_fail(e, "grouped launch");
+    return MOA_OK;
+}
+
+}  // namespace
+
 moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t stream) {
-    std::vector<const moa_gemm_desc *> split;
+    std::vector<const moa_gemm_desc *> split, fp8[2];
     for (int64_t g = 0; g < count; ++g) {
         const moa_gemm_desc &d = descs[g];
         if (d.m == 0 || d.p == 0) continue;
-        if (resolve_path(d) == MOA_PATH_SPLIT_BF16) {
+        const moa_path path = resolve_path(d);
+        if (path == MOA_PATH_SPLIT_BF16) {
             split.push_back(&d);
+        } else if (path == MOA_PATH_FP8_SCALED) {
+            fp8[(d.flags & MOA_FLAG_FP8_TWO_TERM) ? 1 : 0].push_back(&d);
         } else {
             moa_status s = run_gemm(d, stream);
             if (s != MOA_OK) return s;
         }
     }
-    if (split.empty()) return MOA_OK;
-    if (split.size() > (size_t)INT32_MAX) return fail(MOA_ERR_INVALID, "too many members");
-    const int cnt = (int)split.size();
-    void *ws = nullptr;
-    moa_status s = scratch_alloc(&ws, split_grouped_workspace_bytes(split.data(), cnt), stream);
-    if (s != MOA_OK) return s;
-    Staging st;
-    s = staging_acquire((size_t)split_grouped_desc_bytes(cnt), &st);
-    if (s != MOA_OK) {
-        scratch_free(ws, stream);
-        return s;
-    }
-    hipError_t e = launch_split_grouped(split.data(), cnt, ws, st.ptr, stream);
-    staging_release(st, stream);
-    scratch_free(ws, stream);
-    if (e != hipSuccess) return hip_fail(e, "grouped launch");
-    return MOA_OK;
+    moa_status s = run_list(
+        split, split_grouped_desc_bytes((int)split.size()), split_grouped_workspace_bytes,
+        [&](const moa_gemm_desc *const *m, int c, void *ws, void *host) {
+            return launch_split_grouped(m, c, ws, host, stream);
+        },
+        stream);
+    for (int two = 0; two < 2 && s == MOA_OK; ++two)
+        s = run_list(
+            fp8[two], fp8_grouped_desc_bytes((int)fp8[two].size()),
+            [&](const moa_gemm_desc *const *m, int c) { return fp8_grouped_workspace_bytes(m, c, two != 0); },
+            [&](const moa_gemm_desc *const *m, int c, void *ws, void *host) {
+                return launch_fp8_grouped(m, c, two != 0, ws, host, stream);
+            },
+            stream);
+    return s;
 }
 
 }  // namespace moa

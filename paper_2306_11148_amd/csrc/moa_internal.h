@@ -126,6 +126,25 @@ void fp8_shape(bool two_term, int variant, Plan *p);
 int fp8_variant_count(bool two_term);
 int64_t fp8_workspace_bytes(int64_t m, int64_t n, int64_t p, bool two_term);
 
+// Grouped FP8 (members of one term count, validated by the caller): one
+// conditioning pass over all members and one persistent contraction. The
+// layout/enqueue split mirrors the split-BF16 one (graph-capturable enqueue).
+struct Fp8GroupWork {
+    int64_t tiles;                      // contraction tiles over all members
+    int64_t scale_items;                // exponent / amax items
+    int64_t pack_items;                 // record items
+    int64_t clear_words;                // 32-bit words cleared first (counter + column amax)
+    int64_t table_offset;               // byte offset of the member table in the workspace
+};
+int64_t fp8_grouped_workspace_bytes(const moa_gemm_desc *const *members, int count, bool two_term);
+int64_t fp8_grouped_desc_bytes(int count);
+Fp8GroupWork fp8_grouped_layout(const moa_gemm_desc *const *members, int count, bool two_term, void *workspace,
+                                void *host_staging);
+hipError_t fp8_grouped_enqueue(void *workspace, int count, bool two_term, const Fp8GroupWork &work,
+                               hipStream_t stream);
+hipError_t launch_fp8_grouped(const moa_gemm_desc *const *members, int count, bool two_term, void *workspace,
+                              void *host_staging, hipStream_t stream);
+
 hipError_t launch_split_only(const float *X, int64_t count, uint16_t *hi, uint16_t *lo,
                              hipStream_t stream);
 hipError_t launch_quantise_fp8(const float *A, int64_t m, int64_t n, const float *B,

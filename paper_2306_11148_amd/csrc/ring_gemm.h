@@ -122,6 +122,9 @@ __device__ __forceinline__ void tile(const Operands &op, int64_t i0, int64_t j0,
     const int64_t org = loads_a ? i0 : j0;
     const int64_t lim = loads_a ? op.m : op.p;
     const int64_t tiles = min((int64_t)(loads_a ? BM : BN), padded_rows(lim) - org) / GROUP;
+    // (with two arrays this select becomes a variable index into `op`: keep
+    // `op` in kernel-argument or global memory, never in a local variable,
+    // or it is placed in scratch memory)
     const uint8_t *base = loads_a ? (NREC == 1 || arr == 0 ? op.a0 : op.a1)
                                   : (NREC == 1 || arr == 0 ? op.b0 : op.b1);
     const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(

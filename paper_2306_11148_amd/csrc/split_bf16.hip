@@ -235,6 +235,7 @@ ring::Operands split_operands(const uint8_t *Ap, const uint8_t *Bp, float *C, in
 // per-element order depends only on the slab walk, not on the block shape),
 // so grouped and single results are bitwise equal.
 struct GroupMember {
+    ring::Operands op;                  // the contraction's view (read by ring::tile in place)
     const float *A, *B;
     float *C;
     uint8_t *Ap, *Bp;                   // records of this member in the workspace
@@ -271,14 +272,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void split_grouped_kern
         const GroupMember &d = g[k];
         const int64_t local = tile - d.first_tile;
         const int64_t tm = local / d.tiles_n, tn = local - tm * d.tiles_n;
-        ring::Operands op;
-        op.a0 = d.Ap; op.a1 = nullptr;
-        op.b0 = d.Bp; op.b1 = nullptr;
-        op.C = d.C;
-        op.row_exp = op.col_exp = nullptr;
-        op.m = d.m; op.p = d.p; op.S = d.S;
-        op.accumulate = d.accumulate;
-        ring::tile<BM, BN, WM, WN, 1, SplitMode>(op, __builtin_amdgcn_readfirstlane((int)tm) * (int64_t)BM,
+        ring::tile<BM, BN, WM, WN, 1, SplitMode>(d.op, __builtin_amdgcn_readfirstlane((int)tm) * (int64_t)BM,
                                                  __builtin_amdgcn_readfirstlane((int)tn) * (int64_t)BN, lds);
     }
 }
@@ -449,6 +443,7 @@ GroupedWork split_grouped_layout(const moa_gemm_desc *const *members, int count,
         g.Ap = reinterpret_cast<uint8_t *>(rec);
         g.Bp = g.Ap + ring::array_bytes(d.m, g.S);
         rec += align256(split_bf16_workspace_bytes(d.m, d.n, d.p));
+        g.op = split_operands(g.Ap, g.Bp, g.C, d.m, d.p, g.S, d.accumulate);
         g.first_tile = tiles;
         g.tiles_n = (int32_t)((d.p + GB_N - 1) / GB_N);
         g.accumulate = d.accumulate;

@@ -74,7 +74,7 @@ EXPORTS = [
 ]
 
 MOA_KERNELS = {1: "onf_f64", 2: "onf_f32", 3: "mfma_f32", 4: "split_bf16", 5: "fp8", 6: "fp8_2term",
-               7: "split_pack", 8: "fp8_quant", 9: "split_grouped"}
+               7: "split_pack", 8: "fp8_quant", 9: "split_grouped", 10: "fp8_grouped"}
 
 
 class moa_trace_stat(ctypes.Structure):

@@ -134,10 +134,70 @@ def test_prepared_group_graph_replays_match_single_launches():
         moa.moa_group_destroy(g)
 
 
-def test_prepared_group_refuses_fp8_members():
-    A = torch.randn((8, 8), device=DEV)
-    B = torch.randn((8, 8), device=DEV)
-    C = torch.empty((8, 8), device=DEV)
-    with pytest.raises(moa.MoaError) as ei:
-        moa.moa_group_create([moa.make_desc(A, B, C, path="fp8")])
-    assert ei.value.status == moa.MOA_ERR_UNSUPPORTED
+def test_prepared_group_with_fp8_members_replays():
+    """FP8 members of both term counts join the captured sequence; three replays
+    with eager work in between all match single launches bitwise."""
+    shapes = inputs.grouped_shapes(16, lo=3, hi=500, seed=33)
+    ops = inputs.grouped_operands(shapes, seed=33)
+    flags = [0, moa.MOA_FLAG_FP8_TWO_TERM] * 6 + [0, 0, 0, 0]
+    paths = ["fp8"] * 12 + ["split_bf16", "onf", "split_bf16", "mfma_f32"]
+    members, refs = [], []
+    for (A, B), path, fl in zip(ops, paths, flags):
+        At, Bt = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+        Ct = torch.empty((A.shape[0], B.shape[1]), device=DEV)
+        Rt = torch.empty_like(Ct)
+        moa.moa_gemm(At, Bt, Rt, path=path, flags=fl)
+        members.append((At, Bt, Ct, moa.make_desc(At, Bt, Ct, path=path, flags=fl)))
+        refs.append(Rt)
+    torch.cuda.synchronize()
+    g = moa.moa_group_create([m[3] for m in members])
+    try:
+        for replay in range(3):
+            for _, _, Ct, _ in members:
+                Ct.fill_(float("nan"))
+            torch.cuda.synchronize()
+            moa.moa_group_launch(g)
+            torch.cuda.synchronize()
+            for k, ((_, _, Ct, _), Rt) in enumerate(zip(members, refs)):
+                assert torch.equal(Ct, Rt), f"replay {replay} member {k}"
+    finally:
+        moa.moa_group_destroy(g)
+
+
+@pytest.mark.parametrize("accumulate", [False, True])
+@pytest.mark.parametrize("two", [False, True])
+def test_grouped_fp8_bitwise_equals_single(two, accumulate):
+    """One persistent FP8 launch over ragged members (including n = 0 and
+    single-row shapes): every member bitwise equal to its single launch and
+    within the quantised-product bar of the oracle."""
+    shapes = inputs.grouped_shapes(30, lo=1, hi=600, seed=35)
+    shapes[3] = (7, 0, 9)
+    shapes[4] = (1, 300, 1)
+    fl = moa.MOA_FLAG_FP8_TWO_TERM if two else 0
+    rng = np.random.default_rng(36)
+    host, dev, descs = [], [], []
+    for (m, n, p) in shapes:
+        A, B = inputs.row_col_scaled_f32(m, n, p, seed=int(rng.integers(1 << 30)))
+        C0 = (np.arange(m * p, dtype=np.float32).reshape(m, p) % 5 if accumulate
+              else np.full((m, p), np.nan, np.float32))
+        At, Bt, Ct = (torch.from_numpy(x).to(DEV) for x in (A, B, C0))
+        host.append((A, B, C0))
+        dev.append(Ct)
+        descs.append(moa.make_desc(At, Bt, Ct, path="fp8", accumulate=accumulate, flags=fl))
+        dev.append((At, Bt))
+    moa.moa_gemm_grouped(descs)
+    torch.cuda.synchronize()
+    outs = [dev[2 * k].cpu().numpy() for k in range(len(shapes))]
+    for k, (A, B, C0) in enumerate(host):
+        At, Bt = (torch.from_numpy(x).to(DEV) for x in (A, B))
+        Rt = torch.from_numpy(C0).to(DEV)
+        moa.moa_gemm(At, Bt, Rt, path="fp8", accumulate=accumulate, flags=fl)
+        torch.cuda.synchronize()
+        assert np.array_equal(outs[k], Rt.cpu().numpy()), f"member {k} shape {A.shape} x {B.shape}"
+        if A.shape[1] == 0:
+            assert np.array_equal(outs[k], C0 if accumulate else np.zeros_like(C0))
+            continue
+        Q = O.fp8_gemm_2term(A, B) if two else O.fp8_gemm(A, B)
+        if accumulate:
+            Q = Q + C0.astype(np.float64)
+        assert O.rel_err(outs[k], Q) <= 1e-4
