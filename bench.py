@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=5000.0)
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--split-k", type=str, default=None,
+                    help="comma-separated chunk counts: time skinny products (few blocks of C, long k) "
+                         "with each, one JSON line per point")
     ap.add_argument("--serve-rates", type=str, default=None,
                     help="comma-separated offered loads (req/s): run only the serving loop at each, "
                          "one JSON line per rate")
@@ -427,6 +430,36 @@ def sweep(args, torch, moa, inputs):
         del A, B, C
 
 
+def split_k_sweep(args, torch, moa, inputs):
+    """Skinny products whose m x p blocks cannot fill the 256 CUs: time per
+    product with the k walk split into c chunks (c = 1: no split)."""
+    import ctypes
+    L, st = moa.lib(), torch.cuda.current_stream().cuda_stream
+    for (m, n, p) in ((256, 65536, 256), (512, 32768, 512), (1024, 16384, 1024)):
+        gen = torch.Generator(device="cuda").manual_seed(m + n + p)
+        A = torch.randn((m, n), generator=gen, device="cuda")
+        B = torch.randn((n, p), generator=gen, device="cuda")
+        C = torch.empty((m, p), device="cuda")
+        for name, path, base in (("split_bf16", moa.MOA_PATH_SPLIT_BF16, 0),
+                                 ("fp8_2term", moa.MOA_PATH_FP8_SCALED, moa.MOA_FLAG_FP8_TWO_TERM)):
+            for c in [int(x) for x in args.split_k.split(",")]:
+                d = moa.make_desc(A, B, C, path=path, flags=base | (moa.MOA_FLAG_SPLIT_K(c) if c > 1 else 0))
+                plan = moa.moa_plan_query(d)
+
+                def f():
+                    if L.moa_gemm(ctypes.byref(d), st) != 0:
+                        raise RuntimeError(moa.moa_last_error())
+                for _ in range(3):
+                    f()
+                per, tot = timed_loop(f, 20, torch)
+                ms = tot / 20
+                print(json.dumps({"split_k_sweep": {"m": m, "n": n, "p": p, "path": name, "chunks": plan["split_k"],
+                                                    "workgroups": plan["workgroups"], "ms": round(ms, 4),
+                                                    "tflops": round(2.0 * m * n * p / ms / 1e9, 2),
+                                                    "p50_ms": round(pct(per, 50), 4)}}), flush=True)
+        del A, B, C
+
+
 def block_sweep(args, torch, moa):
     """The paper's experiment on this GPU: time and joules per product against
     N for every block size of the plain ONF kernel in FP64 (one JSON line per
@@ -476,6 +509,9 @@ def main():
         return
     if args.block_sweep:
         block_sweep(args, torch, moa)
+        return
+    if args.split_k:
+        split_k_sweep(args, torch, moa, inputs)
         return
     if args.serve_rates:
         for rate in [float(x) for x in args.serve_rates.split(",")]:

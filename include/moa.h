@@ -88,6 +88,20 @@ typedef enum moa_path {
  * index beyond the table is MOA_ERR_INVALID. Occupies flag bits 8..15. */
 #define MOA_FLAG_VARIANT(v) ((uint32_t)((v) + 1) << 8)
 #define MOA_FLAG_VARIANT_MASK 0xFF00u
+/* Split-k, the sigma-lift of Fig. 2 carried across workgroups (its "addition
+ * loop" over k blocks): the k slabs are cut into `c` contiguous chunks
+ * (2 <= c <= 255; clamped so that no chunk is empty), each workgroup sums one
+ * chunk of one block of C into an FP32 partial, and a second kernel adds the
+ * partials in chunk order, then applies the FP8 descale and the accumulate
+ * form. For products with fewer blocks of C than compute units and a long k
+ * walk. Split-BF16 and FP8 paths only (MOA_ERR_UNSUPPORTED otherwise). The
+ * result is deterministic and within the path's error bound, but its
+ * summation order differs from the unsplit product's, so it is not bitwise
+ * equal to it. Grouped launches and the serving loop run such members as
+ * single launches; prepared groups refuse them. The partials (c m p FP32
+ * values) are part of the workspace. Occupies flag bits 16..23. */
+#define MOA_FLAG_SPLIT_K(c) (((uint32_t)(c) & 0xFFu) << 16)
+#define MOA_FLAG_SPLIT_K_MASK 0xFF0000u
 
 /* One matrix product. Field names follow Eq. 1: m rows of A and C, n the
  * shared extent (rho B[0]), p columns of B and C. */
@@ -120,6 +134,8 @@ typedef struct moa_plan_info {
     int64_t static_components;/* static block size rule result (components) */
     int32_t variant;          /* instantiation of the path's kernel table */
     int32_t tuned;            /* 1 if the variant came from the autotuner */
+    int32_t split_k;          /* k chunks summed by separate workgroups (1 = none) */
+    int32_t reserved;
 } moa_plan_info;
 
 /* Eq. 3 on the device. Asynchronous on `stream`.

@@ -44,11 +44,13 @@ moa_status validate(const moa_gemm_desc &d, bool need_ptrs) {
     if (d.dtype != MOA_F64 && d.dtype != MOA_F32) return fail(MOA_ERR_INVALID, "unknown dtype %d", d.dtype);
     if (d.path < MOA_PATH_AUTO || d.path > MOA_PATH_FP8_SCALED)
         return fail(MOA_ERR_INVALID, "unknown path %d", d.path);
-    if (d.flags & ~(MOA_FLAG_FP8_TWO_TERM | MOA_FLAG_VARIANT_MASK))
+    if (d.flags & ~(MOA_FLAG_FP8_TWO_TERM | MOA_FLAG_VARIANT_MASK | MOA_FLAG_SPLIT_K_MASK))
         return fail(MOA_ERR_INVALID, "unknown flag bits 0x%x", d.flags);
     const moa_path path = resolve_path(d);
     if (d.dtype == MOA_F64 && path != MOA_PATH_ONF)
         return fail(MOA_ERR_UNSUPPORTED, "FP64 runs on the ONF path only (path %d)", (int)path);
+    if (split_k_requested(d) > 1 && path != MOA_PATH_SPLIT_BF16 && path != MOA_PATH_FP8_SCALED)
+        return fail(MOA_ERR_UNSUPPORTED, "split-k needs the split-BF16 or FP8 path (path %d)", (int)path);
     const int64_t es = d.dtype == MOA_F64 ? 8 : 4;
     int64_t na, nb, nc, ba, bb, bc;
     if (!mul_ok(d.m, d.n, &na) || !mul_ok(d.n, d.p, &nb) || !mul_ok(d.m, d.p, &nc) ||
@@ -148,6 +150,7 @@ moa_status moa_plan_query(const moa_gemm_desc *desc, moa_plan_info *out) {
         out->static_components = pl.static_components;
         out->variant = pl.variant;
         out->tuned = pl.tuned ? 1 : 0;
+        out->split_k = pl.split_k;
         return MOA_OK;
     } catch (...) {
         return fail(MOA_ERR_DEVICE, "internal error");

@@ -619,6 +619,11 @@ hipError_t launch_fp8(const moa_gemm_desc &d, const Plan &plan, void *ws, hipStr
     op.m = d.m; op.p = d.p;
     op.S = (d.n + SLAB8 - 1) / SLAB8;
     op.accumulate = d.accumulate;
+    if (plan.split_k > 1) {
+        float *partials = reinterpret_cast<float *>(static_cast<char *>(ws) + plan.partial_offset);
+        if (two) return ring::launch_splitk<128, 128, 64, 64, 2, Fp8Mode<true>, 3>(op, plan.split_k, partials, st);
+        return ring::launch_splitk<128, 128, 64, 64, 1, Fp8Mode<false>, 3>(op, plan.split_k, partials, st);
+    }
     if (two) {
         switch (plan.variant) {
         case 0: return launch_shape<128, 128, 64, 64, true>(op, st);

@@ -125,7 +125,10 @@ moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t st
         const moa_gemm_desc &d = descs[g];
         if (d.m == 0 || d.p == 0) continue;
         const moa_path path = resolve_path(d);
-        if (path == MOA_PATH_SPLIT_BF16) {
+        if (split_k_requested(d) > 1) {          // the persistent launches do not split k
+            moa_status s = run_gemm(d, stream);
+            if (s != MOA_OK) return s;
+        } else if (path == MOA_PATH_SPLIT_BF16) {
             split.push_back(&d);
         } else if (path == MOA_PATH_FP8_SCALED) {
             fp8[(d.flags & MOA_FLAG_FP8_TWO_TERM) ? 1 : 0].push_back(&d);

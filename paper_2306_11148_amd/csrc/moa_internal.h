@@ -44,7 +44,18 @@ struct Plan {
     int64_t workspace_bytes = 0;
     int64_t static_components = 0;
     bool tuned = false;
+    int split_k = 1;          // k chunks summed by separate workgroups (ring paths)
+    int64_t partial_offset = 0;   // byte offset of the split-k partials in the workspace
 };
+
+// Chunk count asked for by MOA_FLAG_SPLIT_K (0 or 1: none).
+inline int split_k_requested(const moa_gemm_desc &d) { return (int)((d.flags & MOA_FLAG_SPLIT_K_MASK) >> 16); }
+// Chunks actually used for S slabs: ceil(S / ceil(S / c)), so none is empty.
+inline int split_k_chunks(int requested, int64_t S) {
+    if (requested <= 1 || S <= 1) return 1;
+    const int64_t per = (S + requested - 1) / requested;
+    return (int)((S + per - 1) / per);
+}
 
 // Validates `d` (shapes, pointers, enums, aliasing) without touching the
 // device. `need_ptrs` = false skips pointer checks (plan queries).

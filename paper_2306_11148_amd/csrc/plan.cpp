@@ -179,6 +179,8 @@ moa_status make_plan(const moa_gemm_desc &d, Plan *out) {
         }
         split_bf16_shape(v, &pl);
         pl.workspace_bytes = split_bf16_workspace_bytes(d.m, d.n, d.p);
+        pl.split_k = split_k_chunks(split_k_requested(d), (d.n + 15) / 16);
+        if (pl.split_k > 1) split_bf16_shape(0, &pl);   // split-k runs the first block variant
         // 256 record rows of (n/16) 64-byte records must stay below 2^31 bytes
         // (32-bit buffer offsets of one tile).
         if ((d.n + 15) / 16 > 131071)
@@ -205,6 +207,8 @@ moa_status make_plan(const moa_gemm_desc &d, Plan *out) {
         }
         fp8_shape(two, v, &pl);
         pl.workspace_bytes = fp8_workspace_bytes(d.m, d.n, d.p, two);
+        pl.split_k = split_k_chunks(split_k_requested(d), (d.n + 63) / 64);
+        if (pl.split_k > 1) fp8_shape(two, 0, &pl);     // split-k runs the first block variant
         // 256 record rows of (n/64) 64-byte records must stay below 2^31 bytes
         // (32-bit buffer offsets of one tile).
         if ((d.n + 63) / 64 > 131071)
@@ -215,6 +219,15 @@ moa_status make_plan(const moa_gemm_desc &d, Plan *out) {
         return fail(MOA_ERR_INVALID, "unknown path %d", d.path);
     }
     pl.workgroups = tiles_for(d.m, d.p, pl.tile_m, pl.tile_n);
+    if (pl.split_k > 1) {
+        // the partials follow the path's own workspace, 256-byte aligned
+        pl.partial_offset = (pl.workspace_bytes + 255) / 256 * 256;
+        int64_t mp = 0;
+        if (__builtin_mul_overflow(d.m, d.p, &mp) || mp > (INT64_MAX / 4) / pl.split_k)
+            return fail(MOA_ERR_SHAPE, "split-k partials overflow");
+        pl.workspace_bytes = pl.partial_offset + (int64_t)pl.split_k * mp * 4;
+        pl.workgroups *= pl.split_k;
+    }
     if (pl.workgroups > INT32_MAX) return fail(MOA_ERR_SHAPE, "too many tiles");
     *out = pl;
     return MOA_OK;

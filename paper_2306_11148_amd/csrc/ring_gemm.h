@@ -26,6 +26,8 @@
 // that belongs at its physical position.
 #pragma once
 
+#include <algorithm>
+
 #include "moa_internal.h"
 #include "tile_common.h"
 
@@ -101,8 +103,12 @@ __device__ __forceinline__ V lds_chunk(const uint8_t *buf, int row, int chunk) {
 // [B array 0 (BN)] .. [B array NREC-1].
 // `lds` is the workgroup's ring; on entry no wave may still be reading it, on
 // exit every wave has finished.
+// The k walk covers slabs s_begin .. s_end-1 (all slabs by default). With
+// `partial` set, the epilogue stores the raw block sum there (row-major m x p,
+// no descale, no accumulate): one chunk of a split-k product.
 template <int BM, int BN, int WM, int WN, int NREC, class Mode, int NSTAGE = ring::NSTAGE>
-__device__ __forceinline__ void tile(const Operands &op, int64_t i0, int64_t j0, uint8_t *lds) {
+__device__ __forceinline__ void tile(const Operands &op, int64_t i0, int64_t j0, uint8_t *lds, int s_begin = 0,
+                                     int s_end = -1, float *partial = nullptr) {
     using G = Cfg<BM, BN, WM, WN, NREC, NSTAGE>;
     constexpr int WAVES_N = G::WAVES_N, FM = G::FM, FN = G::FN;
     constexpr int STAGE = G::STAGE, LPW = G::LPW;
@@ -110,6 +116,8 @@ __device__ __forceinline__ void tile(const Operands &op, int64_t i0, int64_t j0,
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int wm = wave / WAVES_N, wn = wave % WAVES_N;
     const int S = (int)op.S;                 // the planner keeps S below 2^17
+    const int s0 = s_begin;
+    const int L = (s_end < 0 ? S : s_end) - s_begin;   // slabs this block walks
 
     // LDS rows of a slab: [A array 0 (BM)] .. [A array NREC-1] [B array 0 (BN)] ..
     // Wave w loads rows 16*LPW*w .. +16*LPW-1, all inside one array.
@@ -134,13 +142,13 @@ __device__ __forceinline__ void tile(const Operands &op, int64_t i0, int64_t j0,
     // lie beyond the resource's range and load as zeros (their outputs are
     // not stored).
     const int voff = (lane >> 2) * REC_BYTES + (((lane & 3) ^ (lane >> 4)) << 4);
-    auto issue = [&](int s) {
+    auto issue = [&](int s) {            // s counts from s_begin
         uint8_t *buf = lds + (s % NSTAGE) * STAGE + row_first * REC_BYTES;
 #pragma unroll
         for (int q = 0; q < LPW; ++q)
             __builtin_amdgcn_raw_ptr_buffer_load_lds(
                 rsrc, (lds_void_t *)(buf + q * 16 * REC_BYTES), 16, voff,
-                (int)((row_in / GROUP + q) * tile_row) + s * GROUP * REC_BYTES, 0, 0);
+                (int)((row_in / GROUP + q) * tile_row) + (s0 + s) * GROUP * REC_BYTES, 0, 0);
     };
 
     const int frow = lane & 31, fhalf = lane >> 5;
@@ -175,25 +183,25 @@ __device__ __forceinline__ void tile(const Operands &op, int64_t i0, int64_t j0,
     auto step = [&](int t, const typename Mode::template Frags<FM, FN> &cur,
                     typename Mode::template Frags<FM, FN> &next) {
         // issued so far: slabs up to t + NSTAGE - 2; t + 1 must have landed
-        wait_loads(min(NSTAGE - 3, S - t - 2));
+        wait_loads(min(NSTAGE - 3, L - t - 2));
         ring_barrier();
-        if (t + NSTAGE - 1 < S) issue(t + NSTAGE - 1);
+        if (t + NSTAGE - 1 < L) issue(t + NSTAGE - 1);
         read(t + 1, next);
         Mode::template mma<FM, FN>(cur, acc);
     };
 
-    if (S > 0) {
+    if (L > 0) {
         for (int q = 0; q < NSTAGE - 1; ++q)
-            if (q < S) issue(q);
-        wait_loads(min(NSTAGE - 2, S - 1));            // slab 0 has landed
+            if (q < L) issue(q);
+        wait_loads(min(NSTAGE - 2, L - 1));            // slab 0 has landed
         ring_barrier();
         read(0, f0);
         int t = 0;
-        for (; t + 2 < S; t += 2) {
+        for (; t + 2 < L; t += 2) {
             step(t, f0, f1);
             step(t + 1, f1, f0);
         }
-        if (t + 1 < S) {                               // two slabs left
+        if (t + 1 < L) {                               // two slabs left
             step(t, f0, f1);
             f0 = f1;
         }
@@ -213,12 +221,16 @@ __device__ __forceinline__ void tile(const Operands &op, int64_t i0, int64_t j0,
         for (int b = 0; b < FN; ++b) {
             const int64_t j = j0 + wn * WN + b * 32 + (lane & 31);
             if (j >= op.p) continue;
-            const int fj = Mode::SCALED ? col_exp[j] : 0;
+            const int fj = Mode::SCALED && !partial ? col_exp[j] : 0;
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int64_t i = i0 + wm * WM + a * 32 + mfma32_row(r, lane);
                 if (i < op.m) {
                     float v = acc[a][b][r];
+                    if (partial) {
+                        ((global_f32 *)partial)[i * op.p + j] = v;
+                        continue;
+                    }
                     if constexpr (Mode::SCALED) v = ldexpf(v, -(row_exp[i] + fj));
                     if (op.accumulate) v += C[i * op.p + j];
                     C[i * op.p + j] = v;
@@ -243,6 +255,61 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void single_kernel(Oper
     int tm, tn;
     block_of(tiles_m, tiles_n, &tm, &tn);
     tile<BM, BN, WM, WN, NREC, Mode, NST>(op, (int64_t)tm * BM, (int64_t)tn * BN, lds);
+}
+
+// Split-k (the sigma loop cut into `chunks` contiguous runs of chunk_slabs
+// slabs, Fig. 2's "addition loop" done across workgroups): workgroup w takes
+// chunk w / tiles of tile w mod tiles (after the XCD remap, so the blocks of
+// one chunk share an L2) and stores its raw block sum in partials + chunk m p.
+template <int BM, int BN, int WM, int WN, int NREC, class Mode, int NST = NSTAGE>
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void splitk_kernel(Operands op, int tiles_m, int tiles_n,
+                                                                            int chunk_slabs, float *partials) {
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[Cfg<BM, BN, WM, WN, NREC, NST>::LDS];
+    const int tiles = tiles_m * tiles_n;
+    const int id = __builtin_amdgcn_readfirstlane(xcd_remap(blockIdx.x, (int)gridDim.x));
+    const int chunk = id / tiles;
+    int tm, tn;
+    tile_coords(id - chunk * tiles, tiles_m, tiles_n, 8, &tm, &tn);
+    tm = __builtin_amdgcn_readfirstlane(tm);
+    tn = __builtin_amdgcn_readfirstlane(tn);
+    const int s_begin = chunk * chunk_slabs;
+    const int s_end = min((int)op.S, s_begin + chunk_slabs);
+    tile<BM, BN, WM, WN, NREC, Mode, NST>(op, (int64_t)tm * BM, (int64_t)tn * BN, lds, s_begin, s_end,
+                                          partials + (int64_t)chunk * op.m * op.p);
+}
+
+// Deterministic reduction of the chunk partials: C = ((P_0 + P_1) + ...) + P_c-1,
+// then the descale (scaled modes) and the accumulate form, as the epilogue of
+// an unsplit product does.
+static __global__ __launch_bounds__(256) void splitk_reduce_kernel(const float *__restrict__ partials, int chunks,
+                                                            int64_t m, int64_t p, float *__restrict__ C,
+                                                            const int32_t *__restrict__ row_exp,
+                                                            const int32_t *__restrict__ col_exp, int accumulate) {
+    const int64_t mp = m * p;
+    for (int64_t i = blockIdx.y; i < m; i += gridDim.y)
+        for (int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x; j < p; j += (int64_t)gridDim.x * 256) {
+            const int64_t x = i * p + j;
+            float v = partials[x];
+            for (int q = 1; q < chunks; ++q) v += partials[(int64_t)q * mp + x];
+            if (row_exp) v = ldexpf(v, -(row_exp[i] + col_exp[j]));
+            if (accumulate) v += C[x];
+            C[x] = v;
+        }
+}
+
+// Host side of a split-k launch: chunk kernel, then the reduction.
+template <int BM, int BN, int WM, int WN, int NREC, class Mode, int NST>
+hipError_t launch_splitk(const Operands &op, int chunks, float *partials, hipStream_t st) {
+    const int tiles_m = (int)((op.m + BM - 1) / BM), tiles_n = (int)((op.p + BN - 1) / BN);
+    const int chunk_slabs = (int)((op.S + chunks - 1) / chunks);
+    chunks = (int)((op.S + chunk_slabs - 1) / chunk_slabs);   // every chunk non-empty
+    hipLaunchKernelGGL((splitk_kernel<BM, BN, WM, WN, NREC, Mode, NST>), dim3(tiles_m * tiles_n * chunks),
+                       dim3(Cfg<BM, BN, WM, WN, NREC, NST>::THREADS), 0, st, op, tiles_m, tiles_n, chunk_slabs,
+                       partials);
+    const dim3 grid((unsigned)std::min<int64_t>((op.p + 255) / 256, 64), (unsigned)std::min<int64_t>(op.m, 65535));
+    hipLaunchKernelGGL(splitk_reduce_kernel, grid, dim3(256), 0, st, partials, chunks, op.m, op.p, op.C, op.row_exp,
+                       op.col_exp, op.accumulate);
+    return hipGetLastError();
 }
 
 }  // namespace ring

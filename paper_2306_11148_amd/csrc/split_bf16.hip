@@ -397,6 +397,11 @@ hipError_t launch_split_bf16(const moa_gemm_desc &d, const Plan &plan, void *ws,
     const int64_t S = (d.n + SLAB - 1) / SLAB;
     const uint8_t *Ap = static_cast<const uint8_t *>(ws);
     const uint8_t *Bp = Ap + ring::array_bytes(d.m, S);
+    if (plan.split_k > 1) {
+        const ring::Operands op = split_operands(Ap, Bp, static_cast<float *>(d.C), d.m, d.p, S, d.accumulate);
+        float *partials = reinterpret_cast<float *>(static_cast<char *>(ws) + plan.partial_offset);
+        return ring::launch_splitk<128, 128, 64, 64, 1, SplitMode, 3>(op, plan.split_k, partials, st);
+    }
     switch (plan.variant) {
     case 0: return launch_shape<128, 128, 64, 64, 3>(d, Ap, Bp, S, st);
     default: return launch_shape<256, 256, 128, 64, 3>(d, Ap, Bp, S, st);

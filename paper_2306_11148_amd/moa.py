@@ -28,6 +28,10 @@ def MOA_FLAG_VARIANT(v: int) -> int:
     return (v + 1) << 8
 
 
+def MOA_FLAG_SPLIT_K(c: int) -> int:
+    return (c & 0xFF) << 16
+
+
 class MoaError(RuntimeError):
     def __init__(self, status: int, where: str, message: str):
         super().__init__(f"{where}: {status_name(status)}: {message}")
@@ -49,7 +53,8 @@ class moa_plan_info(ctypes.Structure):
                 ("lane_n", ctypes.c_int32), ("threads", ctypes.c_int32),
                 ("lds_bytes", ctypes.c_int32), ("workgroups", ctypes.c_int64),
                 ("workspace_bytes", ctypes.c_int64), ("static_components", ctypes.c_int64),
-                ("variant", ctypes.c_int32), ("tuned", ctypes.c_int32)]
+                ("variant", ctypes.c_int32), ("tuned", ctypes.c_int32),
+                ("split_k", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class moa_serve_cfg(ctypes.Structure):

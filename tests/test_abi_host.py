@@ -94,6 +94,27 @@ def test_fp8_plan_variants():
     assert big["tile_m"] == 256 and big["workgroups"] == 1024
 
 
+def test_split_k_plan():
+    """Split-k: chunks clamped so none is empty, partials in the workspace,
+    one workgroup per (block, chunk), first block variant; ring paths only."""
+    S16 = moa.MOA_PATH_SPLIT_BF16
+    base = moa.moa_plan_query(_desc(100, 20000, 100, path=S16))
+    q = moa.moa_plan_query(_desc(100, 20000, 100, path=S16, flags=moa.MOA_FLAG_SPLIT_K(8)))
+    assert base["split_k"] == 1 and q["split_k"] == 8
+    assert q["workgroups"] == 8 * base["workgroups"] and q["tile_m"] == 128
+    assert q["workspace_bytes"] >= base["workspace_bytes"] + 8 * 100 * 100 * 4
+    # n = 40 -> 3 slabs of 16: 8 chunks clamp to 3
+    assert moa.moa_plan_query(_desc(64, 40, 64, path=S16, flags=moa.MOA_FLAG_SPLIT_K(8)))["split_k"] == 3
+    # 10 slabs in 6 chunks -> chunks of 2 -> 5 chunks
+    assert moa.moa_plan_query(_desc(64, 160, 64, path=S16, flags=moa.MOA_FLAG_SPLIT_K(6)))["split_k"] == 5
+    f8 = moa.moa_plan_query(_desc(64, 640, 64, path=moa.MOA_PATH_FP8_SCALED,
+                                  flags=moa.MOA_FLAG_FP8_TWO_TERM | moa.MOA_FLAG_SPLIT_K(4)))
+    assert f8["split_k"] == 4 and f8["tile_k"] == 64          # 10 slabs of 64 -> chunks of 3 -> 4
+    assert call(_desc(8, 8, 8, moa.MOA_F32, moa.MOA_PATH_ONF, flags=moa.MOA_FLAG_SPLIT_K(2))) == \
+        moa.MOA_ERR_UNSUPPORTED
+    assert call(_desc(8, 8, 8, flags=1 << 24)) == moa.MOA_ERR_INVALID
+
+
 def call(d):
     return moa.lib().moa_gemm(ctypes.byref(d), None)
 
@@ -133,7 +154,7 @@ def test_descriptor_layout_matches_header():
     # int64 m,n,p; int32 dtype,path; 3 pointers; int32 accumulate; uint32 flags
     assert ctypes.sizeof(moa.moa_gemm_desc) == 3 * 8 + 2 * 4 + 3 * 8 + 2 * 4
     assert moa.moa_gemm_desc.A.offset == 32
-    assert ctypes.sizeof(moa.moa_plan_info) == 11 * 4 + 4 + 3 * 8 + 2 * 4
+    assert ctypes.sizeof(moa.moa_plan_info) == 11 * 4 + 4 + 3 * 8 + 4 * 4
 
 
 def test_grouped_overlap_rejected_before_launch():
