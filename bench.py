@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=5000.0)
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--layouts", action="store_true",
+                    help="time the N x N product for every row-/column-major combination of A, B, C "
+                         "(gamma_row / gamma_col), one JSON line per point")
     ap.add_argument("--split-k", type=str, default=None,
                     help="comma-separated chunk counts: time skinny products (few blocks of C, long k) "
                          "with each, one JSON line per point")
@@ -430,6 +433,39 @@ def sweep(args, torch, moa, inputs):
         del A, B, C
 
 
+def layout_sweep(args, torch, moa):
+    """Time per N x N product for each layout of A, B and C (row-major or
+    column-major, the latter passed as the transpose of a contiguous tensor)."""
+    import ctypes
+    import itertools
+    N = args.n
+    L, st = moa.lib(), torch.cuda.current_stream().cuda_stream
+    gen = torch.Generator(device="cuda").manual_seed(N)
+    A0 = torch.randn((N, N), generator=gen, device="cuda")
+    B0 = torch.randn((N, N), generator=gen, device="cuda")
+    C0 = torch.empty((N, N), device="cuda")
+    for name, path, flags in (("split_bf16", moa.MOA_PATH_SPLIT_BF16, 0),
+                              ("fp8_1term", moa.MOA_PATH_FP8_SCALED, 0),
+                              ("onf_f32", moa.MOA_PATH_ONF, 0)):
+        for ac, bc, cc in itertools.product([False, True], repeat=3):
+            if name == "onf_f32" and len({ac, bc, cc}) > 1:
+                continue
+            d = moa.make_desc(A0.t() if ac else A0, B0.t() if bc else B0, C0.t() if cc else C0,
+                              path=path, flags=flags)
+
+            def f():
+                if L.moa_gemm(ctypes.byref(d), st) != 0:
+                    raise RuntimeError(moa.moa_last_error())
+            f()
+            reps = 3 if name == "onf_f32" else 20
+            per, tot = timed_loop(f, reps, torch)
+            ms = tot / reps
+            print(json.dumps({"layout_sweep": {"N": N, "path": name, "A": "col" if ac else "row",
+                                               "B": "col" if bc else "row", "C": "col" if cc else "row",
+                                               "ms": round(ms, 4), "tflops": round(2.0 * N ** 3 / ms / 1e9, 2)}}),
+                  flush=True)
+
+
 def split_k_sweep(args, torch, moa, inputs):
     """Skinny products whose m x p blocks cannot fill the 256 CUs: time per
     product with the k walk split into c chunks (c = 1: no split)."""
@@ -512,6 +548,9 @@ def main():
         return
     if args.split_k:
         split_k_sweep(args, torch, moa, inputs)
+        return
+    if args.layouts:
+        layout_sweep(args, torch, moa)
         return
     if args.serve_rates:
         for rate in [float(x) for x in args.serve_rates.split(",")]:

@@ -102,6 +102,21 @@ typedef enum moa_path {
  * values) are part of the workspace. Occupies flag bits 16..23. */
 #define MOA_FLAG_SPLIT_K(c) (((uint32_t)(c) & 0xFFu) << 16)
 #define MOA_FLAG_SPLIT_K_MASK 0xFF0000u
+/* Operand layouts from the paper's family of layout functions gamma (gamma_row,
+ * the default, and gamma_col; conclusion and appendix): with MOA_FLAG_A_COL
+ * the m x n matrix A is stored column by column, element (i, k) at offset
+ * i + k m; MOA_FLAG_B_COL likewise stores B (n x p) as k + j n and
+ * MOA_FLAG_C_COL stores C (m x p) as i + j m. Shapes keep their meaning.
+ * Split-BF16 and FP8 take any combination (the layout only changes how the
+ * operands are conditioned; a column-major C is computed as C^T = B^T A^T).
+ * ONF and FP32 matrix-core paths take all three row-major or all three
+ * column-major (the same kernel on C^T = B^T A^T, no copies); other
+ * combinations are MOA_ERR_UNSUPPORTED. Grouped launches run members with a
+ * column-major operand singly; prepared groups refuse them. */
+#define MOA_FLAG_A_COL 0x1000000u
+#define MOA_FLAG_B_COL 0x2000000u
+#define MOA_FLAG_C_COL 0x4000000u
+#define MOA_FLAG_LAYOUT_MASK 0x7000000u
 
 /* One matrix product. Field names follow Eq. 1: m rows of A and C, n the
  * shared extent (rho B[0]), p columns of B and C. */

@@ -44,13 +44,16 @@ moa_status validate(const moa_gemm_desc &d, bool need_ptrs) {
     if (d.dtype != MOA_F64 && d.dtype != MOA_F32) return fail(MOA_ERR_INVALID, "unknown dtype %d", d.dtype);
     if (d.path < MOA_PATH_AUTO || d.path > MOA_PATH_FP8_SCALED)
         return fail(MOA_ERR_INVALID, "unknown path %d", d.path);
-    if (d.flags & ~(MOA_FLAG_FP8_TWO_TERM | MOA_FLAG_VARIANT_MASK | MOA_FLAG_SPLIT_K_MASK))
+    if (d.flags & ~(MOA_FLAG_FP8_TWO_TERM | MOA_FLAG_VARIANT_MASK | MOA_FLAG_SPLIT_K_MASK | MOA_FLAG_LAYOUT_MASK))
         return fail(MOA_ERR_INVALID, "unknown flag bits 0x%x", d.flags);
     const moa_path path = resolve_path(d);
     if (d.dtype == MOA_F64 && path != MOA_PATH_ONF)
         return fail(MOA_ERR_UNSUPPORTED, "FP64 runs on the ONF path only (path %d)", (int)path);
     if (split_k_requested(d) > 1 && path != MOA_PATH_SPLIT_BF16 && path != MOA_PATH_FP8_SCALED)
         return fail(MOA_ERR_UNSUPPORTED, "split-k needs the split-BF16 or FP8 path (path %d)", (int)path);
+    const uint32_t lay = d.flags & MOA_FLAG_LAYOUT_MASK;
+    if ((path == MOA_PATH_ONF || path == MOA_PATH_MFMA_F32) && lay != 0 && lay != MOA_FLAG_LAYOUT_MASK)
+        return fail(MOA_ERR_UNSUPPORTED, "path %d takes all operands row-major or all column-major", (int)path);
     const int64_t es = d.dtype == MOA_F64 ? 8 : 4;
     int64_t na, nb, nc, ba, bb, bc;
     if (!mul_ok(d.m, d.n, &na) || !mul_ok(d.n, d.p, &nb) || !mul_ok(d.m, d.p, &nc) ||
@@ -75,8 +78,9 @@ moa_status validate(const moa_gemm_desc &d, bool need_ptrs) {
     return MOA_OK;
 }
 
-moa_status run_gemm(const moa_gemm_desc &d, hipStream_t stream) {
-    if (d.m == 0 || d.p == 0) return MOA_OK;
+moa_status run_gemm(const moa_gemm_desc &d_in, hipStream_t stream) {
+    if (d_in.m == 0 || d_in.p == 0) return MOA_OK;
+    const moa_gemm_desc d = row_major_result(d_in);
     Plan pl;
     moa_status s = make_plan(d, &pl);
     if (s != MOA_OK) return s;

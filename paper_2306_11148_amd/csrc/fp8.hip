@@ -518,7 +518,7 @@ constexpr int G_PER_CU_TWO = 1, G_PER_CU_ONE = 3;
 int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
 struct Fp8Workspace {
-    uint32_t *amaxB;
+    uint32_t *amaxA, *amaxB;
     int32_t *e, *f;
     uint8_t *qA, *lA, *qB, *lB;
 };
@@ -528,6 +528,7 @@ Fp8Workspace carve(void *ws, int64_t m, int64_t n, int64_t p, bool two) {
     char *c = static_cast<char *>(ws);
     Fp8Workspace w;
     w.amaxB = reinterpret_cast<uint32_t *>(c); c += align256(4 * p);
+    w.amaxA = reinterpret_cast<uint32_t *>(c); c += align256(4 * m);
     w.e = reinterpret_cast<int32_t *>(c); c += align256(4 * m);
     w.f = reinterpret_cast<int32_t *>(c); c += align256(4 * p);
     w.qA = reinterpret_cast<uint8_t *>(c); c += align256(ring::array_bytes(m, S));
@@ -548,32 +549,50 @@ void scales(const float *A, int64_t m, int64_t n, const float *B, int64_t p, int
                            dim3(256), 0, st, B, n, p, amaxB);
 }
 
+// Exponents and records of one operand. A "row operand" is consumed row by
+// row (A's rows: exponents e); a "column operand" column by column (B's
+// columns: exponents f). `X` is row-major; `by_rows` says whether the wanted
+// vectors are its rows (X is rows x K) or its columns (X is K x rows).
+void operand_records(const float *X, int64_t rows, int64_t K, int64_t S, bool by_rows, bool two, uint32_t *amax,
+                     int32_t *exps, uint8_t *q, uint8_t *l, hipStream_t st) {
+    if (rows == 0) return;
+    if (by_rows) {
+        const int vec = (K % 4 == 0) && ((uintptr_t)X % 16 == 0);
+        hipLaunchKernelGGL(row_exp_kernel, dim3((unsigned)((rows + 3) / 4)), dim3(256), 0, st, X, rows, K, vec, exps);
+        if (S > 0) {
+            int64_t blocks = (padded_rows(rows) * S * 4 + 255) / 256;
+            if (blocks > 65536) blocks = 65536;
+            if (two)
+                hipLaunchKernelGGL(pack_rows_fp8_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, st, X, rows, K,
+                                   S, vec, exps, q, l);
+            else
+                hipLaunchKernelGGL(pack_rows_fp8_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, st, X, rows, K,
+                                   S, vec, exps, q, l);
+        }
+        return;
+    }
+    hipLaunchKernelGGL(fill_u32_kernel, dim3((unsigned)((rows + 255) / 256)), dim3(256), 0, st, amax, rows);
+    if (K > 0)
+        hipLaunchKernelGGL(col_amax_kernel, dim3((unsigned)((rows + 255) / 256), (unsigned)((K + COL_BAND - 1) / COL_BAND)),
+                           dim3(256), 0, st, X, K, rows, amax);
+    // also when S == 0: the epilogue reads the exponents
+    const int vec = (rows % 4 == 0) && ((uintptr_t)X % 16 == 0);
+    const dim3 grid((unsigned)((rows + 63) / 64), (unsigned)(S < 1 ? 1 : S > 65535 ? 65535 : S));
+    if (two)
+        hipLaunchKernelGGL(pack_cols_fp8_kernel<true>, grid, dim3(256), 0, st, X, K, rows, S, vec, amax, exps, q, l);
+    else
+        hipLaunchKernelGGL(pack_cols_fp8_kernel<false>, grid, dim3(256), 0, st, X, K, rows, S, vec, amax, exps, q, l);
+}
+
+// A column-major A (element (i, k) at i + k m) is a row-major n x m array
+// whose columns are A's rows; a column-major B is a row-major p x n array
+// whose rows are B's columns.
 hipError_t pack_records(const moa_gemm_desc &d, bool two, const Fp8Workspace &w, hipStream_t st) {
     const float *A = static_cast<const float *>(d.A);
     const float *B = static_cast<const float *>(d.B);
     const int64_t S = (d.n + SLAB8 - 1) / SLAB8;
-    scales(A, d.m, d.n, B, d.p, w.e, w.amaxB, st);
-    if (d.m > 0 && S > 0) {
-        const int vec = (d.n % 4 == 0) && ((uintptr_t)A % 16 == 0);
-        int64_t blocks = (padded_rows(d.m) * S * 4 + 255) / 256;
-        if (blocks > 65536) blocks = 65536;
-        if (two)
-            hipLaunchKernelGGL(pack_rows_fp8_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, st, A, d.m, d.n, S,
-                               vec, w.e, w.qA, w.lA);
-        else
-            hipLaunchKernelGGL(pack_rows_fp8_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, st, A, d.m, d.n, S,
-                               vec, w.e, w.qA, w.lA);
-    }
-    if (d.p > 0) {   // also when S == 0: the epilogue reads the column exponents
-        const int vec = (d.p % 4 == 0) && ((uintptr_t)B % 16 == 0);
-        const dim3 grid((unsigned)((d.p + 63) / 64), (unsigned)(S < 1 ? 1 : S > 65535 ? 65535 : S));
-        if (two)
-            hipLaunchKernelGGL(pack_cols_fp8_kernel<true>, grid, dim3(256), 0, st, B, d.n, d.p, S, vec, w.amaxB,
-                               w.f, w.qB, w.lB);
-        else
-            hipLaunchKernelGGL(pack_cols_fp8_kernel<false>, grid, dim3(256), 0, st, B, d.n, d.p, S, vec, w.amaxB,
-                               w.f, w.qB, w.lB);
-    }
+    operand_records(A, d.m, d.n, S, !(d.flags & MOA_FLAG_A_COL), two, w.amaxA, w.e, w.qA, w.lA, st);
+    operand_records(B, d.p, d.n, S, (d.flags & MOA_FLAG_B_COL) != 0, two, w.amaxB, w.f, w.qB, w.lB, st);
     return hipGetLastError();
 }
 
@@ -597,7 +616,7 @@ void fp8_shape(bool two, int v, Plan *p) {
 int64_t fp8_workspace_bytes(int64_t m, int64_t n, int64_t p, bool two) {
     const int64_t S = (n + SLAB8 - 1) / SLAB8;
     const int64_t rec = align256(ring::array_bytes(m, S)) + align256(ring::array_bytes(p, S));
-    return align256(4 * p) * 2 + align256(4 * m) + (two ? 2 : 1) * rec;
+    return align256(4 * p) * 2 + align256(4 * m) * 2 + (two ? 2 : 1) * rec;
 }
 
 hipError_t launch_fp8(const moa_gemm_desc &d, const Plan &plan, void *ws, hipStream_t st) {

@@ -49,8 +49,9 @@ moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group
             if (d.m == 0 || d.p == 0) continue;
             Plan pl;
             if ((s = make_plan(d, &pl)) != MOA_OK) return s;
-            if (split_k_requested(d) > 1)
-                return fail(MOA_ERR_UNSUPPORTED, "member %lld asks for split-k: not in a prepared group", (long long)k);
+            if (split_k_requested(d) > 1 || has_col_operand(d))
+                return fail(MOA_ERR_UNSUPPORTED, "member %lld asks for split-k or a column-major operand: "
+                            "not in a prepared group", (long long)k);
             if (pl.path == MOA_PATH_SPLIT_BF16) split.push_back(&d);
             else if (pl.path == MOA_PATH_FP8_SCALED) fp8[(d.flags & MOA_FLAG_FP8_TWO_TERM) ? 1 : 0].push_back(&d);
             else if (pl.workspace_bytes == 0) single.push_back(d);

@@ -125,7 +125,8 @@ moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t st
         const moa_gemm_desc &d = descs[g];
         if (d.m == 0 || d.p == 0) continue;
         const moa_path path = resolve_path(d);
-        if (split_k_requested(d) > 1) {          // the persistent launches do not split k
+        if (split_k_requested(d) > 1 || has_col_operand(d)) {   // the persistent launches take
+                                                                  // row-major, unsplit members
             moa_status s = run_gemm(d, stream);
             if (s != MOA_OK) return s;
         } else if (path == MOA_PATH_SPLIT_BF16) {

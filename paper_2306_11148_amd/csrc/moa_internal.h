@@ -48,6 +48,25 @@ struct Plan {
     int64_t partial_offset = 0;   // byte offset of the split-k partials in the workspace
 };
 
+// A descriptor with a column-major C rewritten as the product C^T = B^T A^T
+// with a row-major result: A and B swap (with their layouts flipped: a
+// row-major A read as A^T is column-major), m and p swap. Other descriptors
+// are returned unchanged. The rewritten descriptor has no MOA_FLAG_C_COL.
+inline moa_gemm_desc row_major_result(const moa_gemm_desc &d) {
+    if (!(d.flags & MOA_FLAG_C_COL)) return d;
+    moa_gemm_desc t = d;
+    t.m = d.p;
+    t.p = d.m;
+    t.A = d.B;
+    t.B = d.A;
+    uint32_t f = d.flags & ~MOA_FLAG_LAYOUT_MASK;
+    if (!(d.flags & MOA_FLAG_B_COL)) f |= MOA_FLAG_A_COL;
+    if (!(d.flags & MOA_FLAG_A_COL)) f |= MOA_FLAG_B_COL;
+    t.flags = f;
+    return t;
+}
+inline bool has_col_operand(const moa_gemm_desc &d) { return (d.flags & MOA_FLAG_LAYOUT_MASK) != 0; }
+
 // Chunk count asked for by MOA_FLAG_SPLIT_K (0 or 1: none).
 inline int split_k_requested(const moa_gemm_desc &d) { return (int)((d.flags & MOA_FLAG_SPLIT_K_MASK) >> 16); }
 // Chunks actually used for S slabs: ceil(S / ceil(S / c)), so none is empty.

@@ -126,7 +126,8 @@ static int64_t tiles_for(int64_t m, int64_t p, int tm, int tn) {
     return ((m + tm - 1) / tm) * ((p + tn - 1) / tn);
 }
 
-moa_status make_plan(const moa_gemm_desc &d, Plan *out) {
+moa_status make_plan(const moa_gemm_desc &d_in, Plan *out) {
+    const moa_gemm_desc d = row_major_result(d_in);   // a column-major C is planned as C^T
     Plan pl;
     pl.path = resolve_path(d);
     const int64_t es = d.dtype == MOA_F64 ? 8 : 4;

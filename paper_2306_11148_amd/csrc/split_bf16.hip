@@ -367,6 +367,26 @@ void split_bf16_shape(int v, Plan *p) {
     p->lds_bytes = s.stages * (s.bm + s.bn) * REC_BYTES;
 }
 
+namespace {
+// Records of the `rows` rows of a row-major rows x K array.
+void rows_records(const float *X, int64_t rows, int64_t K, int64_t S, uint8_t *P, hipStream_t st) {
+    const int vec = (K % 8 == 0) && ((uintptr_t)X % 16 == 0);
+    int64_t blocks = (padded_rows(rows) * S * 2 + 255) / 256;
+    if (blocks > 65536) blocks = 65536;
+    hipLaunchKernelGGL(pack_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, st, X, rows, K, S, vec, P);
+}
+// Records of the `cols` columns of a row-major K x cols array.
+void cols_records(const float *X, int64_t K, int64_t cols, int64_t S, uint8_t *P, hipStream_t st) {
+    const int vec = (cols % 4 == 0) && ((uintptr_t)X % 16 == 0);
+    const int64_t by = ((S + 3) / 4 + COL_BLOCKS - 1) / COL_BLOCKS;
+    hipLaunchKernelGGL(pack_cols_kernel, dim3((unsigned)((cols + 63) / 64), (unsigned)(by < 65535 ? by : 65535)),
+                       dim3(256), 0, st, X, K, cols, S, vec, P);
+}
+}  // namespace
+
+// Records of A's rows and B's columns. A column-major A (element (i, k) at
+// i + k m) is a row-major n x m array whose columns are A's rows; a
+// column-major B is a row-major p x n array whose rows are B's columns.
 hipError_t launch_split_pack(const moa_gemm_desc &d, void *ws, hipStream_t st) {
     const int64_t S = (d.n + SLAB - 1) / SLAB;
     uint8_t *Ap = static_cast<uint8_t *>(ws);
@@ -374,15 +394,10 @@ hipError_t launch_split_pack(const moa_gemm_desc &d, void *ws, hipStream_t st) {
     const float *A = static_cast<const float *>(d.A);
     const float *B = static_cast<const float *>(d.B);
     if (S == 0) return hipSuccess;
-    const int vec = (d.n % 8 == 0) && ((uintptr_t)A % 16 == 0);
-    const int64_t chunks = padded_rows(d.m) * S * 2;
-    int64_t blocks = (chunks + 255) / 256;
-    if (blocks > 65536) blocks = 65536;
-    hipLaunchKernelGGL(pack_rows_kernel, dim3((unsigned)blocks), dim3(256), 0, st, A, d.m, d.n, S, vec, Ap);
-    const int vec_b = (d.p % 4 == 0) && ((uintptr_t)B % 16 == 0);
-    const int64_t by = ((S + 3) / 4 + COL_BLOCKS - 1) / COL_BLOCKS;
-    hipLaunchKernelGGL(pack_cols_kernel, dim3((unsigned)((d.p + 63) / 64), (unsigned)(by < 65535 ? by : 65535)),
-                       dim3(256), 0, st, B, d.n, d.p, S, vec_b, Bp);
+    if (d.flags & MOA_FLAG_A_COL) cols_records(A, d.n, d.m, S, Ap, st);
+    else rows_records(A, d.m, d.n, S, Ap, st);
+    if (d.flags & MOA_FLAG_B_COL) rows_records(B, d.p, d.n, S, Bp, st);
+    else cols_records(B, d.n, d.p, S, Bp, st);
     return hipGetLastError();
 }
 

@@ -32,6 +32,9 @@ def MOA_FLAG_SPLIT_K(c: int) -> int:
     return (c & 0xFF) << 16
 
 
+MOA_FLAG_A_COL, MOA_FLAG_B_COL, MOA_FLAG_C_COL = 0x1000000, 0x2000000, 0x4000000
+
+
 class MoaError(RuntimeError):
     def __init__(self, status: int, where: str, message: str):
         super().__init__(f"{where}: {status_name(status)}: {message}")
@@ -164,11 +167,26 @@ def _dtype_code(t) -> int:
     raise TypeError(f"unsupported dtype {t.dtype}")
 
 
+def _layout_flag(name, t, col_flag):
+    """0 for a row-major (contiguous) 2-D tensor, col_flag for a column-major
+    one (the transpose of a contiguous tensor, e.g. X.t()); anything else is
+    refused."""
+    if t.dim() != 2:
+        raise ValueError(f"{name} must be a 2-D tensor")
+    if t.is_contiguous():
+        return 0
+    if t.t().is_contiguous():
+        return col_flag
+    raise ValueError(f"{name} must be row-major (contiguous) or column-major (the transpose of a contiguous "
+                     f"tensor), Eq. 4 and the gamma_col layout")
+
+
 def make_desc(A, B, C, path=MOA_PATH_AUTO, accumulate=False, flags=0) -> moa_gemm_desc:
-    """Descriptor for C (:= or +=) A.B from 2-D contiguous device tensors."""
-    for name, t in (("A", A), ("B", B), ("C", C)):
-        if t.dim() != 2 or not t.is_contiguous():
-            raise ValueError(f"{name} must be a contiguous 2-D tensor (row-major, Eq. 4)")
+    """Descriptor for C (:= or +=) A.B from 2-D device tensors, each row-major
+    (contiguous) or column-major (the transpose of a contiguous tensor); the
+    layout flags follow from the strides."""
+    flags |= (_layout_flag("A", A, MOA_FLAG_A_COL) | _layout_flag("B", B, MOA_FLAG_B_COL) |
+              _layout_flag("C", C, MOA_FLAG_C_COL))
     m, n = A.shape
     if B.shape[0] != n or tuple(C.shape) != (m, B.shape[1]):
         raise ValueError(f"shapes {tuple(A.shape)} x {tuple(B.shape)} -> {tuple(C.shape)} do not conform")

@@ -112,7 +112,29 @@ def test_split_k_plan():
     assert f8["split_k"] == 4 and f8["tile_k"] == 64          # 10 slabs of 64 -> chunks of 3 -> 4
     assert call(_desc(8, 8, 8, moa.MOA_F32, moa.MOA_PATH_ONF, flags=moa.MOA_FLAG_SPLIT_K(2))) == \
         moa.MOA_ERR_UNSUPPORTED
-    assert call(_desc(8, 8, 8, flags=1 << 24)) == moa.MOA_ERR_INVALID
+    assert call(_desc(8, 8, 8, flags=1 << 28)) == moa.MOA_ERR_INVALID
+
+
+def test_layout_flags():
+    """gamma_col operands: any combination on the ring paths, all-or-nothing on
+    ONF / FP32 matrix cores; make_desc reads the layout from the strides."""
+    import torch
+    F32 = moa.MOA_F32
+    allcol = moa.MOA_FLAG_A_COL | moa.MOA_FLAG_B_COL | moa.MOA_FLAG_C_COL
+    assert call(_desc(8, 8, 8, F32, moa.MOA_PATH_ONF, flags=moa.MOA_FLAG_A_COL)) == moa.MOA_ERR_UNSUPPORTED
+    assert call(_desc(8, 8, 8, F32, moa.MOA_PATH_MFMA_F32, flags=moa.MOA_FLAG_C_COL)) == moa.MOA_ERR_UNSUPPORTED
+    assert moa.moa_plan_query(_desc(8, 8, 8, F32, moa.MOA_PATH_ONF, flags=allcol))["path"] == moa.MOA_PATH_ONF
+    for f in range(8):
+        q = moa.moa_plan_query(_desc(100, 300, 2000, F32, moa.MOA_PATH_SPLIT_BF16, flags=f << 24))
+        assert q["workgroups"] == 16
+    A = torch.zeros(30, 20).t()                   # logical 20 x 30, column-major
+    B = torch.zeros(30, 40)
+    C = torch.zeros(20, 80)[:, ::2]               # every other column: neither layout
+    d = moa.make_desc(A, B, torch.zeros(40, 20).t())
+    assert (d.m, d.n, d.p) == (20, 30, 40)
+    assert d.flags == moa.MOA_FLAG_A_COL | moa.MOA_FLAG_C_COL
+    with pytest.raises(ValueError):
+        moa.make_desc(A, B, C)
 
 
 def call(d):
