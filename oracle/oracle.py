@@ -25,6 +25,15 @@ Contents, each with the passage it follows:
   with amax * 2^e <= 448 (e = 0 for an all-zero row or column). The scales
   factor out of the k-sum, so C = 2^-(e_i+f_j) * sum_k qA[i,k] qB[k,j].
 
+* ``hadamard`` / ``kronecker`` -- the Hadamard and Kronecker products the
+  paper places with the matrix product in one family (ipophp, conclusion and
+  appendix), written from their textbook definitions: C[i,j] = A[i,j] B[i,j];
+  for A m x n and B p x q, C[i p + k, j q + l] = A[i,j] B[k,l]. Each element is
+  one product rounded to the input precision; the accumulate form adds the
+  rounded product to C with a second rounding (no fused multiply-add).
+* ``gemm_batched`` -- a batch of independent products C[b] = A[b] B[b], the
+  3-d contraction as "many parallel 2-d versions" (appendix).
+
 Every function takes numpy arrays and returns numpy arrays.
 """
 from __future__ import annotations
@@ -306,3 +315,48 @@ def fp8_gemm_2term(A32, B32):
     acc = gemm_f64(hA, hB) + 2.0 ** -LO_SHIFT * (gemm_f64(hA, e4m3_decode(lB)) +
                                                   gemm_f64(e4m3_decode(lA), hB))
     return acc * np.exp2(-(e[:, None] + f[None, :]).astype(np.float64))
+
+
+# ---------------------------------------------------------------- ipophp --
+
+def _round_to(x64, dtype):
+    """FP64 values rounded once to `dtype` (FP64 holds every FP32 product and
+    sum of two FP32 values exactly or with innocuous double rounding)."""
+    return np.asarray(x64, dtype=np.float64).astype(dtype)
+
+
+def hadamard(A, B, C=None, accumulate=False):
+    """C[i,j] := A[i,j] * B[i,j] (or C[i,j] + that product), in A's precision."""
+    A = np.asarray(A)
+    dt = A.dtype
+    P = _round_to(A.astype(np.float64) * np.asarray(B, dtype=np.float64), dt)
+    if not accumulate:
+        return P
+    return _round_to(P.astype(np.float64) + np.asarray(C, dtype=np.float64), dt)
+
+
+def kronecker(A, B, C=None, accumulate=False):
+    """A (m x n), B (p x q) -> C ((m p) x (n q)) with C[i p + k, j q + l] =
+    A[i,j] B[k,l]: block (i, j) of C is A[i,j] times B."""
+    A = np.asarray(A)
+    B = np.asarray(B)
+    dt = A.dtype
+    m, n = A.shape
+    p, q = B.shape
+    B64 = B.astype(np.float64)
+    out = np.empty((m * p, n * q), dtype=dt)
+    for i in range(m):
+        for j in range(n):
+            blk = _round_to(float(A[i, j]) * B64, dt)
+            if accumulate:
+                blk = _round_to(blk.astype(np.float64) + np.asarray(C, dtype=np.float64)[i * p:(i + 1) * p,
+                                                                                          j * q:(j + 1) * q], dt)
+            out[i * p:(i + 1) * p, j * q:(j + 1) * q] = blk
+    return out
+
+
+def gemm_batched(A, B):
+    """C[b] = A[b] B[b] (Eq. 3 per member, FP64) for 3-d arrays A (batch x m x n)
+    and B (batch x n x p)."""
+    return np.stack([gemm_f64(np.asarray(A[b], dtype=np.float64), np.asarray(B[b], dtype=np.float64))
+                     for b in range(len(A))])

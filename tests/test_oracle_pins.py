@@ -302,3 +302,58 @@ def test_reduced_precision_error_levels():
     assert e_split < 1e-5
     assert 1e-2 < e_fp8 < 6e-2          # 4 significant bits per operand
     assert e_fp8_2 < 3e-3
+
+
+# ------------------------------------------------- ipophp family (f3) --
+
+def test_kronecker_golden_hand_values():
+    g = json.load(open(os.path.join(GOLDEN, "kronecker_small.json")))
+    for a, b, c in (("A", "B", "C"), ("A2", "B2", "C2")):
+        A = np.array(g[a], np.float64)
+        B = np.array(g[b], np.float64)
+        assert np.array_equal(O.kronecker(A, B), np.array(g[c], np.float64))
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_kronecker_matches_library_and_identities(dt):
+    rng = np.random.default_rng(5)
+    A = rng.standard_normal((3, 4)).astype(dt)
+    B = rng.standard_normal((5, 2)).astype(dt)
+    assert np.array_equal(O.kronecker(A, B), np.kron(A, B))
+    # transpose: (A (x) B)^T = A^T (x) B^T
+    assert np.array_equal(O.kronecker(A, B).T, O.kronecker(A.T.copy(), B.T.copy()))
+    # mixed product on integers (exact): (A (x) B)(C (x) D) = (AC) (x) (BD)
+    Ai = rng.integers(-3, 4, (2, 3)).astype(np.float64)
+    Bi = rng.integers(-3, 4, (3, 2)).astype(np.float64)
+    Ci = rng.integers(-3, 4, (3, 2)).astype(np.float64)
+    Di = rng.integers(-3, 4, (2, 4)).astype(np.float64)
+    lhs = O.gemm_f64(O.kronecker(Ai, Bi), O.kronecker(Ci, Di))
+    rhs = O.kronecker(O.gemm_f64(Ai, Ci), O.gemm_f64(Bi, Di))
+    assert np.array_equal(lhs, rhs)
+    # identity (x) B is block diagonal
+    K = O.kronecker(np.eye(3, dtype=dt), B)
+    for i in range(3):
+        for j in range(3):
+            blk = K[i * 5:(i + 1) * 5, j * 2:(j + 1) * 2]
+            assert np.array_equal(blk, B if i == j else np.zeros_like(B))
+
+
+@pytest.mark.parametrize("dt", [np.float32, np.float64])
+def test_hadamard_matches_library_and_accumulate_rounding(dt):
+    rng = np.random.default_rng(6)
+    A = rng.standard_normal((7, 9)).astype(dt)
+    B = rng.standard_normal((7, 9)).astype(dt)
+    C = rng.standard_normal((7, 9)).astype(dt)
+    assert np.array_equal(O.hadamard(A, B), np.multiply(A, B))
+    assert np.array_equal(O.hadamard(A, B), O.hadamard(B, A))
+    # accumulate = two roundings in the input precision (numpy's own arithmetic)
+    assert np.array_equal(O.hadamard(A, B, C, accumulate=True), (A * B) + C)
+    K = O.kronecker(A[:2, :3], B[:3, :2], O.kronecker(A[:2, :3], B[:3, :2]), accumulate=True)
+    assert np.array_equal(K, np.kron(A[:2, :3], B[:3, :2]) * dt(2))
+
+
+def test_gemm_batched_members():
+    rng = np.random.default_rng(7)
+    A = rng.integers(-8, 9, (3, 4, 5)).astype(np.float64)
+    B = rng.integers(-8, 9, (3, 5, 6)).astype(np.float64)
+    assert np.array_equal(O.gemm_batched(A, B), np.matmul(A, B))
