@@ -47,6 +47,9 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=5000.0)
     ap.add_argument("--serve-seconds", type=float, default=1.0)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--ipophp", action="store_true",
+                    help="time the Hadamard and Kronecker products (against the HBM roofline) and a batched "
+                         "product, one JSON line per point")
     ap.add_argument("--layouts", action="store_true",
                     help="time the N x N product for every row-/column-major combination of A, B, C "
                          "(gamma_row / gamma_col), one JSON line per point")
@@ -433,6 +436,50 @@ def sweep(args, torch, moa, inputs):
         del A, B, C
 
 
+def ipophp_section(torch, moa):
+    """Hadamard (m x n), Kronecker (A m x n, B p x q) and batched products.
+    The first two are HBM-bound: achieved = algorithmic bytes (read A and B,
+    write C; C also read when accumulating) / time, against 8 TB/s."""
+    gen = torch.Generator(device="cuda").manual_seed(21)
+    for dt, es in ((torch.float32, 4), (torch.float64, 8)):
+        N = 8192
+        A = torch.randn((N, N), generator=gen, device="cuda", dtype=dt)
+        B = torch.randn((N, N), generator=gen, device="cuda", dtype=dt)
+        C = torch.empty((N, N), device="cuda", dtype=dt)
+        for acc in (False, True):
+            moa.moa_hadamard(A, B, C, accumulate=acc)
+            per, tot = timed_loop(lambda: moa.moa_hadamard(A, B, C, accumulate=acc), 20, torch)
+            ms = tot / 20
+            nbytes = (4 if acc else 3) * N * N * es
+            print(json.dumps({"ipophp": {"op": "hadamard", "dtype": str(dt).split(".")[-1], "m": N, "n": N,
+                                         "accumulate": acc, "ms": round(ms, 4), "bytes": nbytes,
+                                         "GBps": round(nbytes / ms / 1e6, 1),
+                                         "frac_of_8TBps": round(nbytes / ms / 1e6 / 8000.0, 3)}}), flush=True)
+        del A, B, C
+        a = torch.randn((64, 64), generator=gen, device="cuda", dtype=dt)
+        b = torch.randn((128, 128), generator=gen, device="cuda", dtype=dt)
+        K = torch.empty((8192, 8192), device="cuda", dtype=dt)
+        moa.moa_kronecker(a, b, K)
+        per, tot = timed_loop(lambda: moa.moa_kronecker(a, b, K), 20, torch)
+        ms = tot / 20
+        nbytes = 8192 * 8192 * es + (64 * 64 + 128 * 128) * es
+        print(json.dumps({"ipophp": {"op": "kronecker", "dtype": str(dt).split(".")[-1], "A": [64, 64],
+                                     "B": [128, 128], "ms": round(ms, 4), "bytes": nbytes,
+                                     "GBps": round(nbytes / ms / 1e6, 1),
+                                     "frac_of_8TBps": round(nbytes / ms / 1e6 / 8000.0, 3)}}), flush=True)
+        del K
+    batch, m, n, p = 64, 512, 512, 512
+    A = torch.randn((batch, m, n), generator=gen, device="cuda")
+    B = torch.randn((batch, n, p), generator=gen, device="cuda")
+    C = torch.empty((batch, m, p), device="cuda")
+    moa.moa_gemm_batched(A, B, C, path="split_bf16")
+    per, tot = timed_loop(lambda: moa.moa_gemm_batched(A, B, C, path="split_bf16"), 20, torch)
+    ms = tot / 20
+    print(json.dumps({"ipophp": {"op": "batched", "path": "split_bf16", "batch": batch, "m": m, "n": n, "p": p,
+                                 "ms": round(ms, 4), "tflops": round(2.0 * batch * m * n * p / ms / 1e9, 2)}}),
+          flush=True)
+
+
 def layout_sweep(args, torch, moa):
     """Time per N x N product for each layout of A, B and C (row-major or
     column-major, the latter passed as the transpose of a contiguous tensor)."""
@@ -551,6 +598,9 @@ def main():
         return
     if args.layouts:
         layout_sweep(args, torch, moa)
+        return
+    if args.ipophp:
+        ipophp_section(torch, moa)
         return
     if args.serve_rates:
         for rate in [float(x) for x in args.serve_rates.split(",")]:

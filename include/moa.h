@@ -175,6 +175,35 @@ moa_status moa_gemm(const moa_gemm_desc *desc, void *stream);
 moa_status moa_gemm_grouped(const moa_gemm_desc *descs, int64_t count,
                             void *stream);
 
+/* The ipophp family (conclusion and appendix: the Hadamard, Kronecker and
+ * matrix products in one formulation, higher-dimensional contractions as
+ * many parallel 2-d products). A, B, C are row-major device arrays of
+ * `dtype` (MOA_F32 or MOA_F64), asynchronous on `stream`. Each element is one
+ * product rounded to the element type; with `accumulate` the rounded product
+ * is added to C with a second rounding (no fused multiply-add), so results
+ * are bitwise those of the definitions.
+ *
+ * Hadamard: C[i][j] := A[i][j] B[i][j] for m x n arrays. C may be A or B
+ * itself (in place) but must not overlap them otherwise (MOA_ERR_INVALID).
+ * Errors: MOA_ERR_SHAPE (negative or overflowing size), MOA_ERR_INVALID (null
+ * pointer with a non-empty shape, unknown dtype, misalignment). */
+moa_status moa_hadamard(int64_t m, int64_t n, int32_t dtype, const void *A, const void *B, void *C,
+                        int32_t accumulate, void *stream);
+
+/* Kronecker: A m x n, B p x q, C (m p) x (n q) with
+ * C[i p + k][j q + l] := A[i][j] B[k][l]. C must not overlap A or B; n q must
+ * stay below 2^31 (MOA_ERR_SHAPE). Errors as moa_hadamard. */
+moa_status moa_kronecker(int64_t m, int64_t n, int64_t p, int64_t q, int32_t dtype, const void *A,
+                         const void *B, void *C, int32_t accumulate, void *stream);
+
+/* Batched products C[b] := A[b] B[b], b = 0 .. batch-1 (the 3-d contraction
+ * as parallel 2-d products): member b is *first with A, B, C advanced by
+ * b stride_a, b stride_b, b stride_c elements. Runs as moa_gemm_grouped over
+ * the members (one persistent launch per path), with its checks and errors;
+ * MOA_ERR_INVALID for a negative batch or stride. */
+moa_status moa_gemm_batched(const moa_gemm_desc *first, int64_t batch, int64_t stride_a, int64_t stride_b,
+                            int64_t stride_c, void *stream);
+
 /* Prepared groups: a fixed set of products launched many times. Creation
  * validates the members as moa_gemm_grouped does, allocates a workspace owned
  * by the group, uploads the member list once and captures the whole grouped
@@ -263,7 +292,9 @@ typedef enum moa_kernel {
     MOA_K_FP8_QUANT = 8,      /* FP8 operand conditioning */
     MOA_K_SPLIT_GROUPED = 9,  /* grouped persistent split-BF16 contraction */
     MOA_K_FP8_GROUPED = 10,   /* grouped persistent scaled-FP8 contraction */
-    MOA_K_COUNT = 11
+    MOA_K_HADAMARD = 11,      /* Hadamard product */
+    MOA_K_KRONECKER = 12,     /* Kronecker product */
+    MOA_K_COUNT = 13
 } moa_kernel;
 
 typedef struct moa_trace_stat {

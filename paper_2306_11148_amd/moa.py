@@ -79,10 +79,12 @@ EXPORTS = [
     "moa_status_string", "moa_last_error", "moa_trace_enable", "moa_trace_read",
     "moa_group_create", "moa_group_launch", "moa_group_destroy",
     "moa_autotune", "moa_autotune_save", "moa_autotune_load", "moa_autotune_clear",
+    "moa_hadamard", "moa_kronecker", "moa_gemm_batched",
 ]
 
 MOA_KERNELS = {1: "onf_f64", 2: "onf_f32", 3: "mfma_f32", 4: "split_bf16", 5: "fp8", 6: "fp8_2term",
-               7: "split_pack", 8: "fp8_quant", 9: "split_grouped", 10: "fp8_grouped"}
+               7: "split_pack", 8: "fp8_quant", 9: "split_grouped", 10: "fp8_grouped", 11: "hadamard",
+               12: "kronecker"}
 
 
 class moa_trace_stat(ctypes.Structure):
@@ -127,6 +129,9 @@ def lib():
         "moa_group_launch": ([vp, vp], i32),
         "moa_group_destroy": ([vp], i32),
         "moa_trace_read": ([P(moa_trace_stat), i32, P(i32), i32], i32),
+        "moa_hadamard": ([i64, i64, i32, vp, vp, vp, i32, vp], i32),
+        "moa_kronecker": ([i64, i64, i64, i64, i32, vp, vp, vp, i32, vp], i32),
+        "moa_gemm_batched": ([P(moa_gemm_desc), i64, i64, i64, i64, vp], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -334,3 +339,55 @@ def moa_autotune_load(path: str):
 
 def moa_autotune_clear():
     _check(lib().moa_autotune_clear(), "moa_autotune_clear")
+
+
+# ----------------------------------------------------------- ipophp family --
+
+def _rowmajor(name, t):
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous (row-major)")
+    return t.data_ptr() if t.numel() else None
+
+
+def moa_hadamard(A, B, C, accumulate=False, stream=None):
+    """C := A * B elementwise (or C += A * B) for equal-shape 2-D tensors."""
+    if A.dim() != 2 or tuple(A.shape) != tuple(B.shape) or tuple(A.shape) != tuple(C.shape):
+        raise ValueError("A, B and C must be 2-D tensors of one shape")
+    dt = _dtype_code(A)
+    if _dtype_code(B) != dt or _dtype_code(C) != dt:
+        raise TypeError("A, B and C must share one dtype")
+    _check(lib().moa_hadamard(A.shape[0], A.shape[1], dt, _rowmajor("A", A), _rowmajor("B", B),
+                              _rowmajor("C", C), int(bool(accumulate)), _stream_handle(stream)), "moa_hadamard")
+    return C
+
+
+def moa_kronecker(A, B, C, accumulate=False, stream=None):
+    """C := A (x) B (or +=): A m x n, B p x q, C (m p) x (n q)."""
+    m, n = A.shape
+    p, q = B.shape
+    if tuple(C.shape) != (m * p, n * q):
+        raise ValueError(f"C must be {(m * p, n * q)}")
+    dt = _dtype_code(A)
+    if _dtype_code(B) != dt or _dtype_code(C) != dt:
+        raise TypeError("A, B and C must share one dtype")
+    _check(lib().moa_kronecker(m, n, p, q, dt, _rowmajor("A", A), _rowmajor("B", B), _rowmajor("C", C),
+                               int(bool(accumulate)), _stream_handle(stream)), "moa_kronecker")
+    return C
+
+
+def moa_gemm_batched(A, B, C, path=MOA_PATH_AUTO, accumulate=False, flags=0, stream=None):
+    """C[b] := A[b] B[b] for contiguous 3-D tensors (batch x m x n, batch x n x p,
+    batch x m x p)."""
+    if A.dim() != 3 or B.dim() != 3 or C.dim() != 3:
+        raise ValueError("A, B and C must be 3-D tensors")
+    batch = A.shape[0]
+    if B.shape[0] != batch or C.shape[0] != batch:
+        raise ValueError("batch sizes differ")
+    d = make_desc(A[0], B[0], C[0], path, accumulate, flags) if batch else None
+    if d is None:
+        return C
+    for name, t in (("A", A), ("B", B), ("C", C)):
+        _rowmajor(name, t)
+    _check(lib().moa_gemm_batched(ctypes.byref(d), batch, A.stride(0), B.stride(0), C.stride(0),
+                                  _stream_handle(stream)), "moa_gemm_batched")
+    return C

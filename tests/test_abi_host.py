@@ -137,6 +137,25 @@ def test_layout_flags():
         moa.make_desc(A, B, C)
 
 
+def test_ipophp_argument_errors_are_synchronous():
+    L = moa.lib()
+    F32, F64 = moa.MOA_F32, moa.MOA_F64
+    assert L.moa_hadamard(-1, 2, F32, 0x1000, 0x2000, 0x3000, 0, None) == moa.MOA_ERR_SHAPE
+    assert L.moa_hadamard(2, 2, 7, 0x1000, 0x2000, 0x3000, 0, None) == moa.MOA_ERR_INVALID
+    assert L.moa_hadamard(2, 2, F32, None, 0x2000, 0x3000, 0, None) == moa.MOA_ERR_INVALID
+    assert L.moa_hadamard(2, 2, F64, 0x1004, 0x2000, 0x3000, 0, None) == moa.MOA_ERR_INVALID    # misaligned
+    assert L.moa_hadamard(4, 4, F32, 0x1000, 0x2000, 0x1000 + 8, 0, None) == moa.MOA_ERR_INVALID  # shifted C
+    assert L.moa_hadamard(0, 5, F32, None, None, None, 0, None) == moa.MOA_OK                  # empty: no-op
+    assert L.moa_kronecker(2, 1 << 16, 2, 1 << 16, F32, 0x1000, 0x2000, 0x3000, 0, None) == moa.MOA_ERR_SHAPE
+    assert L.moa_kronecker(2, 2, 2, 2, F32, 0x1000, 0x2000, 0x1000, 0, None) == moa.MOA_ERR_INVALID  # C on A
+    assert L.moa_kronecker(0, 3, 4, 5, F32, None, None, None, 0, None) == moa.MOA_OK
+    d = _desc(4, 4, 4)
+    assert L.moa_gemm_batched(ctypes.byref(d), -1, 16, 16, 16, None) == moa.MOA_ERR_INVALID
+    assert L.moa_gemm_batched(ctypes.byref(d), 0, 16, 16, 16, None) == moa.MOA_OK
+    # members' C overlap each other (stride smaller than m p)
+    assert L.moa_gemm_batched(ctypes.byref(d), 3, 16, 16, 8, None) == moa.MOA_ERR_INVALID
+
+
 def call(d):
     return moa.lib().moa_gemm(ctypes.byref(d), None)
 
