@@ -69,7 +69,7 @@ moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group
                 release(g);
                 return fail(MOA_ERR_NOMEM, "group workspace: %s", hipGetErrorString(e));
             }
-            std::vector<char> host((size_t)split_grouped_desc_bytes(cnt));
+            std::vector<char> host((size_t)split_grouped_desc_bytes(split.data(), cnt));
             work = split_grouped_layout(split.data(), cnt, g->ws, host.data());
             e = hipMemcpy(static_cast<char *>(g->ws) + 256, host.data(), host.size(), hipMemcpyHostToDevice);
             if (e != hipSuccess) {

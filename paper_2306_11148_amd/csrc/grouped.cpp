@@ -139,7 +139,7 @@ moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t st
         }
     }
     moa_status s = run_list(
-        split, split_grouped_desc_bytes((int)split.size()), split_grouped_workspace_bytes,
+        split, split_grouped_desc_bytes(split.data(), (int)split.size()), split_grouped_workspace_bytes,
         [&](const moa_gemm_desc *const *m, int c, void *ws, void *host) {
             return launch_split_grouped(m, c, ws, host, stream);
         },

@@ -135,7 +135,7 @@ int64_t split_bf16_workspace_bytes(int64_t m, int64_t n, int64_t p);
 // split_grouped_desc_bytes(count) bytes that stays untouched until the
 // stream has passed this call.
 int64_t split_grouped_workspace_bytes(const moa_gemm_desc *const *members, int count);
-int64_t split_grouped_desc_bytes(int count);
+int64_t split_grouped_desc_bytes(const moa_gemm_desc *const *members, int count);
 hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, void *workspace,
                                 void *host_staging, hipStream_t stream);
 // The two halves of launch_split_grouped: host layout (returns the sizes of

@@ -247,18 +247,10 @@ struct GroupMember {
     int32_t col_blocks_x;               // then col_blocks_x * ceil(S/4) 64 x 64 blocks of B
 };
 
-__device__ __forceinline__ int find_member(const GroupMember *__restrict__ g, int count, int64_t tile) {
-    int lo = 0, hi = count - 1;         // last member with first_tile <= tile
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (g[mid].first_tile <= tile) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
 
 template <int BM, int BN, int WM, int WN>
 __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void split_grouped_kernel(
-    const GroupMember *__restrict__ g, int count, int64_t total_tiles,
+    const GroupMember *__restrict__ g, const int32_t *__restrict__ tile_owner, int64_t total_tiles,
     unsigned long long *__restrict__ counter) {
     __shared__ __attribute__((aligned(1024))) uint8_t lds[ring::Cfg<BM, BN, WM, WN, 1>::LDS];
     __shared__ int64_t s_tile;
@@ -268,7 +260,7 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void split_grouped_kern
         __syncthreads();
         const int64_t tile = s_tile;
         if (tile >= total_tiles) break;
-        const int k = __builtin_amdgcn_readfirstlane(find_member(g, count, tile));
+        const int k = __builtin_amdgcn_readfirstlane(tile_owner[tile]);
         const GroupMember &d = g[k];
         const int64_t local = tile - d.first_tile;
         const int64_t tm = local / d.tiles_n, tn = local - tm * d.tiles_n;
@@ -280,23 +272,15 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void split_grouped_kern
 // Grouped conditioning: one work list over every member, each member
 // contributing row items (256 chunks of A each) followed by 64-column x 64-k
 // blocks of B; workgroups stride through the list, so large and small members
-// share the machine evenly.
+// share the machine evenly. item_owner[item] names the member (a table built
+// on the host: one load instead of a search through the member list).
 constexpr int PACK_ROW_ITEM = 256;      // chunks per row item (one per thread)
 
-__device__ __forceinline__ int find_pack_member(const GroupMember *__restrict__ g, int count, int64_t item) {
-    int lo = 0, hi = count - 1;         // last member with pack_first <= item
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (g[mid].pack_first <= item) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
-__global__ __launch_bounds__(256) void grouped_pack_kernel(const GroupMember *__restrict__ g, int count,
-                                                           int64_t total) {
+__global__ __launch_bounds__(256) void grouped_pack_kernel(const GroupMember *__restrict__ g,
+                                                           const int32_t *__restrict__ item_owner, int64_t total) {
     __shared__ __attribute__((aligned(16))) float tile[4 * SLAB][64 + 4];
     for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-        const int k = __builtin_amdgcn_readfirstlane(find_pack_member(g, count, item));
+        const int k = __builtin_amdgcn_readfirstlane(item_owner[item]);
         const GroupMember &d = g[k];
         const int64_t local = item - d.pack_first;
         if (local < d.row_items) {
@@ -429,14 +413,34 @@ constexpr int GB_M = 128, GB_N = 128, GW_M = 64, GW_N = 64;   // grouped block s
 int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 }  // namespace
 
+namespace {
+// Tiles and conditioning items of a member list (independent of the order).
+GroupedWork grouped_counts(const moa_gemm_desc *const *members, int count) {
+    GroupedWork w{0, 0};
+    for (int k = 0; k < count; ++k) {
+        const moa_gemm_desc &d = *members[k];
+        const int64_t S = (d.n + SLAB - 1) / SLAB;
+        w.tiles += ((d.m + GB_M - 1) / GB_M) * ((d.p + GB_N - 1) / GB_N);
+        w.pack_items += (padded_rows(d.m) * S * 2 + PACK_ROW_ITEM - 1) / PACK_ROW_ITEM + ((d.p + 63) / 64) * ((S + 3) / 4);
+    }
+    return w;
+}
+// Member table, then tile -> member and item -> member tables (int32).
+int64_t table_bytes(int count, const GroupedWork &w) {
+    return align256((int64_t)count * (int64_t)sizeof(GroupMember)) + align256(4 * w.tiles) + align256(4 * w.pack_items);
+}
+}  // namespace
+
+int64_t split_grouped_desc_bytes(const moa_gemm_desc *const *members, int count) {
+    return table_bytes(count, grouped_counts(members, count));
+}
+
 int64_t split_grouped_workspace_bytes(const moa_gemm_desc *const *members, int count) {
-    int64_t b = 256 + align256((int64_t)count * (int64_t)sizeof(GroupMember));
+    int64_t b = 256 + split_grouped_desc_bytes(members, count);
     for (int k = 0; k < count; ++k)
         b += align256(split_bf16_workspace_bytes(members[k]->m, members[k]->n, members[k]->p));
     return b;
 }
-
-int64_t split_grouped_desc_bytes(int count) { return (int64_t)count * (int64_t)sizeof(GroupMember); }
 
 // Lays out the members (longest k walk first: the tail of the work list holds
 // the cheapest tiles) in `host_staging` and the workspace; returns the tile
@@ -448,9 +452,13 @@ GroupedWork split_grouped_layout(const moa_gemm_desc *const *members, int count,
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         return members[a]->n > members[b]->n;
     });
+    const GroupedWork totals = grouped_counts(members, count);
     char *base = static_cast<char *>(ws);
-    char *rec = base + 256 + align256((int64_t)count * (int64_t)sizeof(GroupMember));
+    char *rec = base + 256 + table_bytes(count, totals);
     GroupMember *h = static_cast<GroupMember *>(host_staging);
+    int32_t *tile_owner = reinterpret_cast<int32_t *>(static_cast<char *>(host_staging) +
+                                                      align256((int64_t)count * (int64_t)sizeof(GroupMember)));
+    int32_t *item_owner = tile_owner + align256(4 * totals.tiles) / 4;
     int64_t tiles = 0, items = 0;
     for (int q = 0; q < count; ++q) {
         const moa_gemm_desc &d = *members[order[q]];
@@ -467,11 +475,15 @@ GroupedWork split_grouped_layout(const moa_gemm_desc *const *members, int count,
         g.first_tile = tiles;
         g.tiles_n = (int32_t)((d.p + GB_N - 1) / GB_N);
         g.accumulate = d.accumulate;
-        tiles += ((d.m + GB_M - 1) / GB_M) * g.tiles_n;
+        const int64_t mt = ((d.m + GB_M - 1) / GB_M) * g.tiles_n;
+        for (int64_t t = 0; t < mt; ++t) tile_owner[tiles + t] = q;
+        tiles += mt;
         g.pack_first = items;
         g.row_items = (int32_t)((padded_rows(d.m) * g.S * 2 + PACK_ROW_ITEM - 1) / PACK_ROW_ITEM);
         g.col_blocks_x = (int32_t)((d.p + 63) / 64);
-        items += g.row_items + (int64_t)g.col_blocks_x * ((g.S + 3) / 4);
+        const int64_t mi = g.row_items + (int64_t)g.col_blocks_x * ((g.S + 3) / 4);
+        for (int64_t t = 0; t < mi; ++t) item_owner[items + t] = q;
+        items += mi;
         h[q] = g;
     }
     return {tiles, items};
@@ -485,18 +497,21 @@ hipError_t split_grouped_enqueue(void *ws, int count, const GroupedWork &work, h
     char *base = static_cast<char *>(ws);
     unsigned long long *counter = reinterpret_cast<unsigned long long *>(base);
     const GroupMember *dev_members = reinterpret_cast<const GroupMember *>(base + 256);
+    const int32_t *tile_owner = reinterpret_cast<const int32_t *>(
+        base + 256 + align256((int64_t)count * (int64_t)sizeof(GroupMember)));
+    const int32_t *item_owner = tile_owner + align256(4 * tiles) / 4;
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, st, counter);
     if (work.pack_items > 0) {
         TraceScope ts(MOA_K_SPLIT_PACK, st);
         const int64_t g = std::min<int64_t>(work.pack_items, 8 * kNumCUs);
-        hipLaunchKernelGGL(grouped_pack_kernel, dim3((unsigned)g), dim3(256), 0, st, dev_members, count,
+        hipLaunchKernelGGL(grouped_pack_kernel, dim3((unsigned)g), dim3(256), 0, st, dev_members, item_owner,
                            work.pack_items);
     }
     const int64_t grid = std::min<int64_t>(tiles, 2 * kNumCUs);   // two 64 KiB-LDS blocks per CU
     TraceScope ts(MOA_K_SPLIT_GROUPED, st);
     if (grid > 0)
         hipLaunchKernelGGL((split_grouped_kernel<GB_M, GB_N, GW_M, GW_N>), dim3((unsigned)grid),
-                           dim3(ring::Cfg<GB_M, GB_N, GW_M, GW_N, 1>::THREADS), 0, st, dev_members, count,
+                           dim3(ring::Cfg<GB_M, GB_N, GW_M, GW_N, 1>::THREADS), 0, st, dev_members, tile_owner,
                            tiles, counter);
     return hipGetLastError();
 }
@@ -506,7 +521,7 @@ hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, 
     if (count <= 0) return hipSuccess;
     const GroupedWork work = split_grouped_layout(members, count, ws, host_staging);
     char *base = static_cast<char *>(ws);
-    hipError_t e = hipMemcpyAsync(base + 256, host_staging, (size_t)count * sizeof(GroupMember),
+    hipError_t e = hipMemcpyAsync(base + 256, host_staging, (size_t)split_grouped_desc_bytes(members, count),
                                   hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return e;
     return split_grouped_enqueue(ws, count, work, st);
