@@ -416,7 +416,9 @@ def sweep(args, torch, moa, inputs):
         C = torch.empty((N, N), device="cuda")
         for name, path, flags in (("onf_f32", moa.MOA_PATH_ONF, 0),
                                   ("mfma_f32", moa.MOA_PATH_MFMA_F32, 0),
-                                  ("split_bf16", moa.MOA_PATH_SPLIT_BF16, 0)):
+                                  ("split_bf16", moa.MOA_PATH_SPLIT_BF16, 0),
+                                  ("fp8_1term", moa.MOA_PATH_FP8_SCALED, 0),
+                                  ("fp8_2term", moa.MOA_PATH_FP8_SCALED, moa.MOA_FLAG_FP8_TWO_TERM)):
             d = moa.make_desc(A, B, C, path=path, flags=flags)
             L, st = moa.lib(), torch.cuda.current_stream().cuda_stream
             import ctypes
