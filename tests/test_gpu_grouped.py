@@ -3,6 +3,9 @@
 * Each member's result is bitwise the result of moa_gemm on the same
   descriptor (the per-element operation sequence does not depend on which
   launch or block shape produced it).
+* Large groups (thousands of tiles, several claims per persistent workgroup)
+  are bitwise equal to moa_gemm as well, also on a second launch that reuses
+  the cached scratch.
 * The batching workload at full size -- 512 products, m, n, p log-uniform in
   [32, 2048], N(0,1) FP32 -- is checked member by member against the FP64
   oracle (normwise <= 1e-5).
@@ -89,6 +92,22 @@ def test_grouped_empty_members_and_empty_group():
     moa.moa_gemm_grouped([moa.make_desc(A2, B2, C2)])
     torch.cuda.synchronize()
     assert torch.all(C2 == 0)
+
+
+@pytest.mark.parametrize("accumulate", [False, True])
+def test_large_group_bitwise_equals_single(accumulate):
+    """64 products, m, n, p log-uniform in [256, 1500] (seed 31): 2381 tiles,
+    several claims per persistent workgroup."""
+    shapes = inputs.grouped_shapes(64, 256, 1500, seed=31)
+    host, dev, descs = make_members(shapes, seed=31, accumulate=accumulate)
+    for _ in range(2):                  # a second launch reuses the cached scratch
+        moa.moa_gemm_grouped(descs)
+        if accumulate:
+            break
+    torch.cuda.synchronize()
+    ref = singles(host, "split_bf16", accumulate)
+    for k, ((A, B, _), (_, _, Ct)) in enumerate(zip(host, dev)):
+        assert np.array_equal(Ct.cpu().numpy(), ref[k]), f"member {k} shape {A.shape} x {B.shape}"
 
 
 def test_grouped_batching_workload_full_size():
