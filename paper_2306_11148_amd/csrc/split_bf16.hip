@@ -82,7 +82,7 @@ __global__ __launch_bounds__(256) void pack_rows_kernel(const float *__restrict_
 
 // Columns of X (K x cols, row-major) -> records (transposed), 64 columns x
 // 64 k (4 slabs) per block through LDS: reads of X rows are contiguous
-// float4s and each thread writes one whole 64-byte record. Columns past
+// float4s and each thread writes two half records. Columns past
 // `cols` get zero records. All 256 threads must take part.
 struct ColBlockRegs { float4 v[4]; };
 
@@ -110,6 +110,11 @@ __device__ __forceinline__ void pack_cols_load(const float *__restrict__ X, int6
 }
 
 // Stores a loaded block to LDS, then (after a barrier) writes its records.
+// The 512 half records of the block (4 slabs x 64 columns x {k 0-7, k 8-15})
+// are taken two per thread; within a wave consecutive lanes take the two
+// halves of consecutive records, so that each 16-byte store instruction fills
+// half of every 64-byte record of two row tiles (as the row packer does),
+// rather than a quarter of 64 scattered records.
 __device__ __forceinline__ void pack_cols_emit(const ColBlockRegs &r, int64_t cols, int64_t S,
                                                uint8_t *__restrict__ P, int64_t bx, int64_t by,
                                                float (*tile)[64 + 4]) {
@@ -118,23 +123,22 @@ __device__ __forceinline__ void pack_cols_emit(const ColBlockRegs &r, int64_t co
     for (int i = 0; i < 4; ++i)
         *reinterpret_cast<float4 *>(&tile[(t >> 4) + 16 * i][(t & 15) * 4]) = r.v[i];
     __syncthreads();
-    const int jj = t & 63, part = t >> 6;
-    const int64_t j = bx * 64 + jj, s = by * 4 + part;
-    if (j < padded_rows(cols) && s < S) {
-        uint4 h[2], l[2];
 #pragma unroll
-        for (int c = 0; c < 2; ++c) {
+    for (int h = 0; h < 2; ++h) {
+        const int u = t + 256 * h;
+        const int c = u & 1, jj = (u >> 1) & 63, part = u >> 7;
+        const int64_t j = bx * 64 + jj, s = by * 4 + part;
+        if (j < padded_rows(cols) && s < S) {
             const int kb = part * SLAB + c * 8;
-            split_pair(tile[kb + 0][jj], tile[kb + 1][jj], &h[c].x, &l[c].x);
-            split_pair(tile[kb + 2][jj], tile[kb + 3][jj], &h[c].y, &l[c].y);
-            split_pair(tile[kb + 4][jj], tile[kb + 5][jj], &h[c].z, &l[c].z);
-            split_pair(tile[kb + 6][jj], tile[kb + 7][jj], &h[c].w, &l[c].w);
+            uint4 hi, lo;
+            split_pair(tile[kb + 0][jj], tile[kb + 1][jj], &hi.x, &lo.x);
+            split_pair(tile[kb + 2][jj], tile[kb + 3][jj], &hi.y, &lo.y);
+            split_pair(tile[kb + 4][jj], tile[kb + 5][jj], &hi.z, &lo.z);
+            split_pair(tile[kb + 6][jj], tile[kb + 7][jj], &hi.w, &lo.w);
+            uint8_t *rec = P + ring::rec_byte(j, s, S);
+            *reinterpret_cast<uint4 *>(rec + c * 16) = hi;          // hi: bytes 0 .. 31
+            *reinterpret_cast<uint4 *>(rec + 32 + c * 16) = lo;     // lo: bytes 32 .. 63
         }
-        uint4 *rec = reinterpret_cast<uint4 *>(P + ring::rec_byte(j, s, S));
-        rec[0] = h[0];
-        rec[1] = h[1];
-        rec[2] = l[0];
-        rec[3] = l[1];
     }
     __syncthreads();                             // tile free for the next block
 }
