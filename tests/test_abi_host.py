@@ -115,6 +115,26 @@ def test_split_k_plan():
     assert call(_desc(8, 8, 8, flags=1 << 28)) == moa.MOA_ERR_INVALID
 
 
+def test_size_limits_at_the_boundary():
+    """The record offsets inside one 16-row tile are 32-bit: n may reach
+    16 * 131071 on split-BF16 (16 k per record) and 64 * 131071 on FP8 (64 k
+    per record); one more is refused with MOA_ERR_SHAPE, before any launch."""
+    cases = [(moa.MOA_PATH_SPLIT_BF16, 0, 16), (moa.MOA_PATH_FP8_SCALED, 0, 64),
+             (moa.MOA_PATH_FP8_SCALED, moa.MOA_FLAG_FP8_TWO_TERM, 64)]
+    for path, flags, k in cases:
+        q = moa.moa_plan_query(_desc(3, k * 131071, 5, path=path, flags=flags))
+        assert q["tile_k"] == k and q["workspace_bytes"] > 0
+        with pytest.raises(moa.MoaError) as ei:
+            moa.moa_plan_query(_desc(3, k * 131071 + 1, 5, path=path, flags=flags))
+        assert ei.value.status == moa.MOA_ERR_SHAPE
+        assert call(_desc(3, k * 131071 + 1, 5, path=path, flags=flags)) == moa.MOA_ERR_SHAPE
+    # ONF: at most 65535 row blocks
+    tm = moa.moa_plan_query(_desc(8, 1, 1, moa.MOA_F32, moa.MOA_PATH_ONF, flags=moa.MOA_FLAG_VARIANT(0)))["tile_m"]
+    moa.moa_plan_query(_desc(65535 * tm, 1, 1, moa.MOA_F32, moa.MOA_PATH_ONF, flags=moa.MOA_FLAG_VARIANT(0)))
+    assert call(_desc(65535 * tm + 1, 1, 1, moa.MOA_F32, moa.MOA_PATH_ONF,
+                      flags=moa.MOA_FLAG_VARIANT(0))) == moa.MOA_ERR_SHAPE
+
+
 def test_layout_flags():
     """gamma_col operands: any combination on the ring paths, all-or-nothing on
     ONF / FP32 matrix cores; make_desc reads the layout from the strides."""
