@@ -77,16 +77,37 @@ def test_onf_f32_bitwise_fma_order(shape):
     assert O.rel_err(C, O.gemm_f64(A.astype(np.float64), B.astype(np.float64))) <= 1e-5
 
 
-@pytest.mark.parametrize("variant", range(4))
+def onf_variants(dt):
+    """Number of ONF block variants the planner offers for a dtype."""
+    d = moa.moa_gemm_desc(m=300, n=300, p=300, dtype=moa.MOA_F64 if dt == np.float64 else moa.MOA_F32,
+                          path=moa.PATHS["onf"], A=16, B=16, C=1 << 20, accumulate=0, flags=0)
+    v = 0
+    while True:
+        d.flags = moa.MOA_FLAG_VARIANT(v)
+        try:
+            moa.moa_plan_query(d)
+        except moa.MoaError:
+            return v
+        v += 1
+
+
+@pytest.mark.parametrize("shape", [(200, 77, 333), (1, 16, 5), (70, 1000, 600)])
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
-def test_onf_every_block_size_is_bitwise_the_same(variant, dt):
-    """Changing the dimension lift (block sizes) never changes a result."""
-    m, n, p = 200, 77, 333
+def test_onf_every_block_size_is_bitwise_the_same(dt, shape):
+    """Changing the dimension lift (block sizes) never changes a result:
+    every variant, overwrite and accumulate, bitwise the fma-ordered oracle."""
+    m, n, p = shape
     A, B = inputs.uniform_f64(m, n, p, seed=5)
     A, B = A.astype(dt), B.astype(dt)
-    C = run(A, B, "onf", flags=moa.MOA_FLAG_VARIANT(variant))
+    C0 = (np.arange(m * p).reshape(m, p) % 13 - 6).astype(dt)
     ref = O.gemm_f64_fma(A, B) if dt == np.float64 else O.gemm_f32_fma(A, B)
-    assert np.array_equal(C, ref)
+    ref_acc = O.gemm_f64_fma(A, B, C0, True) if dt == np.float64 else O.gemm_f32_fma(A, B, C0, True)
+    count = onf_variants(dt)
+    assert count == 4
+    for v in range(count):
+        fl = moa.MOA_FLAG_VARIANT(v)
+        assert np.array_equal(run(A, B, "onf", flags=fl), ref), f"variant {v}"
+        assert np.array_equal(run(A, B, "onf", accumulate=True, C0=C0, flags=fl), ref_acc), f"variant {v}"
 
 
 @pytest.mark.parametrize("path", ["onf", "mfma_f32", "split_bf16", "fp8"])
