@@ -26,8 +26,10 @@
  *    A failed launch returns MOA_ERR_DEVICE. No C++ exception crosses the
  *    ABI. moa_last_error() gives a thread-local message for the last error.
  *  - Calls on different streams may run concurrently; each call uses only
- *    its own arguments and, where it needs scratch space, memory taken from
- *    the stream-ordered allocator on the same stream.
+ *    its own arguments and, where it needs scratch space, a device buffer
+ *    of the library's cache that no unfinished work on another stream still
+ *    uses (the stream-ordered allocator while the stream is being captured).
+ *    The cache keeps buffers between calls (at most 64 GiB per device).
  */
 #ifndef MOA_H
 #define MOA_H

@@ -93,8 +93,8 @@ moa_status check_group_overlap(const moa_gemm_desc *descs, int64_t count) {
 
 namespace {
 
-// One persistent launch sequence over `list`: workspace from the stream-ordered
-// pool, member table through pinned staging.
+// One persistent launch sequence over `list`: workspace from the scratch
+// cache, member table through pinned staging.
 template <class Bytes, class Launch>
 moa_status run_list(const std::vector<const moa_gemm_desc *> &list, int64_t desc_bytes, Bytes ws_bytes,
                     Launch launch, hipStream_t stream) {

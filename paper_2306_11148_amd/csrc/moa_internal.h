@@ -189,12 +189,14 @@ hipError_t launch_error_norm(int64_t count, moa_dtype xt, const void *X, const d
 moa_status run_gemm(const moa_gemm_desc &d, hipStream_t stream);
 
 // Grouped products (validated by the caller): split-BF16 members in one
-// persistent launch, the others one after another.
+// persistent launch sequence, scaled-FP8 members in one per term count, the
+// others (and split-k or column-major members) one after another.
 moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t stream);
 moa_status check_group_overlap(const moa_gemm_desc *descs, int64_t count);
 
-// Stream-ordered scratch (hipMallocAsync on the default pool of the current
-// device, pool kept warm).
+// Scratch of one call on `stream` (scratch.cpp): cached device buffers,
+// reused on the same stream at once and across streams once their last use
+// has completed; the stream-ordered allocator during graph capture.
 moa_status scratch_alloc(void **ptr, int64_t bytes, hipStream_t stream);
 void scratch_free(void *ptr, hipStream_t stream);
 
