@@ -356,9 +356,17 @@ moa_status moa_serve_submit(moa_server *srv, const moa_gemm_desc *desc,
 
 /* MOA_OK and the timestamps once the request is done (its C is final),
  * MOA_NOT_READY before, MOA_ERR_INVALID for an unknown ticket. A completed
- * ticket may be polled any number of times. Thread-safe. */
+ * ticket may be polled any number of times until it is released.
+ * Thread-safe. */
 moa_status moa_serve_poll(moa_server *srv, uint64_t ticket,
                           moa_req_info *out);
+
+/* Frees the record of a completed ticket; later polls of it return
+ * MOA_ERR_INVALID. MOA_NOT_READY (nothing changes) while the request runs,
+ * MOA_ERR_INVALID for an unknown or already released ticket. Records of
+ * tickets never released are kept until moa_serve_destroy, so a long-running
+ * server should release each ticket once it has read it. Thread-safe. */
+moa_status moa_serve_release(moa_server *srv, uint64_t ticket);
 
 /* Waits until every submitted request is done. */
 moa_status moa_serve_drain(moa_server *srv);

@@ -238,6 +238,18 @@ moa_status moa_serve_poll(moa_server *srv, uint64_t ticket, moa_req_info *out) {
     return MOA_OK;
 }
 
+moa_status moa_serve_release(moa_server *srv, uint64_t ticket) {
+    if (!srv) return fail(MOA_ERR_INVALID, "null server");
+    std::lock_guard<std::mutex> lk(srv->mu);
+    auto it = srv->all.find(ticket);
+    if (it == srv->all.end()) return fail(MOA_ERR_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
+    if (!it->second->done) return MOA_NOT_READY;
+    // a done request is referenced by no queue or slot any more
+    delete it->second;
+    srv->all.erase(it);
+    return MOA_OK;
+}
+
 moa_status moa_serve_drain(moa_server *srv) {
     if (!srv) return fail(MOA_ERR_INVALID, "null server");
     std::unique_lock<std::mutex> lk(srv->mu);

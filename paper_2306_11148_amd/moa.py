@@ -75,7 +75,7 @@ class moa_req_info(ctypes.Structure):
 EXPORTS = [
     "moa_gemm", "moa_gemm_grouped", "moa_plan_query", "moa_static_block_components",
     "moa_split_bf16", "moa_quantise_fp8", "moa_error_norm", "moa_serve_create",
-    "moa_serve_submit", "moa_serve_poll", "moa_serve_drain", "moa_serve_destroy",
+    "moa_serve_submit", "moa_serve_poll", "moa_serve_release", "moa_serve_drain", "moa_serve_destroy",
     "moa_status_string", "moa_last_error", "moa_trace_enable", "moa_trace_read",
     "moa_group_create", "moa_group_launch", "moa_group_destroy",
     "moa_autotune", "moa_autotune_save", "moa_autotune_load", "moa_autotune_clear",
@@ -116,6 +116,7 @@ def lib():
         "moa_serve_create": ([P(moa_serve_cfg), P(vp)], i32),
         "moa_serve_submit": ([vp, P(moa_gemm_desc), P(ctypes.c_uint64)], i32),
         "moa_serve_poll": ([vp, ctypes.c_uint64, P(moa_req_info)], i32),
+        "moa_serve_release": ([vp, ctypes.c_uint64], i32),
         "moa_serve_drain": ([vp], i32),
         "moa_serve_destroy": ([vp], i32),
         "moa_status_string": ([i32], ctypes.c_char_p),
@@ -276,6 +277,16 @@ def moa_serve_poll(srv, ticket: int):
         return None
     _check(s, "moa_serve_poll")
     return {f: getattr(info, f) for f, _ in moa_req_info._fields_}
+
+
+def moa_serve_release(srv, ticket: int) -> bool:
+    """Frees a completed ticket's record: True once released, False while the
+    request still runs."""
+    s = lib().moa_serve_release(srv, ticket)
+    if s == MOA_NOT_READY:
+        return False
+    _check(s, "moa_serve_release")
+    return True
 
 
 def moa_serve_drain(srv):

@@ -242,6 +242,7 @@ def test_serve_argument_errors_before_device():
     t = ctypes.c_uint64()
     assert L.moa_serve_submit(None, None, ctypes.byref(t)) == moa.MOA_ERR_INVALID
     assert L.moa_serve_poll(None, 1, None) == moa.MOA_ERR_INVALID
+    assert L.moa_serve_release(None, 1) == moa.MOA_ERR_INVALID
     assert L.moa_serve_drain(None) == moa.MOA_ERR_INVALID
     assert L.moa_serve_destroy(None) == moa.MOA_OK
 

@@ -92,6 +92,28 @@ def test_serve_budget_bounds_inflight_bytes():
     assert admits == sorted(admits)
 
 
+def test_serve_release_frees_completed_tickets_only():
+    reqs = build_requests(6, seed=8)
+    srv = moa.moa_serve_create(200 << 30, slots=2, max_group=4)
+    try:
+        tickets = [moa.moa_serve_submit(srv, r["desc"]) for r in reqs]
+        moa.moa_serve_drain(srv)
+        for t in tickets:
+            info = moa.moa_serve_poll(srv, t)
+            assert info is not None and info["status"] == 0
+            assert moa.moa_serve_poll(srv, t) == info          # polled again until released
+            assert moa.moa_serve_release(srv, t) is True
+            for call in (lambda: moa.moa_serve_poll(srv, t), lambda: moa.moa_serve_release(srv, t)):
+                with pytest.raises(moa.MoaError) as ei:
+                    call()
+                assert ei.value.status == moa.MOA_ERR_INVALID
+        # tickets are never reused after a release
+        assert moa.moa_serve_submit(srv, reqs[0]["desc"]) > max(tickets)
+        moa.moa_serve_drain(srv)
+    finally:
+        moa.moa_serve_destroy(srv)
+
+
 def test_serve_refuses_request_beyond_budget_and_unknown_ticket():
     A = torch.zeros((256, 256), device=DEV)
     B = torch.zeros((256, 256), device=DEV)
