@@ -15,6 +15,7 @@ struct moa_group {
     void *ws8[2] = {nullptr, nullptr};  // FP8 members, one and two terms
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    hipEvent_t done = nullptr;          // recorded behind every replay
 };
 
 using namespace moa;
@@ -23,6 +24,11 @@ namespace {
 
 void release(moa_group *g) {
     if (!g) return;
+    // replays of one group never overlap, so the last one recorded covers all
+    if (g->done) {
+        (void)hipEventSynchronize(g->done);
+        (void)hipEventDestroy(g->done);
+    }
     if (g->exec) (void)hipGraphExecDestroy(g->exec);
     if (g->graph) (void)hipGraphDestroy(g->graph);
     if (g->ws) (void)hipFree(g->ws);   // hipFree waits for work using it
@@ -60,7 +66,12 @@ moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group
         moa_status s = check_group_overlap(descs, count);
         if (s != MOA_OK) return s;
         auto *g = new moa_group();
-        hipError_t e = hipSuccess;
+        hipError_t e = hipEventCreateWithFlags(&g->done, hipEventDisableTiming);
+        if (e != hipSuccess) {
+            g->done = nullptr;
+            release(g);
+            return hip_fail(e, "hipEventCreateWithFlags");
+        }
         GroupedWork work{0, 0};
         const int cnt = (int)split.size();
         if (cnt > 0) {
@@ -131,7 +142,8 @@ moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group
 
 moa_status moa_group_launch(moa_group *g, void *stream) {
     if (!g) return fail(MOA_ERR_INVALID, "null group");
-    const hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
+    hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
+    if (e == hipSuccess) e = hipEventRecord(g->done, static_cast<hipStream_t>(stream));
     if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
     return MOA_OK;
 }
