@@ -253,7 +253,7 @@ struct GroupMember {
 
 
 template <int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void split_grouped_kernel(
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, 3) void split_grouped_kernel(
     const GroupMember *__restrict__ g, const int32_t *__restrict__ tile_owner, int64_t total_tiles,
     unsigned long long *__restrict__ counter) {
     __shared__ __attribute__((aligned(1024))) uint8_t lds[ring::Cfg<BM, BN, WM, WN, 1>::LDS];
@@ -511,7 +511,7 @@ hipError_t split_grouped_enqueue(void *ws, int count, const GroupedWork &work, h
         hipLaunchKernelGGL(grouped_pack_kernel, dim3((unsigned)g), dim3(256), 0, st, dev_members, item_owner,
                            work.pack_items);
     }
-    const int64_t grid = std::min<int64_t>(tiles, 2 * kNumCUs);   // two 64 KiB-LDS blocks per CU
+    const int64_t grid = std::min<int64_t>(tiles, 3 * kNumCUs);   // three 48 KiB-LDS blocks per CU
     TraceScope ts(MOA_K_SPLIT_GROUPED, st);
     if (grid > 0)
         hipLaunchKernelGGL((split_grouped_kernel<GB_M, GB_N, GW_M, GW_N>), dim3((unsigned)grid),
