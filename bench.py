@@ -61,6 +61,9 @@ def parse():
                          "one JSON line per rate")
     ap.add_argument("--no-grouped", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
+    ap.add_argument("--split-variants", type=str, default=None,
+                    help="comma-separated N list: split-BF16 contraction and conditioning time per block "
+                         "variant (square FP32 operands, seed N), two rounds, one JSON line per point")
     ap.add_argument("--block-sweep", type=str, default=None,
                     help="comma-separated N list: ONF FP64 time/energy per block size only")
     ap.add_argument("--sweep", type=str, default=None,
@@ -576,6 +579,50 @@ def block_sweep(args, torch, moa):
         del A, B, C
 
 
+def split_variants(args, torch, moa):
+    """Kernel times of every split-BF16 block variant against N (library trace:
+    HIP events on the launch stream), two rounds over the list, so that the
+    spread between rounds shows alongside the differences between variants."""
+    d0 = moa.moa_gemm_desc(m=1024, n=1024, p=1024, dtype=moa.MOA_F32, path=moa.MOA_PATH_SPLIT_BF16,
+                           A=16, B=16, C=1 << 24, accumulate=0, flags=0)
+    count = 0
+    while True:
+        d0.flags = moa.MOA_FLAG_VARIANT(count)
+        try:
+            moa.moa_plan_query(d0)
+        except moa.MoaError:
+            break
+        count += 1
+    for rnd in range(2):
+        for N in [int(x) for x in args.split_variants.split(",")]:
+            gen = torch.Generator(device="cuda").manual_seed(N)
+            A = torch.randn((N, N), generator=gen, device="cuda")
+            B = torch.randn((N, N), generator=gen, device="cuda")
+            C = torch.empty((N, N), device="cuda")
+            default = moa.moa_plan_query(moa.make_desc(A, B, C, path=moa.MOA_PATH_SPLIT_BF16))["variant"]
+            for v in range(count):
+                fl = moa.MOA_FLAG_VARIANT(v)
+                plan = moa.moa_plan_query(moa.make_desc(A, B, C, path=moa.MOA_PATH_SPLIT_BF16, flags=fl))
+                for _ in range(3):
+                    moa.moa_gemm(A, B, C, path="split_bf16", flags=fl)
+                torch.cuda.synchronize()
+                moa.moa_trace_enable(True)
+                moa.moa_trace_read(reset=True)
+                reps = max(5, min(50, int(2e12 / N ** 3)))
+                for _ in range(reps):
+                    moa.moa_gemm(A, B, C, path="split_bf16", flags=fl)
+                torch.cuda.synchronize()
+                st = moa.moa_trace_read(reset=True)
+                moa.moa_trace_enable(False)
+                k_ms = st["split_bf16"][1] / st["split_bf16"][0]
+                p_ms = st["split_pack"][1] / st["split_pack"][0]
+                print(json.dumps({"split_variants": rnd, "N": N, "variant": v, "default": v == default,
+                                  "block": [plan["tile_m"], plan["tile_n"]], "wave": [plan["wave_m"], plan["wave_n"]],
+                                  "kernel_ms": round(k_ms, 4), "pack_ms": round(p_ms, 4),
+                                  "kernel_tflops_issued": round(3 * 2.0 * N ** 3 / k_ms / 1e9, 1)}), flush=True)
+            del A, B, C
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -594,6 +641,9 @@ def main():
         return
     if args.block_sweep:
         block_sweep(args, torch, moa)
+        return
+    if args.split_variants:
+        split_variants(args, torch, moa)
         return
     if args.split_k:
         split_k_sweep(args, torch, moa, inputs)

@@ -129,6 +129,7 @@ hipError_t launch_split_bf16(const moa_gemm_desc &d, const Plan &plan, void *wor
 hipError_t launch_split_pack(const moa_gemm_desc &d, void *workspace, hipStream_t stream);
 void split_bf16_shape(int variant, Plan *p);
 int split_bf16_variant_count();
+int split_bf16_default_variant(int64_t m, int64_t p);   // the planner's default block
 int64_t split_bf16_workspace_bytes(int64_t m, int64_t n, int64_t p);
 // Grouped split-BF16: all `members` in one conditioning pass and one
 // persistent launch. `host_staging` is pinned memory of at least

@@ -171,12 +171,7 @@ moa_status make_plan(const moa_gemm_desc &d_in, Plan *out) {
         } else if ((v = tuned_variant(d, pl.path)) >= 0) {
             pl.tuned = true;
         } else {
-            v = 0;
-            for (int c = nv - 1; c >= 0; --c) {
-                Plan t;
-                split_bf16_shape(c, &t);
-                if (tiles_for(d.m, d.p, t.tile_m, t.tile_n) >= kNumCUs) { v = c; break; }
-            }
+            v = split_bf16_default_variant(d.m, d.p);
         }
         split_bf16_shape(v, &pl);
         pl.workspace_bytes = split_bf16_workspace_bytes(d.m, d.n, d.p);

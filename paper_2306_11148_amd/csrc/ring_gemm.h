@@ -72,7 +72,9 @@ template <int BM, int BN, int WM, int WN, int NREC, int NST = NSTAGE> struct Cfg
     static constexpr int LDS = NST * STAGE;
     static constexpr int LPW = ROWS / 16 / NW;            // KiB direct loads per wave per slab
     static_assert(ROWS % (16 * NW) == 0, "whole loads per wave");
-    static_assert(BM % (16 * LPW) == 0 && BN % (16 * LPW) == 0, "a wave loads rows of one array");
+    // a wave's rows lie in one array, or span two (then fewer rows than either array)
+    static constexpr bool ONE_ARRAY = BM % (16 * LPW) == 0 && BN % (16 * LPW) == 0;
+    static_assert(ONE_ARRAY || (16 * LPW <= BM && 16 * LPW <= BN), "a wave's rows span at most two arrays");
 };
 
 // The conditioned operands of one product.
@@ -120,23 +122,38 @@ __device__ __forceinline__ void tile(const Operands &op, int64_t i0, int64_t j0,
     const int L = (s_end < 0 ? S : s_end) - s_begin;   // slabs this block walks
 
     // LDS rows of a slab: [A array 0 (BM)] .. [A array NREC-1] [B array 0 (BN)] ..
-    // Wave w loads rows 16*LPW*w .. +16*LPW-1, all inside one array.
+    // Wave w loads rows 16*LPW*w .. +16*LPW-1: inside one array, or (when the
+    // block's arrays are not multiples of a wave's share) across the end of
+    // one array into the next, from loads q_split onwards.
     static_assert(NREC == 1 || NREC == 2, "one or two record arrays per operand");
     const int64_t tile_row = S * GROUP * REC_BYTES;       // bytes per row tile (16 rows, all slabs)
     const int row_first = wave * LPW * 16;
-    const bool loads_a = row_first < NREC * BM;
-    const int arr = NREC == 1 ? 0 : loads_a ? row_first / BM : (row_first - NREC * BM) / BN;
-    const int row_in = loads_a ? row_first - arr * BM : row_first - NREC * BM - arr * BN;
-    const int64_t org = loads_a ? i0 : j0;
-    const int64_t lim = loads_a ? op.m : op.p;
-    const int64_t tiles = min((int64_t)(loads_a ? BM : BN), padded_rows(lim) - org) / GROUP;
-    // (with two arrays this select becomes a variable index into `op`: keep
-    // `op` in kernel-argument or global memory, never in a local variable,
-    // or it is placed in scratch memory)
-    const uint8_t *base = loads_a ? (NREC == 1 || arr == 0 ? op.a0 : op.a1)
-                                  : (NREC == 1 || arr == 0 ? op.b0 : op.b1);
-    const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(base + (org / GROUP) * tile_row), (short)0, (int)(tiles * tile_row), 0x00020000);
+    // The array holding LDS row `row`: a buffer resource over this block's row
+    // tiles of it, and the row's index inside the block's part of the array.
+    // (with two arrays the select of the base becomes a variable index into
+    // `op`: keep `op` in kernel-argument or global memory, never in a local
+    // variable, or it is placed in scratch memory)
+    auto source = [&](int row, int *row_in) {
+        const bool a = row < NREC * BM;
+        const int arr = NREC == 1 ? 0 : a ? row / BM : (row - NREC * BM) / BN;
+        *row_in = a ? row - arr * BM : row - NREC * BM - arr * BN;
+        const int64_t org = a ? i0 : j0;
+        const int64_t lim = a ? op.m : op.p;
+        const int64_t tiles = min((int64_t)(a ? BM : BN), padded_rows(lim) - org) / GROUP;
+        const uint8_t *base = a ? (NREC == 1 || arr == 0 ? op.a0 : op.a1) : (NREC == 1 || arr == 0 ? op.b0 : op.b1);
+        return __builtin_amdgcn_make_buffer_rsrc((void *)(base + (org / GROUP) * tile_row), (short)0,
+                                                 (int)(tiles * tile_row), 0x00020000);
+    };
+    int row_in0 = 0, row_in1 = 0;
+    const __amdgpu_buffer_rsrc_t rsrc0 = source(row_first, &row_in0);
+    int q_split = LPW;
+    __amdgpu_buffer_rsrc_t rsrc1 = rsrc0;
+    if constexpr (!G::ONE_ARRAY) {
+        const int end0 = row_first < NREC * BM ? (row_first / BM + 1) * BM
+                                               : NREC * BM + ((row_first - NREC * BM) / BN + 1) * BN;
+        q_split = min(LPW, (end0 - row_first) / 16);
+        if (q_split < LPW) rsrc1 = source(row_first + 16 * q_split, &row_in1);
+    }
     // lane L lands at row 16Q + L/4, physical chunk L%4, and fetches logical
     // chunk (L%4) ^ ((row/4) mod 4) = (L%4) ^ (L/16). Records past m (or p)
     // lie beyond the resource's range and load as zeros (their outputs are
@@ -145,10 +162,13 @@ __device__ __forceinline__ void tile(const Operands &op, int64_t i0, int64_t j0,
     auto issue = [&](int s) {            // s counts from s_begin
         uint8_t *buf = lds + (s % NSTAGE) * STAGE + row_first * REC_BYTES;
 #pragma unroll
-        for (int q = 0; q < LPW; ++q)
+        for (int q = 0; q < LPW; ++q) {
+            const bool first = G::ONE_ARRAY || q < q_split;
+            const int tile_in = first ? row_in0 / GROUP + q : row_in1 / GROUP + (q - q_split);
             __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                rsrc, (lds_void_t *)(buf + q * 16 * REC_BYTES), 16, voff,
-                (int)((row_in / GROUP + q) * tile_row) + (s0 + s) * GROUP * REC_BYTES, 0, 0);
+                first ? rsrc0 : rsrc1, (lds_void_t *)(buf + q * 16 * REC_BYTES), 16, voff,
+                (int)(tile_in * tile_row) + (s0 + s) * GROUP * REC_BYTES, 0, 0);
+        }
     };
 
     const int frow = lane & 31, fhalf = lane >> 5;
@@ -248,8 +268,18 @@ __device__ __forceinline__ void block_of(int tiles_m, int tiles_n, int *tm, int 
     *tn = __builtin_amdgcn_readfirstlane(*tn);
 }
 
+// Workgroups per CU the register allocation must allow: two for four-wave
+// blocks with a ring of more than 64 KiB that still leaves room for a second
+// one in LDS (left to the compiler otherwise, which reaches three for the
+// 48 KiB rings by itself).
+template <int BM, int BN, int WM, int WN, int NREC, int NST>
+constexpr int min_blocks() {
+    using G = Cfg<BM, BN, WM, WN, NREC, NST>;
+    return G::NW == 4 && G::LDS > 64 * 1024 && 2 * G::LDS <= 160 * 1024 ? 2 : 1;
+}
+
 template <int BM, int BN, int WM, int WN, int NREC, class Mode, int NST = NSTAGE>
-__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64) void single_kernel(Operands op, int tiles_m,
+__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, (min_blocks<BM, BN, WM, WN, NREC, NST>())) void single_kernel(Operands op, int tiles_m,
                                                                             int tiles_n) {
     __shared__ __attribute__((aligned(1024))) uint8_t lds[Cfg<BM, BN, WM, WN, NREC, NST>::LDS];
     int tm, tn;

@@ -319,8 +319,11 @@ __global__ __launch_bounds__(256) void split_only_kernel(const float *__restrict
 }
 
 struct SplitShape { int bm, bn, wm, wn, stages; };
-// (deeper rings were measured no faster for this path at N = 8192)
-constexpr SplitShape kSplit[] = {{128, 128, 64, 64, 3}, {256, 256, 128, 64, 3}};
+// (deeper rings were measured no faster for this path at N = 8192). The
+// rectangular blocks run four waves of 128 x 64 or 64 x 128, two workgroups
+// per CU.
+constexpr SplitShape kSplit[] = {{128, 128, 64, 64, 3}, {256, 256, 128, 64, 3}, {256, 128, 128, 64, 3},
+                                 {128, 256, 64, 128, 3}};
 
 template <int BM, int BN, int WM, int WN, int NST>
 hipError_t launch_shape(const moa_gemm_desc &d, const uint8_t *Ap, const uint8_t *Bp, int64_t S,
@@ -336,6 +339,20 @@ hipError_t launch_shape(const moa_gemm_desc &d, const uint8_t *Ap, const uint8_t
 }  // namespace
 
 int split_bf16_variant_count() { return (int)(sizeof(kSplit) / sizeof(kSplit[0])); }
+
+// Default block: 256 x 256 (one workgroup per CU) once it gives every CU a
+// block, else 128 x 128. When its blocks fill more than one round of the CUs
+// but leave the last round less than 40% full, the rectangular blocks (two
+// per CU, half the area) shorten that tail: measured N = 6144 and 7168
+// (2.25 and 3.06 rounds) 7-9% faster, while 256 x 256 stays ahead at whole
+// or well-filled rounds (N = 4096, 5120, 8192, 12288).
+int split_bf16_default_variant(int64_t m, int64_t p) {
+    const int64_t big = ((m + 255) / 256) * ((p + 255) / 256);
+    if (big < kNumCUs) return 0;
+    const int64_t tail = big % kNumCUs;
+    if (big > kNumCUs && tail != 0 && 10 * tail < 4 * kNumCUs) return p >= m ? 3 : 2;
+    return 1;
+}
 
 int64_t split_bf16_workspace_bytes(int64_t m, int64_t n, int64_t p) {
     const int64_t S = (n + SLAB - 1) / SLAB;
@@ -407,6 +424,8 @@ hipError_t launch_split_bf16(const moa_gemm_desc &d, const Plan &plan, void *ws,
     }
     switch (plan.variant) {
     case 0: return launch_shape<128, 128, 64, 64, 3>(d, Ap, Bp, S, st);
+    case 2: return launch_shape<256, 128, 128, 64, 3>(d, Ap, Bp, S, st);
+    case 3: return launch_shape<128, 256, 64, 128, 3>(d, Ap, Bp, S, st);
     default: return launch_shape<256, 256, 128, 64, 3>(d, Ap, Bp, S, st);
     }
 }
