@@ -39,7 +39,30 @@ __global__ __launch_bounds__(256) void mfma_f32_kernel(const float *__restrict__
     const int64_t j0 = (int64_t)tn * BN;
 
     float ra[CA][8], rb[CB][8];
+    // whole blocks (the slab inside n, the block inside m and p, A vector-aligned)
+    // load without per-element checks
+    const bool inner = i0 + BM <= m && j0 + BN <= p && vec_a;
     auto load = [&](int64_t k0) {
+        if (inner && k0 + BK <= n) {
+#pragma unroll
+            for (int s = 0; s < CA; ++s) {
+                const int cid = t + 256 * s;
+                const int row = cid % BM, kc = cid / BM;
+                const float4 *src = reinterpret_cast<const float4 *>(A + (i0 + row) * n + k0 + kc * 8);
+                const float4 x0 = src[0], x1 = src[1];
+                ra[s][0] = x0.x; ra[s][1] = x0.y; ra[s][2] = x0.z; ra[s][3] = x0.w;
+                ra[s][4] = x1.x; ra[s][5] = x1.y; ra[s][6] = x1.z; ra[s][7] = x1.w;
+            }
+#pragma unroll
+            for (int s = 0; s < CB; ++s) {
+                const int cid = t + 256 * s;
+                const int col = cid % BN, kc = cid / BN;
+                const float *src = B + (k0 + kc * 8) * p + j0 + col;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) rb[s][e] = src[e * p];
+            }
+            return;
+        }
 #pragma unroll
         for (int s = 0; s < CA; ++s) {
             const int cid = t + 256 * s;

@@ -82,7 +82,25 @@ __global__ __launch_bounds__(256) void onf_kernel(const T *__restrict__ A,
 
     // ---- global -> registers for one k slab ------------------------------
     V ra[A_PER], rb[B_PER];
+    // whole blocks (inside m and p, the slab inside n, vector-aligned rows)
+    // load without per-vector checks
+    const bool inner = i0 + TM <= m && j0 + TN <= p && vec_a && vec_b;
     auto load_slab = [&](int64_t k0) {
+        if (inner && k0 + BK <= n) {
+#pragma unroll
+            for (int s = 0; s < A_PER; ++s) {
+                const int v = t + 256 * s;
+                if (A_VECS % 256 == 0 || v < A_VECS)
+                    ra[s] = *reinterpret_cast<const V *>(A + (i0 + v / (BK / VW)) * n + k0 + (v % (BK / VW)) * VW);
+            }
+#pragma unroll
+            for (int s = 0; s < B_PER; ++s) {
+                const int v = t + 256 * s;
+                if (B_VECS % 256 == 0 || v < B_VECS)
+                    rb[s] = *reinterpret_cast<const V *>(B + (k0 + v / (TN / VW)) * p + j0 + (v % (TN / VW)) * VW);
+            }
+            return;
+        }
 #pragma unroll
         for (int s = 0; s < A_PER; ++s) {
             const int v = t + 256 * s;
