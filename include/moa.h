@@ -62,7 +62,10 @@ typedef enum moa_dtype {
  *                  (the paper's loop order); FP64 or FP32. Bitwise equal to
  *                  the same loop with one fma per step.
  *  MFMA_F32     -- FP32 matrix-core tiles (v_mfma_f32_32x32x2_f32), FP32
- *                  accumulation. F32 only.
+ *                  accumulation. F32 only. Variants 0, 1 copy A's rows and
+ *                  B's columns into 64-byte records (scratch of 4 (m + p) n
+ *                  bytes, n <= 16 * 131071) and run the record ring;
+ *                  variant 2 stages through registers and takes no scratch.
  *  SPLIT_BF16   -- each FP32 input x is split into hi = RNE_bf16(x) and
  *                  lo = RNE_bf16(x - hi); C = hi.hi + hi.lo + lo.hi on BF16
  *                  matrix cores with FP32 accumulation. F32 only.
@@ -207,8 +210,9 @@ moa_status moa_gemm_batched(const moa_gemm_desc *first, int64_t batch, int64_t s
                             int64_t stride_c, void *stream);
 
 /* Prepared groups: a fixed set of products launched many times. Creation
- * validates the members as moa_gemm_grouped does, allocates a workspace owned
- * by the group, uploads the member list once and captures the whole grouped
+ * validates the members as moa_gemm_grouped does, allocates the workspaces
+ * (member tables, conditioned records) owned by the group, uploads the member
+ * list once and captures the whole grouped
  * launch sequence (conditioning + one persistent contraction for split-BF16
  * members and one per FP8 term count, single launches for ONF and FP32
  * matrix-core members) in a HIP graph. Each moa_group_launch replays it on

@@ -92,8 +92,14 @@ moa_status run_gemm(const moa_gemm_desc &d_in, hipStream_t stream) {
         break;
     }
     case MOA_PATH_MFMA_F32: {
-        TraceScope ts(pl.kernel, stream);
-        e = launch_mfma_f32(d, pl, stream);
+        void *ws = nullptr;
+        s = scratch_alloc(&ws, pl.workspace_bytes, stream);
+        if (s != MOA_OK) return s;
+        {
+            TraceScope ts(pl.kernel, stream);      // record copies and contraction
+            e = launch_mfma_f32(d, pl, ws, stream);
+        }
+        scratch_free(ws, stream);
         break;
     }
     case MOA_PATH_SPLIT_BF16:

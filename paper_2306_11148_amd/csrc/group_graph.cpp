@@ -3,9 +3,9 @@
 // tables are owned by the group; the captured sequence (per persistent
 // launch: counter reset, grouped conditioning, persistent contraction -- one
 // for split-BF16 members and one per FP8 term count -- then single launches
-// of ONF / FP32 matrix-core members) allocates, copies and clears nothing
-// outside kernels, so every replay repeats exactly the same work on the same
-// buffers.
+// of ONF / FP32 matrix-core members, the latter with record workspaces of the
+// group) allocates, copies and clears nothing outside kernels, so every
+// replay repeats exactly the same work on the same buffers.
 #include <vector>
 
 #include "moa_internal.h"
@@ -13,6 +13,7 @@
 struct moa_group {
     void *ws = nullptr;                 // split-BF16 members
     void *ws8[2] = {nullptr, nullptr};  // FP8 members, one and two terms
+    void *wsf = nullptr;                // FP32 matrix-core members' records
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     hipEvent_t done = nullptr;          // recorded behind every replay
@@ -34,6 +35,7 @@ void release(moa_group *g) {
     if (g->ws) (void)hipFree(g->ws);   // hipFree waits for work using it
     for (void *w : g->ws8)
         if (w) (void)hipFree(w);
+    if (g->wsf) (void)hipFree(g->wsf);
     delete g;
 }
 
@@ -47,7 +49,9 @@ moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group
         *out = nullptr;
         if (count < 0 || (count > 0 && !descs)) return fail(MOA_ERR_INVALID, "bad descriptor array");
         std::vector<const moa_gemm_desc *> split, fp8[2];
-        std::vector<moa_gemm_desc> single;
+        std::vector<moa_gemm_desc> single, f32m;
+        std::vector<Plan> f32p;
+        int64_t f32_bytes = 0;
         for (int64_t k = 0; k < count; ++k) {
             const moa_gemm_desc &d = descs[k];
             moa_status s = validate(d, true);
@@ -61,7 +65,13 @@ moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group
             if (pl.path == MOA_PATH_SPLIT_BF16) split.push_back(&d);
             else if (pl.path == MOA_PATH_FP8_SCALED) fp8[(d.flags & MOA_FLAG_FP8_TWO_TERM) ? 1 : 0].push_back(&d);
             else if (pl.workspace_bytes == 0) single.push_back(d);
-            else return fail(MOA_ERR_UNSUPPORTED, "member %lld needs per-call scratch", (long long)k);
+            else if (pl.path == MOA_PATH_MFMA_F32) {
+                f32m.push_back(d);
+                f32p.push_back(pl);
+                f32_bytes += (pl.workspace_bytes + 255) & ~int64_t(255);
+            } else {
+                return fail(MOA_ERR_UNSUPPORTED, "member %lld needs per-call scratch", (long long)k);
+            }
         }
         moa_status s = check_group_overlap(descs, count);
         if (s != MOA_OK) return s;
@@ -87,6 +97,11 @@ moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group
                 release(g);
                 return hip_fail(e, "group member upload");
             }
+        }
+        if (f32_bytes > 0 && (e = hipMalloc(&g->wsf, (size_t)f32_bytes)) != hipSuccess) {
+            g->wsf = nullptr;
+            release(g);
+            return fail(MOA_ERR_NOMEM, "group workspace: %s", hipGetErrorString(e));
         }
         hipStream_t cs = nullptr;
         if ((e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking)) != hipSuccess) {
@@ -120,6 +135,10 @@ moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group
         moa_status rs = MOA_OK;
         for (size_t k = 0; e == hipSuccess && rs == MOA_OK && k < single.size(); ++k)
             rs = run_gemm(single[k], cs);
+        for (size_t k = 0, off = 0; e == hipSuccess && rs == MOA_OK && k < f32m.size(); ++k) {
+            e = launch_mfma_f32(f32m[k], f32p[k], static_cast<char *>(g->wsf) + off, cs);
+            off += (size_t)((f32p[k].workspace_bytes + 255) & ~int64_t(255));
+        }
         hipGraph_t graph = nullptr;
         const hipError_t ee = hipStreamEndCapture(cs, &graph);
         (void)hipStreamDestroy(cs);

@@ -121,8 +121,14 @@ hipError_t launch_onf(const moa_gemm_desc &d, const Plan &plan, hipStream_t stre
 int onf_variant_count(moa_dtype t);
 void onf_variant_shape(moa_dtype t, int v, Plan *p);
 
-hipError_t launch_mfma_f32(const moa_gemm_desc &d, const Plan &plan, hipStream_t stream);
-void mfma_f32_shape(Plan *p);
+// FP32 matrix cores: variants 0, 1 run the record ring (workspace for the
+// records), mfma_f32_staged_variant() the register-staged kernel (none).
+hipError_t launch_mfma_f32(const moa_gemm_desc &d, const Plan &plan, void *workspace, hipStream_t stream);
+void mfma_f32_shape(int variant, Plan *p);
+int mfma_f32_variant_count();
+int mfma_f32_staged_variant();
+int mfma_f32_default_variant(int64_t m, int64_t p);
+int64_t mfma_f32_workspace_bytes(int64_t m, int64_t n, int64_t p, int variant);
 
 hipError_t launch_split_bf16(const moa_gemm_desc &d, const Plan &plan, void *workspace,
                              hipStream_t stream);

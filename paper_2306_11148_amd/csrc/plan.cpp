@@ -56,6 +56,7 @@ int variant_count(const moa_gemm_desc &d, moa_path path) {
     switch (path) {
     case MOA_PATH_ONF: return onf_variant_count((moa_dtype)d.dtype);
     case MOA_PATH_SPLIT_BF16: return split_bf16_variant_count();
+    case MOA_PATH_MFMA_F32: return mfma_f32_variant_count();
     case MOA_PATH_FP8_SCALED: return fp8_variant_count((d.flags & MOA_FLAG_FP8_TWO_TERM) != 0);
     default: return 1;
     }
@@ -156,11 +157,25 @@ moa_status make_plan(const moa_gemm_desc &d_in, Plan *out) {
             return fail(MOA_ERR_SHAPE, "m = %lld exceeds the ONF grid limit", (long long)d.m);
         break;
     }
-    case MOA_PATH_MFMA_F32:
+    case MOA_PATH_MFMA_F32: {
         pl.kernel = K_MFMA_F32;
-        if (forced > 0) return fail(MOA_ERR_INVALID, "variant %d out of range (MFMA_F32 has 1)", forced);
-        mfma_f32_shape(&pl);
+        const int nv = mfma_f32_variant_count();
+        int v;
+        if (forced >= 0) {
+            if (forced >= nv) return fail(MOA_ERR_INVALID, "variant %d out of range (MFMA_F32 has %d)", forced, nv);
+            v = forced;
+        } else if ((v = tuned_variant(d, pl.path)) >= 0) {
+            pl.tuned = true;
+        } else {
+            v = mfma_f32_default_variant(d.m, d.p);
+        }
+        mfma_f32_shape(v, &pl);
+        pl.workspace_bytes = mfma_f32_workspace_bytes(d.m, d.n, d.p, v);
+        // the record ring's 32-bit offsets inside a row tile, as on split-BF16
+        if (pl.workspace_bytes > 0 && (d.n + 15) / 16 > 131071)
+            return fail(MOA_ERR_SHAPE, "n = %lld exceeds the FP32 record offset range", (long long)d.n);
         break;
+    }
     case MOA_PATH_SPLIT_BF16: {
         pl.kernel = K_SPLIT_BF16;
         const int nv = split_bf16_variant_count();
