@@ -135,6 +135,23 @@ def test_size_limits_at_the_boundary():
                       flags=moa.MOA_FLAG_VARIANT(0))) == moa.MOA_ERR_SHAPE
 
 
+def test_mfma_f32_plan_variants():
+    """FP32 matrix cores: record ring (128x128 / 256x256, scratch for the
+    records) by default, the register-staged kernel (no scratch) as variant 2."""
+    M = moa.MOA_PATH_MFMA_F32
+    big = moa.moa_plan_query(_desc(8192, 8192, 8192, path=M))
+    assert (big["variant"], big["tile_m"], big["tile_n"]) == (1, 256, 256)
+    assert big["workspace_bytes"] == 4 * (8192 + 8192) * 8192
+    small = moa.moa_plan_query(_desc(1000, 300, 1000, path=M))
+    assert (small["variant"], small["tile_m"]) == (0, 128)
+    staged = moa.moa_plan_query(_desc(8192, 8192, 8192, path=M, flags=moa.MOA_FLAG_VARIANT(2)))
+    assert staged["workspace_bytes"] == 0 and staged["tile_k"] == 32
+    assert call(_desc(8, 8, 8, path=M, flags=moa.MOA_FLAG_VARIANT(3))) == moa.MOA_ERR_INVALID
+    # the record ring's offsets bound n; the staged kernel has no such limit
+    assert call(_desc(3, 16 * 131071 + 1, 5, path=M)) == moa.MOA_ERR_SHAPE
+    moa.moa_plan_query(_desc(3, 16 * 131071 + 1, 5, path=M, flags=moa.MOA_FLAG_VARIANT(2)))
+
+
 def test_layout_flags():
     """gamma_col operands: any combination on the ring paths, all-or-nothing on
     ONF / FP32 matrix cores; make_desc reads the layout from the strides."""
