@@ -138,15 +138,6 @@ moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t st
             if (s != MOA_OK) return s;
         }
     }
-    // a list of one runs as a single launch sequence: bitwise the same result
-    // (the per-element operation sequence does not depend on the launch), and
-    // no member table has to be copied to the device first
-    for (auto *list : {&split, &fp8[0], &fp8[1]})
-        if (list->size() == 1) {
-            moa_status s1 = run_gemm(*list->front(), stream);
-            if (s1 != MOA_OK) return s1;
-            list->clear();
-        }
     moa_status s = run_list(
         split, split_grouped_desc_bytes(split.data(), (int)split.size()), split_grouped_workspace_bytes,
         [&](const moa_gemm_desc *const *m, int c, void *ws, void *host) {
