@@ -473,8 +473,12 @@ constexpr Fp8Shape kOne[] = {{128, 128, 64, 64, 3}, {256, 256, 128, 64, 3}, {256
                              {256, 256, 128, 64, 5}};
 // Deeper rings pay off here: a slab carries 64 k, so a step is short next
 // to the latency of its loads.
+// The rectangular two-term blocks (8 waves of 64 x 64, 144 KB ring) read a
+// third less LDS per matrix-core step than 128 x 128 with 64 x 32 waves; a
+// wave's 96 LDS rows may span two record arrays. 256 x 128 is the default
+// for large products (8192 x 4096 x 8192: 0.75 vs 0.83-0.89 ms).
 constexpr Fp8Shape kTwo[] = {{128, 128, 64, 64, 3}, {128, 128, 64, 32, 3}, {128, 128, 64, 32, 5},
-                             {128, 128, 64, 32, 4}};
+                             {128, 128, 64, 32, 4}, {128, 256, 64, 64, 3}, {256, 128, 64, 64, 3}};
 constexpr int kOneCount = sizeof(kOne) / sizeof(kOne[0]);
 constexpr int kTwoCount = sizeof(kTwo) / sizeof(kTwo[0]);
 
@@ -649,6 +653,8 @@ hipError_t launch_fp8(const moa_gemm_desc &d, const Plan &plan, void *ws, hipStr
         case 0: return launch_shape<128, 128, 64, 64, true>(op, st);
         case 1: return launch_shape<128, 128, 64, 32, true>(op, st);
         case 2: return launch_shape<128, 128, 64, 32, true, 5>(op, st);
+        case 4: return launch_shape<128, 256, 64, 64, true, 3>(op, st);
+        case 5: return launch_shape<256, 128, 64, 64, true, 3>(op, st);
         default: return launch_shape<128, 128, 64, 32, true, 4>(op, st);
         }
     }
