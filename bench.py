@@ -199,10 +199,19 @@ def energy_per_call(fn, seconds, ms_each, energy, torch):
     def med(key):
         v = sorted(x[key] for x in samples if isinstance(x.get(key), (int, float)))
         return v[len(v) // 2] if v else None
-    return {"joules_per_gemm": (e1 - e0) / reps, "reps": reps, "seconds": t1 - t0,
-            "avg_power_w": (e1 - e0) / (t1 - t0), "median_gfx_clock_mhz": med("gfx_clock_mhz"),
-            "median_power_w": med("power_w"), "median_temp_hotspot_c": med("temp_hotspot_c"),
-            "clock_samples": len(samples)}
+    powers = [x["power_w"] for x in samples if isinstance(x.get("power_w"), (int, float))]
+    out = {"joules_per_gemm": (e1 - e0) / reps, "reps": reps, "seconds": t1 - t0,
+           "avg_power_w": (e1 - e0) / (t1 - t0), "median_gfx_clock_mhz": med("gfx_clock_mhz"),
+           "median_power_w": med("power_w"), "median_temp_hotspot_c": med("temp_hotspot_c"),
+           "clock_samples": len(samples)}
+    if powers:
+        # second estimate from the 10 ms power samples; the accumulator can
+        # lag on some boards, moving energy between consecutive windows
+        out["joules_per_gemm_sampled"] = sum(powers) / len(powers) * (t1 - t0) / reps
+        if out["joules_per_gemm_sampled"] > 0 and \
+                abs(out["joules_per_gemm"] / out["joules_per_gemm_sampled"] - 1.0) > 0.25:
+            out["note"] = "energy accumulator and power samples disagree by more than 25%"
+    return out
 
 
 def cpu_baseline(A, B, C_gpu, n, target_s, onf_rows=None, precision=None):
