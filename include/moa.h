@@ -290,7 +290,7 @@ moa_status moa_error_norm(int64_t count, int32_t x_dtype, const void *X,
 typedef enum moa_kernel {
     MOA_K_ONF_F64 = 1,        /* plain ONF contraction, FP64 */
     MOA_K_ONF_F32 = 2,        /* plain ONF contraction, FP32 */
-    MOA_K_MFMA_F32 = 3,       /* FP32 matrix-core contraction */
+    MOA_K_MFMA_F32 = 3,       /* FP32 matrix-core product (record copies included) */
     MOA_K_SPLIT_BF16 = 4,     /* split-BF16 contraction (single product) */
     MOA_K_FP8 = 5,            /* scaled-FP8 contraction, one term */
     MOA_K_FP8_2TERM = 6,      /* scaled-FP8 contraction, two terms */
