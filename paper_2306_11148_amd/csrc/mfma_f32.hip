@@ -313,7 +313,9 @@ hipError_t launch_ring(const moa_gemm_desc &d, const uint8_t *Ap, const uint8_t 
 }
 
 struct F32Shape { int bm, bn, wm, wn; bool ring; };
-constexpr F32Shape kF32Mfma[] = {{128, 128, 64, 64, true}, {256, 256, 128, 64, true}, {BM, BN, WM, WN, false}};
+// 3 and 4: rectangular blocks of four 128 x 64 / 64 x 128 waves, two per CU
+constexpr F32Shape kF32Mfma[] = {{128, 128, 64, 64, true}, {256, 256, 128, 64, true}, {BM, BN, WM, WN, false},
+                                 {256, 128, 128, 64, true}, {128, 256, 64, 128, true}};
 constexpr int kRegisterStaged = 2;         // the variant without workspace
 
 }  // namespace
@@ -321,9 +323,15 @@ constexpr int kRegisterStaged = 2;         // the variant without workspace
 int mfma_f32_variant_count() { return (int)(sizeof(kF32Mfma) / sizeof(kF32Mfma[0])); }
 int mfma_f32_staged_variant() { return kRegisterStaged; }
 
-// 256 x 256 blocks once they give every CU a block, else 128 x 128.
+// 256 x 256 blocks once they give every CU a block, else 128 x 128; the
+// rectangular blocks when 256 x 256 ones fill more than one round of the CUs
+// but leave the last round less than 40% full (as on the split-BF16 path).
 int mfma_f32_default_variant(int64_t m, int64_t p) {
-    return ((m + 255) / 256) * ((p + 255) / 256) >= kNumCUs ? 1 : 0;
+    const int64_t big = ((m + 255) / 256) * ((p + 255) / 256);
+    if (big < kNumCUs) return 0;
+    const int64_t tail = big % kNumCUs;
+    if (big > kNumCUs && tail != 0 && 10 * tail < 4 * kNumCUs) return p >= m ? 4 : 3;
+    return 1;
 }
 
 int64_t mfma_f32_workspace_bytes(int64_t m, int64_t n, int64_t p, int v) {
@@ -362,8 +370,12 @@ hipError_t launch_mfma_f32(const moa_gemm_desc &d, const Plan &plan, void *ws, h
             hipLaunchKernelGGL(f32_cols_kernel, dim3((unsigned)((d.p + 63) / 64), (unsigned)by), dim3(256), 0, st,
                                B, d.n, d.p, S, vec_b, Bp);
         }
-        if (plan.variant == 1) return launch_ring<256, 256, 128, 64>(d, Ap, Bp, S, st);
-        return launch_ring<128, 128, 64, 64>(d, Ap, Bp, S, st);
+        switch (plan.variant) {
+        case 1: return launch_ring<256, 256, 128, 64>(d, Ap, Bp, S, st);
+        case 3: return launch_ring<256, 128, 128, 64>(d, Ap, Bp, S, st);
+        case 4: return launch_ring<128, 256, 64, 128>(d, Ap, Bp, S, st);
+        default: return launch_ring<128, 128, 64, 64>(d, Ap, Bp, S, st);
+        }
     }
     const int tiles_m = (int)((d.m + BM - 1) / BM);
     const int tiles_n = (int)((d.p + BN - 1) / BN);

@@ -146,7 +146,9 @@ def test_mfma_f32_plan_variants():
     assert (small["variant"], small["tile_m"]) == (0, 128)
     staged = moa.moa_plan_query(_desc(8192, 8192, 8192, path=M, flags=moa.MOA_FLAG_VARIANT(2)))
     assert staged["workspace_bytes"] == 0 and staged["tile_k"] == 32
-    assert call(_desc(8, 8, 8, path=M, flags=moa.MOA_FLAG_VARIANT(3))) == moa.MOA_ERR_INVALID
+    assert call(_desc(8, 8, 8, path=M, flags=moa.MOA_FLAG_VARIANT(5))) == moa.MOA_ERR_INVALID
+    tail = moa.moa_plan_query(_desc(6144, 1024, 6144, path=M))   # 576 blocks: 2.25 rounds
+    assert (tail["variant"], tail["tile_m"], tail["tile_n"]) == (4, 128, 256)
     # the record ring's offsets bound n; the staged kernel has no such limit
     assert call(_desc(3, 16 * 131071 + 1, 5, path=M)) == moa.MOA_ERR_SHAPE
     moa.moa_plan_query(_desc(3, 16 * 131071 + 1, 5, path=M, flags=moa.MOA_FLAG_VARIANT(2)))

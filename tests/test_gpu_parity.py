@@ -132,18 +132,19 @@ def test_fp8_two_term_integer_exact():
 
 @pytest.mark.parametrize("shape", SHAPES)
 def test_mfma_f32_tolerance(shape):
-    """Every FP32 matrix-core variant within 1e-5 of Eq. 3 in FP64; the two
-    record-ring blocks (variants 0 and 1) walk the same per-element sequence
-    and agree bitwise; the register-staged kernel (variant 2) only within the
-    bar (its k pairing inside a matrix-core step differs)."""
+    """Every FP32 matrix-core variant within 1e-5 of Eq. 3 in FP64; the
+    record-ring blocks (variants 0, 1, 3, 4) walk the same per-element
+    sequence and agree bitwise; the register-staged kernel (variant 2) only
+    within the bar (its k pairing inside a matrix-core step differs)."""
     m, n, p = shape
     A, B = inputs.normal_f32(m, n, p, seed=m + 3 * p)
     R = O.gemm_f64(A.astype(np.float64), B.astype(np.float64))
-    assert variants("mfma_f32") == 3
-    out = [run(A, B, "mfma_f32", flags=moa.MOA_FLAG_VARIANT(v)) for v in range(3)]
+    assert variants("mfma_f32") == 5
+    out = [run(A, B, "mfma_f32", flags=moa.MOA_FLAG_VARIANT(v)) for v in range(5)]
     for C in out + [run(A, B, "mfma_f32")]:
         assert O.rel_err(C, R) <= 1e-5
-    assert np.array_equal(out[0], out[1])
+    for v in (1, 3, 4):
+        assert np.array_equal(out[0], out[v]), f"variant {v}"
 
 
 @pytest.mark.parametrize("variant", range(4))
