@@ -94,6 +94,12 @@ def test_fp8_plan_variants():
     assert big["tile_m"] == 256 and big["workgroups"] == 1024
 
 
+def test_fp8_one_term_default_shortens_the_last_round():
+    F8 = moa.MOA_PATH_FP8_SCALED
+    assert moa.moa_plan_query(_desc(8192, 4096, 8192, path=F8))["tile_m"] == 256    # 4 whole rounds
+    assert moa.moa_plan_query(_desc(6144, 6144, 6144, path=F8))["variant"] == 0     # 2.25 rounds
+
+
 def test_split_k_plan():
     """Split-k: chunks clamped so none is empty, partials in the workspace,
     one workgroup per (block, chunk), first block variant; ring paths only."""
