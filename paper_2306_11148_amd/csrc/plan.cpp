@@ -146,7 +146,11 @@ moa_status make_plan(const moa_gemm_desc &d_in, Plan *out) {
             pl.tuned = true;
         } else {
             v = 0;
-            for (int c = nv - 1; c >= 0; --c) {
+            // FP64: the 128 x 128 block (last entry) needs more registers than
+            // two waves per SIMD allow and measured slower than 64 x 128 at
+            // every N from 2048 to 8192, so the default stops one entry short
+            const int top = d.dtype == MOA_F64 ? nv - 2 : nv - 1;
+            for (int c = top; c >= 0; --c) {
                 Plan t;
                 onf_variant_shape((moa_dtype)d.dtype, c, &t);
                 if (tiles_for(d.m, d.p, t.tile_m, t.tile_n) >= kNumCUs) { v = c; break; }
