@@ -94,6 +94,21 @@ def test_fp8_plan_variants():
     assert big["tile_m"] == 256 and big["workgroups"] == 1024
 
 
+def test_split_default_block_rule():
+    """256x256 once every CU gets a block, 128x128 below; rectangular blocks
+    (orientation by the longer side) when the last round of 256x256 blocks
+    would be less than 40% full."""
+    S16 = moa.MOA_PATH_SPLIT_BF16
+    shape = lambda m, p: (lambda q: (q["variant"], q["tile_m"], q["tile_n"]))(
+        moa.moa_plan_query(_desc(m, 1024, p, path=S16)))
+    assert shape(3072, 3072) == (0, 128, 128)          # 144 big blocks
+    assert shape(4096, 4096) == (1, 256, 256)          # one whole round
+    assert shape(5120, 5120) == (1, 256, 256)          # 1.56 rounds
+    assert shape(6144, 6144) == (3, 128, 256)          # 2.25 rounds
+    assert shape(6400, 6144) == (2, 256, 128)          # 600 blocks, m > p
+    assert shape(8192, 8192) == (1, 256, 256)          # four whole rounds
+
+
 def test_fp8_one_term_default_shortens_the_last_round():
     F8 = moa.MOA_PATH_FP8_SCALED
     assert moa.moa_plan_query(_desc(8192, 4096, 8192, path=F8))["tile_m"] == 256    # 4 whole rounds
