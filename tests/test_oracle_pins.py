@@ -357,3 +357,18 @@ def test_gemm_batched_members():
     A = rng.integers(-8, 9, (3, 4, 5)).astype(np.float64)
     B = rng.integers(-8, 9, (3, 5, 6)).astype(np.float64)
     assert np.array_equal(O.gemm_batched(A, B), np.matmul(A, B))
+
+
+def test_max_row_rel_err_hand_values():
+    """Largest per-row error ||X_i - R_i|| / ||R_i|| (rows of C3 span 10^+-3,
+    where a normwise figure is dominated by the largest rows)."""
+    R = np.array([[3.0, 4.0], [0.0, 1e-3], [1e3, 0.0]])
+    X = np.array([[3.0, 4.0], [0.0, 2e-3], [1e3 + 1.0, 0.0]])
+    # row 0 exact, row 1 off by 100%, row 2 off by 1e-3
+    assert O.max_row_rel_err(X, R) == pytest.approx(1.0, rel=1e-15)
+    assert O.max_row_rel_err(X[[0, 2]], R[[0, 2]]) == pytest.approx(1e-3, rel=1e-12)
+    # the normwise error of the same data hides the small row
+    assert O.rel_err(X, R) < 2e-3
+    # a zero row of R contributes its absolute error
+    assert O.max_row_rel_err(np.array([[0.0, 0.5]]), np.zeros((1, 2))) == 0.5
+    assert O.max_row_rel_err(R, R) == 0.0
