@@ -282,6 +282,19 @@ moa_status moa_quantise_fp8(const float *A, int64_t m, int64_t n,
 moa_status moa_error_norm(int64_t count, int32_t x_dtype, const void *X,
                           const double *R, double *out, void *stream);
 
+/* Host-side check of the direct-to-LDS loads that the record-ring kernel of
+ * `desc`'s plan would issue (split-BF16, scaled FP8 and the FP32 matrix-core
+ * record variants; section "Dimension Lifting to Machine Coordinates": the
+ * blocks of the lift may overhang the matrix). Walks every block, wave and
+ * load of the launch on the host and counts loads that would read outside
+ * their record array or buffer range, or whose offsets overflow 32 bits.
+ * No device work; pointers in `desc` may be null. `loads` (may be null)
+ * receives the number of loads per slab checked, `violations` the count found
+ * (0 when every load is in bounds). Errors: as moa_plan_query;
+ * MOA_ERR_UNSUPPORTED when the plan runs no record ring (ONF, the
+ * register-staged FP32 variant). */
+moa_status moa_diag_ring_loads(const moa_gemm_desc *desc, int64_t *loads, int64_t *violations);
+
 /* ------------------------------------------------------------------------
  * Kernel timing (profiling aid). While enabled, every kernel the library
  * launches is bracketed by two HIP events recorded on the launch's own

@@ -7,6 +7,7 @@
 #include <string>
 
 #include "moa_internal.h"
+#include "ring_gemm.h"
 
 namespace moa {
 
@@ -291,6 +292,31 @@ moa_status moa_error_norm(int64_t count, int32_t x_dtype, const void *X, const d
     scratch_free(partials, st);
     if (e != hipSuccess) return hip_fail(e, "error-norm launch");
     return MOA_OK;
+}
+
+moa_status moa_diag_ring_loads(const moa_gemm_desc *desc, int64_t *loads, int64_t *violations) {
+    try {
+        if (!desc || !violations) return fail(MOA_ERR_INVALID, "null argument");
+        moa_status s = validate(*desc, false);
+        if (s != MOA_OK) return s;
+        const moa_gemm_desc d = row_major_result(*desc);
+        Plan pl;
+        if ((s = make_plan(d, &pl)) != MOA_OK) return s;
+        const bool ring = pl.path == MOA_PATH_SPLIT_BF16 || pl.path == MOA_PATH_FP8_SCALED ||
+                          (pl.path == MOA_PATH_MFMA_F32 && pl.workspace_bytes > 0);
+        if (!ring) return fail(MOA_ERR_UNSUPPORTED, "path %d runs no record ring", (int)pl.path);
+        const int nrec = pl.path == MOA_PATH_FP8_SCALED && (d.flags & MOA_FLAG_FP8_TWO_TERM) ? 2 : 1;
+        const int64_t S = (d.n + pl.tile_k - 1) / pl.tile_k;
+        if (d.m == 0 || d.p == 0 || S == 0) {
+            if (loads) *loads = 0;
+            *violations = 0;
+            return MOA_OK;
+        }
+        *violations = ring::check_loads(pl.tile_m, pl.tile_n, pl.wave_m, pl.wave_n, nrec, d.m, d.p, S, loads);
+        return MOA_OK;
+    } catch (...) {
+        return fail(MOA_ERR_DEVICE, "internal error");
+    }
 }
 
 const char *moa_status_string(moa_status s) {

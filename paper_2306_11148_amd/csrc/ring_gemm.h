@@ -77,6 +77,44 @@ template <int BM, int BN, int WM, int WN, int NREC, int NST = NSTAGE> struct Cfg
     static_assert(ONE_ARRAY || (16 * LPW <= BM && 16 * LPW <= BN), "a wave's rows span at most two arrays");
 };
 
+// Vector offset of a load that must touch no memory: beyond any resource
+// range (records per resource stay below 2^31 bytes).
+constexpr int kDeadVoffset = (int)0x80000000u;
+
+// Where LDS row `row` of a slab comes from (rows: [A array 0 (BM)] ..
+// [A array NREC-1] [B array 0 (BN)] ..): operand A or B, record array, the
+// row's index inside the block's part of that array, the block's first row
+// tile of the array and how many 16-row tiles of it exist from there (the
+// block may overhang the padded end). Shared by the kernels and the host
+// check of their loads (check_loads).
+struct RowWindow {
+    bool a;
+    int arr, row_in, tiles;
+    int64_t first_tile;
+};
+__host__ __device__ inline RowWindow row_window(int BM, int BN, int NREC, int row, int64_t i0, int64_t j0, int64_t m,
+                                                int64_t p) {
+    RowWindow w;
+    w.a = row < NREC * BM;
+    w.arr = NREC == 1 ? 0 : w.a ? row / BM : (row - NREC * BM) / BN;
+    w.row_in = w.a ? row - w.arr * BM : row - NREC * BM - w.arr * BN;
+    const int64_t org = w.a ? i0 : j0;
+    const int64_t left = padded_rows(w.a ? m : p) - org;
+    const int64_t span = w.a ? BM : BN;
+    w.first_tile = org / GROUP;
+    w.tiles = (int)((left < span ? left : span) / GROUP);
+    return w;
+}
+// The first of a wave's LPW loads whose rows lie in the next array (LPW when
+// they all lie in one).
+__host__ __device__ inline int q_split_of(int BM, int BN, int NREC, int LPW, bool one_array, int row_first) {
+    if (one_array) return LPW;
+    const int end0 = row_first < NREC * BM ? (row_first / BM + 1) * BM
+                                           : NREC * BM + ((row_first - NREC * BM) / BN + 1) * BN;
+    const int q = (end0 - row_first) / 16;
+    return q < LPW ? q : LPW;
+}
+
 // The conditioned operands of one product.
 struct Operands {
     const uint8_t *a0, *a1;               // record arrays of A (a1 only when NREC == 2)
@@ -128,46 +166,46 @@ __device__ __forceinline__ void tile(const Operands &op, int64_t i0, int64_t j0,
     static_assert(NREC == 1 || NREC == 2, "one or two record arrays per operand");
     const int64_t tile_row = S * GROUP * REC_BYTES;       // bytes per row tile (16 rows, all slabs)
     const int row_first = wave * LPW * 16;
-    // The array holding LDS row `row`: a buffer resource over this block's row
-    // tiles of it, and the row's index inside the block's part of the array.
-    // (with two arrays the select of the base becomes a variable index into
-    // `op`: keep `op` in kernel-argument or global memory, never in a local
-    // variable, or it is placed in scratch memory)
-    auto source = [&](int row, int *row_in) {
-        const bool a = row < NREC * BM;
-        const int arr = NREC == 1 ? 0 : a ? row / BM : (row - NREC * BM) / BN;
-        *row_in = a ? row - arr * BM : row - NREC * BM - arr * BN;
-        const int64_t org = a ? i0 : j0;
-        const int64_t lim = a ? op.m : op.p;
-        const int64_t tiles = min((int64_t)(a ? BM : BN), padded_rows(lim) - org) / GROUP;
-        const uint8_t *base = a ? (NREC == 1 || arr == 0 ? op.a0 : op.a1) : (NREC == 1 || arr == 0 ? op.b0 : op.b1);
-        return __builtin_amdgcn_make_buffer_rsrc((void *)(base + (org / GROUP) * tile_row), (short)0,
-                                                 (int)(tiles * tile_row), 0x00020000);
+    // A buffer resource over the block's row tiles of the array holding a
+    // window's rows. (with two arrays the select of the base becomes a
+    // variable index into `op`: keep `op` in kernel-argument or global memory,
+    // never in a local variable, or it is placed in scratch memory)
+    auto resource = [&](const RowWindow &w) {
+        const uint8_t *base = w.a ? (NREC == 1 || w.arr == 0 ? op.a0 : op.a1) : (NREC == 1 || w.arr == 0 ? op.b0 : op.b1);
+        return __builtin_amdgcn_make_buffer_rsrc((void *)(base + w.first_tile * tile_row), (short)0,
+                                                 (int)(w.tiles * tile_row), 0x00020000);
     };
-    int row_in0 = 0, row_in1 = 0;
-    const __amdgpu_buffer_rsrc_t rsrc0 = source(row_first, &row_in0);
-    int q_split = LPW;
+    const RowWindow w0 = row_window(BM, BN, NREC, row_first, i0, j0, op.m, op.p);
+    const __amdgpu_buffer_rsrc_t rsrc0 = resource(w0);
+    const int q_split = q_split_of(BM, BN, NREC, LPW, G::ONE_ARRAY, row_first);
+    RowWindow w1 = w0;
     __amdgpu_buffer_rsrc_t rsrc1 = rsrc0;
     if constexpr (!G::ONE_ARRAY) {
-        const int end0 = row_first < NREC * BM ? (row_first / BM + 1) * BM
-                                               : NREC * BM + ((row_first - NREC * BM) / BN + 1) * BN;
-        q_split = min(LPW, (end0 - row_first) / 16);
-        if (q_split < LPW) rsrc1 = source(row_first + 16 * q_split, &row_in1);
+        if (q_split < LPW) {
+            w1 = row_window(BM, BN, NREC, row_first + 16 * q_split, i0, j0, op.m, op.p);
+            rsrc1 = resource(w1);
+        }
     }
     // lane L lands at row 16Q + L/4, physical chunk L%4, and fetches logical
-    // chunk (L%4) ^ ((row/4) mod 4) = (L%4) ^ (L/16). Records past m (or p)
-    // lie beyond the resource's range and load as zeros (their outputs are
-    // not stored).
+    // chunk (L%4) ^ ((row/4) mod 4) = (L%4) ^ (L/16). Rows of the last
+    // partial tile past m (or p) are zero records written by the conditioning.
+    // A load whose whole 16-row tile lies past the padded end of its array
+    // (the block overhangs the operand) gets the vector offset 2^31, beyond
+    // the resource's range (below 2^31 bytes), so it touches no memory whether
+    // or not the range check counts the scalar offset (below 2^31 too, so the
+    // sum does not wrap); its LDS rows feed only outputs past m or p, which
+    // are never stored.
     const int voff = (lane >> 2) * REC_BYTES + (((lane & 3) ^ (lane >> 4)) << 4);
     auto issue = [&](int s) {            // s counts from s_begin
         uint8_t *buf = lds + (s % NSTAGE) * STAGE + row_first * REC_BYTES;
 #pragma unroll
         for (int q = 0; q < LPW; ++q) {
             const bool first = G::ONE_ARRAY || q < q_split;
-            const int tile_in = first ? row_in0 / GROUP + q : row_in1 / GROUP + (q - q_split);
+            const int tile_in = first ? w0.row_in / GROUP + q : w1.row_in / GROUP + (q - q_split);
+            const bool live = tile_in < (first ? w0.tiles : w1.tiles);
             __builtin_amdgcn_raw_ptr_buffer_load_lds(
-                first ? rsrc0 : rsrc1, (lds_void_t *)(buf + q * 16 * REC_BYTES), 16, voff,
-                (int)(tile_in * tile_row) + (s0 + s) * GROUP * REC_BYTES, 0, 0);
+                first ? rsrc0 : rsrc1, (lds_void_t *)(buf + q * 16 * REC_BYTES), 16,
+                live ? voff : kDeadVoffset, (int)(tile_in * tile_row) + (s0 + s) * GROUP * REC_BYTES, 0, 0);
         }
     };
 
@@ -340,6 +378,58 @@ hipError_t launch_splitk(const Operands &op, int chunks, float *partials, hipStr
     hipLaunchKernelGGL(splitk_reduce_kernel, grid, dim3(256), 0, st, partials, chunks, op.m, op.p, op.C, op.row_exp,
                        op.col_exp, op.accumulate);
     return hipGetLastError();
+}
+
+// Host check of the direct loads of single-product launches over an m x p
+// product with S slabs and blocks of BM x BN (waves WM x WN, NREC record
+// arrays per operand), through the same window functions as the kernel. For
+// every block, wave and load: a live load's last window (slab S-1, where the
+// offsets peak) lies inside its array's padded rows and inside its
+// resource's range, with both offsets below 2^31; a dead load's tile lies
+// wholly past the operand's padded rows (so its LDS rows feed only outputs
+// that are not stored), and its vector offset 2^31 exceeds every resource
+// range (num_records below 2^31). Returns the number of violations and the number of
+// loads checked per slab in *loads.
+inline int64_t check_loads(int BM, int BN, int WM, int WN, int NREC, int64_t m, int64_t p, int64_t S,
+                           int64_t *loads) {
+    const int NW = (BM / WM) * (BN / WN);
+    const int ROWS = NREC * (BM + BN);
+    const int LPW = ROWS / 16 / NW;
+    const bool one_array = BM % (16 * LPW) == 0 && BN % (16 * LPW) == 0;
+    const int64_t tile_row = S * GROUP * REC_BYTES;
+    const int64_t lim31 = (int64_t(1) << 31) - 1;
+    int64_t bad = 0, count = 0;
+    if (ROWS % (16 * NW) != 0 || S <= 0) return 1;
+    for (int64_t i0 = 0; i0 < m; i0 += BM)
+        for (int64_t j0 = 0; j0 < p; j0 += BN)
+            for (int wave = 0; wave < NW; ++wave) {
+                const int row_first = wave * LPW * 16;
+                const RowWindow w0 = row_window(BM, BN, NREC, row_first, i0, j0, m, p);
+                const int q_split = q_split_of(BM, BN, NREC, LPW, one_array, row_first);
+                const RowWindow w1 = q_split < LPW ? row_window(BM, BN, NREC, row_first + 16 * q_split, i0, j0, m, p) : w0;
+                for (int q = 0; q < LPW; ++q) {
+                    ++count;
+                    const bool first = one_array || q < q_split;
+                    const RowWindow &w = first ? w0 : w1;
+                    const int tile_in = first ? w0.row_in / GROUP + q : w1.row_in / GROUP + (q - q_split);
+                    // the load's rows in LDS must be the rows this window names
+                    const RowWindow here = row_window(BM, BN, NREC, row_first + 16 * q, i0, j0, m, p);
+                    if (here.a != w.a || here.arr != w.arr || here.row_in != tile_in * GROUP) ++bad;
+                    const int64_t padded_tiles = padded_rows(w.a ? m : p) / GROUP;
+                    const int64_t num_records = (int64_t)w.tiles * tile_row;
+                    if (w.tiles < 1 || num_records > lim31) ++bad;
+                    const int64_t soff = tile_in * tile_row + (S - 1) * GROUP * REC_BYTES;
+                    if (soff > lim31) ++bad;
+                    if (tile_in < w.tiles) {                  // live
+                        const int64_t end = soff + GROUP * REC_BYTES;   // voffset < 1 KiB, 16 bytes each
+                        if (w.first_tile + tile_in >= padded_tiles || end > num_records) ++bad;
+                    } else if (w.first_tile + tile_in < padded_tiles) {
+                        ++bad;                                // dead but inside the operand
+                    }
+                }
+            }
+    if (loads) *loads = count;
+    return bad;
 }
 
 }  // namespace ring

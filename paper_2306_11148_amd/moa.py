@@ -79,7 +79,7 @@ EXPORTS = [
     "moa_status_string", "moa_last_error", "moa_trace_enable", "moa_trace_read",
     "moa_group_create", "moa_group_launch", "moa_group_destroy",
     "moa_autotune", "moa_autotune_save", "moa_autotune_load", "moa_autotune_clear",
-    "moa_hadamard", "moa_kronecker", "moa_gemm_batched",
+    "moa_hadamard", "moa_kronecker", "moa_gemm_batched", "moa_diag_ring_loads",
 ]
 
 MOA_KERNELS = {1: "onf_f64", 2: "onf_f32", 3: "mfma_f32", 4: "split_bf16", 5: "fp8", 6: "fp8_2term",
@@ -133,6 +133,7 @@ def lib():
         "moa_hadamard": ([i64, i64, i32, vp, vp, vp, i32, vp], i32),
         "moa_kronecker": ([i64, i64, i64, i64, i32, vp, vp, vp, i32, vp], i32),
         "moa_gemm_batched": ([P(moa_gemm_desc), i64, i64, i64, i64, vp], i32),
+        "moa_diag_ring_loads": ([P(moa_gemm_desc), P(i64), P(i64)], i32),
     }
     for name, (args, res) in sig.items():
         fn = getattr(L, name)
@@ -226,6 +227,14 @@ def moa_plan_query(desc: moa_gemm_desc) -> dict:
     info = moa_plan_info()
     _check(lib().moa_plan_query(ctypes.byref(desc), ctypes.byref(info)), "moa_plan_query")
     return {f: getattr(info, f) for f, _ in moa_plan_info._fields_}
+
+
+def moa_diag_ring_loads(desc: moa_gemm_desc) -> tuple[int, int]:
+    """(loads checked per slab, violations) of the record-ring launch of desc's plan."""
+    loads, bad = ctypes.c_int64(), ctypes.c_int64()
+    _check(lib().moa_diag_ring_loads(ctypes.byref(desc), ctypes.byref(loads), ctypes.byref(bad)),
+           "moa_diag_ring_loads")
+    return loads.value, bad.value
 
 
 def moa_static_block_components(budget_bytes: int, elem_bytes: int, nblocks: int = 3) -> int:

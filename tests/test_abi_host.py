@@ -309,3 +309,53 @@ def test_autotune_table_save_load_and_validation(tmp_path):
     moa.moa_autotune_clear()
     assert moa.moa_plan_query(_desc(256, 256, 256, moa.MOA_F64))["tuned"] == 0
     assert moa.lib().moa_autotune(None, 1, None, None, None) == moa.MOA_ERR_INVALID
+
+
+def _plan_variants(path, two_term):
+    d = moa.moa_gemm_desc(m=64, n=64, p=64, dtype=moa.MOA_F32, path=path, A=None, B=None, C=None,
+                          accumulate=0, flags=moa.MOA_FLAG_FP8_TWO_TERM if two_term else 0)
+    count = 0
+    while True:
+        d.flags = (moa.MOA_FLAG_FP8_TWO_TERM if two_term else 0) | moa.MOA_FLAG_VARIANT(count)
+        try:
+            moa.moa_plan_query(d)
+        except moa.MoaError:
+            return count
+        count += 1
+
+
+RING_PATHS = [(moa.MOA_PATH_SPLIT_BF16, False), (moa.MOA_PATH_FP8_SCALED, False),
+              (moa.MOA_PATH_FP8_SCALED, True), (moa.MOA_PATH_MFMA_F32, False)]
+
+
+@pytest.mark.parametrize("path,two", RING_PATHS)
+def test_ring_loads_stay_in_bounds_for_every_variant_and_ragged_shape(path, two):
+    """Every direct load of the record ring reads inside its record array (or
+    is marked dead: out of its resource's range, touching no memory), for
+    blocks that overhang the operands by partial and by whole 16-row tiles."""
+    shapes = [(1, 1, 1), (17, 33, 15), (130, 70, 129), (255, 16, 257), (272, 100, 48), (48, 300, 272),
+              (513, 17, 769), (16, 4096, 1000), (1000, 4096, 16)]
+    ran = 0
+    for v in range(_plan_variants(path, two)):
+        flags = (moa.MOA_FLAG_FP8_TWO_TERM if two else 0) | moa.MOA_FLAG_VARIANT(v)
+        for m, n, p in shapes:
+            for extra in (0, moa.MOA_FLAG_C_COL):
+                d = moa.moa_gemm_desc(m=m, n=n, p=p, dtype=moa.MOA_F32, path=path, A=None, B=None, C=None,
+                                      accumulate=0, flags=flags | (extra if path != moa.MOA_PATH_MFMA_F32 else 0))
+                try:
+                    loads, bad = moa.moa_diag_ring_loads(d)
+                except moa.MoaError as e:
+                    assert e.status == moa.MOA_ERR_UNSUPPORTED      # the register-staged FP32 variant
+                    continue
+                assert bad == 0, (path, two, v, m, n, p, extra)
+                assert loads > 0
+                ran += 1
+    assert ran > 0
+
+
+def test_ring_load_check_refuses_non_ring_paths():
+    d = moa.moa_gemm_desc(m=8, n=8, p=8, dtype=moa.MOA_F64, path=moa.MOA_PATH_ONF, A=None, B=None, C=None,
+                          accumulate=0, flags=0)
+    with pytest.raises(moa.MoaError) as e:
+        moa.moa_diag_ring_loads(d)
+    assert e.value.status == moa.MOA_ERR_UNSUPPORTED
