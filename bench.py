@@ -398,7 +398,7 @@ def precision_section(torch, moa, inputs, reps=5):
            "error": "normwise vs the FP64 oracle on 48 seeded rows (computed in the CPU leg)"}
     kept = {}
     paths = [("onf_f32", moa.MOA_PATH_ONF, 0), ("mfma_f32", moa.MOA_PATH_MFMA_F32, 0),
-             ("split_bf16", moa.MOA_PATH_SPLIT_BF16, 0), ("fp8_1term", moa.MOA_PATH_FP8_SCALED, 0),
+             ("split_bf16", moa.MOA_PATH_SPLIT_BF16, 0), ("fp8_1term", moa.MOA_PATH_FP8_SCALED, moa.MOA_FLAG_FP8_ONE_TERM),
              ("fp8_2term", moa.MOA_PATH_FP8_SCALED, moa.MOA_FLAG_FP8_TWO_TERM)]
     L, st = moa.lib(), torch.cuda.current_stream().cuda_stream
     for name, path, flags in paths:
@@ -429,7 +429,7 @@ def sweep(args, torch, moa, inputs):
         for name, path, flags in (("onf_f32", moa.MOA_PATH_ONF, 0),
                                   ("mfma_f32", moa.MOA_PATH_MFMA_F32, 0),
                                   ("split_bf16", moa.MOA_PATH_SPLIT_BF16, 0),
-                                  ("fp8_1term", moa.MOA_PATH_FP8_SCALED, 0),
+                                  ("fp8_1term", moa.MOA_PATH_FP8_SCALED, moa.MOA_FLAG_FP8_ONE_TERM),
                                   ("fp8_2term", moa.MOA_PATH_FP8_SCALED, moa.MOA_FLAG_FP8_TWO_TERM)):
             d = moa.make_desc(A, B, C, path=path, flags=flags)
             L, st = moa.lib(), torch.cuda.current_stream().cuda_stream
@@ -506,7 +506,7 @@ def layout_sweep(args, torch, moa):
     B0 = torch.randn((N, N), generator=gen, device="cuda")
     C0 = torch.empty((N, N), device="cuda")
     for name, path, flags in (("split_bf16", moa.MOA_PATH_SPLIT_BF16, 0),
-                              ("fp8_1term", moa.MOA_PATH_FP8_SCALED, 0),
+                              ("fp8_1term", moa.MOA_PATH_FP8_SCALED, moa.MOA_FLAG_FP8_ONE_TERM),
                               ("onf_f32", moa.MOA_PATH_ONF, 0)):
         for ac, bc, cc in itertools.product([False, True], repeat=3):
             if name == "onf_f32" and len({ac, bc, cc}) > 1:

@@ -73,9 +73,10 @@ typedef enum moa_dtype {
  *                  (e the largest integer with amax * 2^e <= 448), rounded
  *                  to OCP E4M3, multiplied on FP8 matrix cores with FP32
  *                  accumulation and descaled exactly by 2^-(e_i+f_j).
- *                  With MOA_FLAG_FP8_TWO_TERM the rounding residual is kept
- *                  as a second E4M3 term (stored times 2^4) and
- *                  C = 2^-(e_i+f_j) (h.h + 2^-4 (h.l + l.h)). F32 only.
+ *                  By default the rounding residual is kept as a second
+ *                  E4M3 term (stored times 2^4) and
+ *                  C = 2^-(e_i+f_j) (h.h + 2^-4 (h.l + l.h)); with
+ *                  MOA_FLAG_FP8_ONE_TERM only h.h is formed. F32 only.
  *  AUTO         -- ONF for F64, SPLIT_BF16 for F32.
  * The split and FP8 paths require finite inputs. */
 typedef enum moa_path {
@@ -86,7 +87,15 @@ typedef enum moa_path {
     MOA_PATH_FP8_SCALED = 4
 } moa_path;
 
+/* Term count of the scaled-FP8 path. Two terms are the default (normwise
+ * error about 1e-3 against Eq. 3 on rows and columns spanning 10^+-3, within
+ * the 3e-2 bar of that path); MOA_FLAG_FP8_TWO_TERM names the default
+ * explicitly. MOA_FLAG_FP8_ONE_TERM opts into the single E4M3 term: about
+ * four times faster, but its error is about 3.7e-2 -- the four significant
+ * bits of E4M3, which no power-of-two scale improves -- above that bar.
+ * Setting both is MOA_ERR_INVALID. */
 #define MOA_FLAG_FP8_TWO_TERM 0x1u
+#define MOA_FLAG_FP8_ONE_TERM 0x2u
 /* Forces instantiation `v` (0-based) of the path's kernel table instead of
  * the planner's choice: the block sizes of the dimension lift, for block-size
  * sweeps and autotuning (moa_plan_query reports the resulting shape). An

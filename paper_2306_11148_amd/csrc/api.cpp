@@ -45,8 +45,11 @@ moa_status validate(const moa_gemm_desc &d, bool need_ptrs) {
     if (d.dtype != MOA_F64 && d.dtype != MOA_F32) return fail(MOA_ERR_INVALID, "unknown dtype %d", d.dtype);
     if (d.path < MOA_PATH_AUTO || d.path > MOA_PATH_FP8_SCALED)
         return fail(MOA_ERR_INVALID, "unknown path %d", d.path);
-    if (d.flags & ~(MOA_FLAG_FP8_TWO_TERM | MOA_FLAG_VARIANT_MASK | MOA_FLAG_SPLIT_K_MASK | MOA_FLAG_LAYOUT_MASK))
+    if (d.flags & ~(MOA_FLAG_FP8_TWO_TERM | MOA_FLAG_FP8_ONE_TERM | MOA_FLAG_VARIANT_MASK | MOA_FLAG_SPLIT_K_MASK |
+                    MOA_FLAG_LAYOUT_MASK))
         return fail(MOA_ERR_INVALID, "unknown flag bits 0x%x", d.flags);
+    if ((d.flags & MOA_FLAG_FP8_TWO_TERM) && (d.flags & MOA_FLAG_FP8_ONE_TERM))
+        return fail(MOA_ERR_INVALID, "MOA_FLAG_FP8_ONE_TERM and MOA_FLAG_FP8_TWO_TERM both set");
     const moa_path path = resolve_path(d);
     if (d.dtype == MOA_F64 && path != MOA_PATH_ONF)
         return fail(MOA_ERR_UNSUPPORTED, "FP64 runs on the ONF path only (path %d)", (int)path);
@@ -305,7 +308,7 @@ moa_status moa_diag_ring_loads(const moa_gemm_desc *desc, int64_t *loads, int64_
         const bool ring = pl.path == MOA_PATH_SPLIT_BF16 || pl.path == MOA_PATH_FP8_SCALED ||
                           (pl.path == MOA_PATH_MFMA_F32 && pl.workspace_bytes > 0);
         if (!ring) return fail(MOA_ERR_UNSUPPORTED, "path %d runs no record ring", (int)pl.path);
-        const int nrec = pl.path == MOA_PATH_FP8_SCALED && (d.flags & MOA_FLAG_FP8_TWO_TERM) ? 2 : 1;
+        const int nrec = pl.path == MOA_PATH_FP8_SCALED && fp8_two_term(d) ? 2 : 1;
         const int64_t S = (d.n + pl.tile_k - 1) / pl.tile_k;
         if (d.m == 0 || d.p == 0 || S == 0) {
             if (loads) *loads = 0;

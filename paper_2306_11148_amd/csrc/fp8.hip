@@ -625,7 +625,7 @@ int64_t fp8_workspace_bytes(int64_t m, int64_t n, int64_t p, bool two) {
 }
 
 hipError_t launch_fp8(const moa_gemm_desc &d, const Plan &plan, void *ws, hipStream_t st) {
-    const bool two = (d.flags & MOA_FLAG_FP8_TWO_TERM) != 0;
+    const bool two = fp8_two_term(d);
     const Fp8Workspace w = carve(ws, d.m, d.n, d.p, two);
     hipError_t err;
     {

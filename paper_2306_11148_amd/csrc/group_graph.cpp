@@ -63,7 +63,7 @@ moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group
                 return fail(MOA_ERR_UNSUPPORTED, "member %lld asks for split-k or a column-major operand: "
                             "not in a prepared group", (long long)k);
             if (pl.path == MOA_PATH_SPLIT_BF16) split.push_back(&d);
-            else if (pl.path == MOA_PATH_FP8_SCALED) fp8[(d.flags & MOA_FLAG_FP8_TWO_TERM) ? 1 : 0].push_back(&d);
+            else if (pl.path == MOA_PATH_FP8_SCALED) fp8[fp8_two_term(d) ? 1 : 0].push_back(&d);
             else if (pl.workspace_bytes == 0) single.push_back(d);
             else if (pl.path == MOA_PATH_MFMA_F32) {
                 f32m.push_back(d);

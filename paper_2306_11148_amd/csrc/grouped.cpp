@@ -132,7 +132,7 @@ moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t st
         } else if (path == MOA_PATH_SPLIT_BF16) {
             split.push_back(&d);
         } else if (path == MOA_PATH_FP8_SCALED) {
-            fp8[(d.flags & MOA_FLAG_FP8_TWO_TERM) ? 1 : 0].push_back(&d);
+            fp8[fp8_two_term(d) ? 1 : 0].push_back(&d);
         } else {
             moa_status s = run_gemm(d, stream);
             if (s != MOA_OK) return s;

@@ -67,6 +67,9 @@ inline moa_gemm_desc row_major_result(const moa_gemm_desc &d) {
 }
 inline bool has_col_operand(const moa_gemm_desc &d) { return (d.flags & MOA_FLAG_LAYOUT_MASK) != 0; }
 
+// Term count of a scaled-FP8 descriptor: two unless MOA_FLAG_FP8_ONE_TERM.
+inline bool fp8_two_term(const moa_gemm_desc &d) { return !(d.flags & MOA_FLAG_FP8_ONE_TERM); }
+
 // Chunk count asked for by MOA_FLAG_SPLIT_K (0 or 1: none).
 inline int split_k_requested(const moa_gemm_desc &d) { return (int)((d.flags & MOA_FLAG_SPLIT_K_MASK) >> 16); }
 // Chunks actually used for S slabs: ceil(S / ceil(S / c)), so none is empty.

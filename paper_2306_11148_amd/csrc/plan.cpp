@@ -35,7 +35,7 @@ int ceil_log2(int64_t x) {
 }
 
 ClassKey class_key(const moa_gemm_desc &d, moa_path path) {
-    return {d.dtype, (int)path, (d.flags & MOA_FLAG_FP8_TWO_TERM) ? 2 : 1, ceil_log2(d.m),
+    return {d.dtype, (int)path, path == MOA_PATH_FP8_SCALED && fp8_two_term(d) ? 2 : 1, ceil_log2(d.m),
             ceil_log2(d.n), ceil_log2(d.p)};
 }
 
@@ -57,7 +57,7 @@ int variant_count(const moa_gemm_desc &d, moa_path path) {
     case MOA_PATH_ONF: return onf_variant_count((moa_dtype)d.dtype);
     case MOA_PATH_SPLIT_BF16: return split_bf16_variant_count();
     case MOA_PATH_MFMA_F32: return mfma_f32_variant_count();
-    case MOA_PATH_FP8_SCALED: return fp8_variant_count((d.flags & MOA_FLAG_FP8_TWO_TERM) != 0);
+    case MOA_PATH_FP8_SCALED: return fp8_variant_count(fp8_two_term(d));
     default: return 1;
     }
 }
@@ -90,7 +90,7 @@ moa_status autotune_load(const char *path) {
         }
         moa_gemm_desc probe{};
         probe.dtype = k[0];
-        probe.flags = k[2] == 2 ? MOA_FLAG_FP8_TWO_TERM : 0;
+        probe.flags = k[2] == 2 ? 0 : MOA_FLAG_FP8_ONE_TERM;
         if (k[1] < MOA_PATH_ONF || k[1] > MOA_PATH_FP8_SCALED || (k[0] != MOA_F64 && k[0] != MOA_F32) ||
             t.variant < 0 || t.variant >= variant_count(probe, (moa_path)k[1])) {
             std::fclose(f);
@@ -203,7 +203,7 @@ moa_status make_plan(const moa_gemm_desc &d_in, Plan *out) {
         break;
     }
     case MOA_PATH_FP8_SCALED: {
-        const bool two = (d.flags & MOA_FLAG_FP8_TWO_TERM) != 0;
+        const bool two = fp8_two_term(d);
         pl.kernel = two ? K_FP8_2TERM : K_FP8;
         const int nv = fp8_variant_count(two);
         int v = 0;

@@ -19,6 +19,7 @@ MOA_F64, MOA_F32 = 0, 1
 MOA_PATH_AUTO, MOA_PATH_ONF, MOA_PATH_MFMA_F32 = 0, 1, 2
 MOA_PATH_SPLIT_BF16, MOA_PATH_FP8_SCALED = 3, 4
 MOA_FLAG_FP8_TWO_TERM = 0x1
+MOA_FLAG_FP8_ONE_TERM = 0x2
 
 PATHS = {"auto": MOA_PATH_AUTO, "onf": MOA_PATH_ONF, "mfma_f32": MOA_PATH_MFMA_F32,
          "split_bf16": MOA_PATH_SPLIT_BF16, "fp8": MOA_PATH_FP8_SCALED}

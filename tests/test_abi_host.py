@@ -76,7 +76,8 @@ def test_fp8_plan_variants():
     a workgroup per CU by default."""
     F8 = moa.MOA_PATH_FP8_SCALED
     TWO = moa.MOA_FLAG_FP8_TWO_TERM
-    one = [moa.moa_plan_query(_desc(1000, 300, 1000, path=F8, flags=moa.MOA_FLAG_VARIANT(v))) for v in range(2)]
+    ONE = moa.MOA_FLAG_FP8_ONE_TERM
+    one = [moa.moa_plan_query(_desc(1000, 300, 1000, path=F8, flags=ONE | moa.MOA_FLAG_VARIANT(v))) for v in range(2)]
     assert [(q["tile_m"], q["tile_n"], q["tile_k"]) for q in one] == [(128, 128, 64), (256, 256, 64)]
     assert [q["lds_bytes"] for q in one] == [3 * 256 * 64, 3 * 512 * 64]
     two = [moa.moa_plan_query(_desc(1000, 300, 1000, path=F8, flags=TWO | moa.MOA_FLAG_VARIANT(v)))
@@ -85,13 +86,16 @@ def test_fp8_plan_variants():
     assert all(q["lds_bytes"] == 3 * 2 * 256 * 64 for q in two)
     assert call(_desc(8, 8, 8, path=F8, flags=moa.MOA_FLAG_VARIANT(9))) == moa.MOA_ERR_INVALID
     # records: padded rows x ceil(n / 64) x 64 bytes per operand (twice for two terms)
-    q1 = moa.moa_plan_query(_desc(100, 200, 300, path=F8))
+    q1 = moa.moa_plan_query(_desc(100, 200, 300, path=F8, flags=ONE))
     q2 = moa.moa_plan_query(_desc(100, 200, 300, path=F8, flags=TWO))
     rec = (112 + 304) * 4 * 64
     assert rec <= q1["workspace_bytes"] < rec + 8 * 1024
     assert 2 * rec <= q2["workspace_bytes"] < 2 * rec + 8 * 1024
-    big = moa.moa_plan_query(_desc(8192, 8192, 8192, path=F8))
+    big = moa.moa_plan_query(_desc(8192, 8192, 8192, path=F8, flags=ONE))
     assert big["tile_m"] == 256 and big["workgroups"] == 1024
+    # two terms are the default; both flags together are refused
+    assert moa.moa_plan_query(_desc(100, 200, 300, path=F8)) == q2
+    assert call(_desc(8, 8, 8, path=F8, flags=ONE | TWO)) == moa.MOA_ERR_INVALID
 
 
 def test_split_default_block_rule():
@@ -111,8 +115,9 @@ def test_split_default_block_rule():
 
 def test_fp8_one_term_default_shortens_the_last_round():
     F8 = moa.MOA_PATH_FP8_SCALED
-    assert moa.moa_plan_query(_desc(8192, 4096, 8192, path=F8))["tile_m"] == 256    # 4 whole rounds
-    assert moa.moa_plan_query(_desc(6144, 6144, 6144, path=F8))["variant"] == 0     # 2.25 rounds
+    ONE = moa.MOA_FLAG_FP8_ONE_TERM
+    assert moa.moa_plan_query(_desc(8192, 4096, 8192, path=F8, flags=ONE))["tile_m"] == 256    # 4 whole rounds
+    assert moa.moa_plan_query(_desc(6144, 6144, 6144, path=F8, flags=ONE))["variant"] == 0     # 2.25 rounds
 
 
 def test_split_k_plan():
@@ -140,7 +145,7 @@ def test_size_limits_at_the_boundary():
     """The record offsets inside one 16-row tile are 32-bit: n may reach
     16 * 131071 on split-BF16 (16 k per record) and 64 * 131071 on FP8 (64 k
     per record); one more is refused with MOA_ERR_SHAPE, before any launch."""
-    cases = [(moa.MOA_PATH_SPLIT_BF16, 0, 16), (moa.MOA_PATH_FP8_SCALED, 0, 64),
+    cases = [(moa.MOA_PATH_SPLIT_BF16, 0, 16), (moa.MOA_PATH_FP8_SCALED, moa.MOA_FLAG_FP8_ONE_TERM, 64),
              (moa.MOA_PATH_FP8_SCALED, moa.MOA_FLAG_FP8_TWO_TERM, 64)]
     for path, flags, k in cases:
         q = moa.moa_plan_query(_desc(3, k * 131071, 5, path=path, flags=flags))
@@ -313,10 +318,11 @@ def test_autotune_table_save_load_and_validation(tmp_path):
 
 def _plan_variants(path, two_term):
     d = moa.moa_gemm_desc(m=64, n=64, p=64, dtype=moa.MOA_F32, path=path, A=None, B=None, C=None,
-                          accumulate=0, flags=moa.MOA_FLAG_FP8_TWO_TERM if two_term else 0)
+                          accumulate=0, flags=0)
+    term = moa.MOA_FLAG_FP8_TWO_TERM if two_term else moa.MOA_FLAG_FP8_ONE_TERM if path == moa.MOA_PATH_FP8_SCALED else 0
     count = 0
     while True:
-        d.flags = (moa.MOA_FLAG_FP8_TWO_TERM if two_term else 0) | moa.MOA_FLAG_VARIANT(count)
+        d.flags = term | moa.MOA_FLAG_VARIANT(count)
         try:
             moa.moa_plan_query(d)
         except moa.MoaError:
@@ -337,7 +343,8 @@ def test_ring_loads_stay_in_bounds_for_every_variant_and_ragged_shape(path, two)
               (513, 17, 769), (16, 4096, 1000), (1000, 4096, 16)]
     ran = 0
     for v in range(_plan_variants(path, two)):
-        flags = (moa.MOA_FLAG_FP8_TWO_TERM if two else 0) | moa.MOA_FLAG_VARIANT(v)
+        term = moa.MOA_FLAG_FP8_TWO_TERM if two else moa.MOA_FLAG_FP8_ONE_TERM if path == moa.MOA_PATH_FP8_SCALED else 0
+        flags = term | moa.MOA_FLAG_VARIANT(v)
         for m, n, p in shapes:
             for extra in (0, moa.MOA_FLAG_C_COL):
                 d = moa.moa_gemm_desc(m=m, n=n, p=p, dtype=moa.MOA_F32, path=path, A=None, B=None, C=None,

@@ -92,7 +92,7 @@ def precision_workload():
 @pytest.mark.parametrize("path", ["split_bf16", "mfma_f32", "onf", "fp8", "fp8_two"])
 def test_precision_workload_every_path(precision_workload, path):
     A, B, At, Bt = precision_workload
-    flags = moa.MOA_FLAG_FP8_TWO_TERM if path == "fp8_two" else 0
+    flags = moa.MOA_FLAG_FP8_TWO_TERM if path == "fp8_two" else moa.MOA_FLAG_FP8_ONE_TERM if path == "fp8" else 0
     Ct = run(At, Bt, "fp8" if path == "fp8_two" else path, flags)
     rows = sample_rows(8192, 24, seed=84)
     got = Ct[torch.from_numpy(rows).to(DEV)].cpu().numpy()

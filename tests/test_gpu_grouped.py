@@ -158,7 +158,7 @@ def test_prepared_group_with_fp8_members_replays():
     with eager work in between all match single launches bitwise."""
     shapes = inputs.grouped_shapes(16, lo=3, hi=500, seed=33)
     ops = inputs.grouped_operands(shapes, seed=33)
-    flags = [0, moa.MOA_FLAG_FP8_TWO_TERM] * 6 + [0, 0, 0, 0]
+    flags = [moa.MOA_FLAG_FP8_ONE_TERM, moa.MOA_FLAG_FP8_TWO_TERM] * 6 + [0, 0, 0, 0]
     paths = ["fp8"] * 12 + ["split_bf16", "onf", "split_bf16", "mfma_f32"]
     members, refs = [], []
     for (A, B), path, fl in zip(ops, paths, flags):
@@ -192,7 +192,7 @@ def test_grouped_fp8_bitwise_equals_single(two, accumulate):
     shapes = inputs.grouped_shapes(30, lo=1, hi=600, seed=35)
     shapes[3] = (7, 0, 9)
     shapes[4] = (1, 300, 1)
-    fl = moa.MOA_FLAG_FP8_TWO_TERM if two else 0
+    fl = moa.MOA_FLAG_FP8_TWO_TERM if two else moa.MOA_FLAG_FP8_ONE_TERM
     rng = np.random.default_rng(36)
     host, dev, descs = [], [], []
     for (m, n, p) in shapes:

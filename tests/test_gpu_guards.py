@@ -71,7 +71,7 @@ def variant_count(path, flags, dtype):
 
 
 CASES = [("onf", 0, torch.float64), ("onf", 0, torch.float32), ("mfma_f32", 0, torch.float32),
-         ("split_bf16", 0, torch.float32), ("fp8", 0, torch.float32),
+         ("split_bf16", 0, torch.float32), ("fp8", moa.MOA_FLAG_FP8_ONE_TERM, torch.float32),
          ("fp8", moa.MOA_FLAG_FP8_TWO_TERM, torch.float32)]
 
 
@@ -87,7 +87,7 @@ def test_every_variant_writes_only_c(path, flags, dtype, shape):
         check(A, B, C)
 
 
-@pytest.mark.parametrize("path,flags", [("split_bf16", 0), ("fp8", 0), ("fp8", moa.MOA_FLAG_FP8_TWO_TERM)])
+@pytest.mark.parametrize("path,flags", [("split_bf16", 0), ("fp8", moa.MOA_FLAG_FP8_ONE_TERM), ("fp8", moa.MOA_FLAG_FP8_TWO_TERM)])
 @pytest.mark.parametrize("shape", SHAPES)
 def test_split_k_writes_only_c(path, flags, shape):
     m, n, p = shape
@@ -112,7 +112,7 @@ def test_column_major_operands_write_only_c(path, combo):
 
 def test_grouped_members_write_only_their_c():
     shapes = [(130, 77, 258), (1, 33, 1), (257, 1000, 129), (64, 16, 64), (300, 500, 3)]
-    paths = [("split_bf16", 0), ("fp8", 0), ("fp8", moa.MOA_FLAG_FP8_TWO_TERM), ("onf", 0), ("mfma_f32", 0)]
+    paths = [("split_bf16", 0), ("fp8", moa.MOA_FLAG_FP8_ONE_TERM), ("fp8", moa.MOA_FLAG_FP8_TWO_TERM), ("onf", 0), ("mfma_f32", 0)]
     members, descs = [], []
     for k, (m, n, p) in enumerate(shapes):
         for path, flags in paths:

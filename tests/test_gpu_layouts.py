@@ -65,7 +65,7 @@ def test_split_bf16_every_layout(shape, combo):
 @pytest.mark.parametrize("two", [False, True])
 def test_fp8_every_layout(two, combo):
     A, B = inputs.row_col_scaled_f32(130, 700, 90, seed=22)
-    C = run(A, B, "fp8", *combo, flags=moa.MOA_FLAG_FP8_TWO_TERM if two else 0)
+    C = run(A, B, "fp8", *combo, flags=moa.MOA_FLAG_FP8_TWO_TERM if two else moa.MOA_FLAG_FP8_ONE_TERM)
     Q = O.fp8_gemm_2term(A, B) if two else O.fp8_gemm(A, B)
     assert O.rel_err(C, Q) <= 1e-4
 

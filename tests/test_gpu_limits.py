@@ -21,7 +21,7 @@ DEV = "cuda:0"
 @pytest.mark.parametrize("path,flags,k", [
     ("split_bf16", 0, 16),
     ("split_bf16", moa.MOA_FLAG_SPLIT_K(7), 16),
-    ("fp8", 0, 64),
+    ("fp8", moa.MOA_FLAG_FP8_ONE_TERM, 64),
     ("fp8", moa.MOA_FLAG_FP8_TWO_TERM, 64),
 ])
 def test_longest_k_walk_exact(path, flags, k):

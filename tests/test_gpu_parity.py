@@ -171,7 +171,7 @@ def test_split_bf16_wide_dynamic_range():
 def test_fp8_against_quantised_product(shape, two):
     m, n, p = shape
     A, B = inputs.row_col_scaled_f32(m, n, p, seed=m + n)
-    C = run(A, B, "fp8", flags=moa.MOA_FLAG_FP8_TWO_TERM if two else 0)
+    C = run(A, B, "fp8", flags=moa.MOA_FLAG_FP8_TWO_TERM if two else moa.MOA_FLAG_FP8_ONE_TERM)
     Q = O.fp8_gemm_2term(A, B) if two else O.fp8_gemm(A, B)
     assert O.rel_err(C, Q) <= 1e-4
 
@@ -183,7 +183,7 @@ def test_fp8_every_variant_same_bits(two):
     the shape has ragged edges in m, n and p."""
     m, n, p = 300, 1000, 259
     A, B = inputs.row_col_scaled_f32(m, n, p, seed=41)
-    flag = moa.MOA_FLAG_FP8_TWO_TERM if two else 0
+    flag = moa.MOA_FLAG_FP8_TWO_TERM if two else moa.MOA_FLAG_FP8_ONE_TERM
     outs = [run(A, B, "fp8", flags=flag | moa.MOA_FLAG_VARIANT(v)) for v in range(variants("fp8", flag))]
     for o in outs[1:]:
         assert np.array_equal(outs[0], o)
@@ -194,10 +194,10 @@ def test_fp8_every_variant_same_bits(two):
 @pytest.mark.parametrize("variant", range(4))
 @pytest.mark.parametrize("two", [False, True])
 def test_fp8_variants_integer_exact(variant, two):
-    if variant >= variants("fp8", moa.MOA_FLAG_FP8_TWO_TERM if two else 0):
+    if variant >= variants("fp8", moa.MOA_FLAG_FP8_TWO_TERM if two else moa.MOA_FLAG_FP8_ONE_TERM):
         pytest.skip("no such block variant")
     A, B = inputs.integer_valued(260, 200, 300, seed=8, dtype=np.float32)
-    flag = (moa.MOA_FLAG_FP8_TWO_TERM if two else 0) | moa.MOA_FLAG_VARIANT(variant)
+    flag = (moa.MOA_FLAG_FP8_TWO_TERM if two else moa.MOA_FLAG_FP8_ONE_TERM) | moa.MOA_FLAG_VARIANT(variant)
     C = run(A, B, "fp8", flags=flag)
     assert np.array_equal(C.astype(np.float64), O.gemm_f64(A.astype(np.float64), B.astype(np.float64)))
 
@@ -315,3 +315,22 @@ def test_autotune_records_a_variant_and_results_stay_bitwise():
         assert np.array_equal(Ct.cpu().numpy(), O.gemm_f32_fma(A, B))
     finally:
         moa.moa_autotune_clear()
+
+
+@pytest.mark.parametrize("shape", [(512, 1024, 384), (257, 4096, 129)])
+def test_fp8_default_meets_the_path_bar_against_eq3(shape):
+    """The scaled-FP8 path's default mode (two terms) against Eq. 3 in FP64 on
+    rows of A and columns of B spanning 10^+-3: within the path's 3e-2 bar.
+    The one-term mode (opt-in) is reported beside it: its error is E4M3's
+    input rounding (4 significant bits), about 3.7e-2, above the bar."""
+    m, n, p = shape
+    A, B = inputs.row_col_scaled_f32(m, n, p, seed=m + n)
+    R = O.gemm_f64(A.astype(np.float64), B.astype(np.float64))
+    default = run(A, B, "fp8")
+    assert np.array_equal(default, run(A, B, "fp8", flags=moa.MOA_FLAG_FP8_TWO_TERM))
+    err_default = O.rel_err(default, R)
+    assert err_default <= 3e-2, err_default
+    assert O.rel_err(default, O.fp8_gemm_2term(A, B)) <= 1e-4
+    err_one = O.rel_err(run(A, B, "fp8", flags=moa.MOA_FLAG_FP8_ONE_TERM), R)
+    print(f"FP8 vs Eq. 3: two terms {err_default:.3e}, one term {err_one:.3e}")
+    assert 1e-2 < err_one < 6e-2

@@ -50,14 +50,14 @@ def test_split_bf16_split_k_tolerance_and_determinism(shape, chunks):
 def test_fp8_split_k_against_quantised_product(shape, two):
     m, n, p = shape
     A, B = inputs.row_col_scaled_f32(m, n, p, seed=m * 3 + n)
-    fl = moa.MOA_FLAG_SPLIT_K(5) | (moa.MOA_FLAG_FP8_TWO_TERM if two else 0)
+    fl = moa.MOA_FLAG_SPLIT_K(5) | (moa.MOA_FLAG_FP8_TWO_TERM if two else moa.MOA_FLAG_FP8_ONE_TERM)
     C = run(A, B, "fp8", fl)
     Q = O.fp8_gemm_2term(A, B) if two else O.fp8_gemm(A, B)
     assert O.rel_err(C, Q) <= 1e-4
     assert np.array_equal(C, run(A, B, "fp8", fl))
 
 
-@pytest.mark.parametrize("path,flags", [("split_bf16", 0), ("fp8", 0), ("fp8", moa.MOA_FLAG_FP8_TWO_TERM)])
+@pytest.mark.parametrize("path,flags", [("split_bf16", 0), ("fp8", moa.MOA_FLAG_FP8_ONE_TERM), ("fp8", moa.MOA_FLAG_FP8_TWO_TERM)])
 def test_split_k_integer_exact_and_accumulate(path, flags):
     A, B = inputs.integer_valued(70, 3000, 90, seed=12, dtype=np.float32)
     C0 = (np.arange(70 * 90, dtype=np.float32).reshape(70, 90) % 11)
