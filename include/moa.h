@@ -347,21 +347,57 @@ moa_status moa_trace_read(moa_trace_stat *out, int32_t capacity, int32_t *count,
  * Serving: a request loop that admits products of mixed shapes under an HBM
  * budget and batches them into grouped launches on several streams
  * (continuous batching: requests that arrive while others run are admitted
- * as slots and memory free up).
+ * as slots and memory free up). Not a construct of the paper; every request
+ * computes Eq. 3 as moa_gemm does, bitwise the same result.
+ *
+ * Two kinds of request:
+ *  - caller-owned: a moa_gemm_desc whose A, B, C are the caller's device
+ *    memory (moa_serve_submit);
+ *  - synthetic: (m, n, p, path, flags, seed) only (moa_serve_submit_synthetic).
+ *    The server takes A, B and C from its own pool at admission and draws A
+ *    and B on the device with moa_fill_synthetic's generator (A: operand 0,
+ *    B: operand 1, both with the request's seed) right before the group's
+ *    launch; C stays in the pool until the ticket is released.
+ *
+ * Memory: all device memory the server allocates -- synthetic operands and
+ * results, and the scratch of every grouped launch, caller-owned requests
+ * included -- comes from a pool whose total never exceeds hbm_budget_bytes.
+ * A request counts against the budget from admission to completion with its
+ * operands and result (caller-owned ones too) and the scratch it would take
+ * alone; a synthetic request's C stays counted until it is released.
+ *
+ * Ordering: the server's streams do not wait for any stream of the caller.
+ * The operands of a caller-owned request must be complete when it is
+ * submitted (e.g. the stream that produced them synchronized), and requests
+ * are unordered with respect to each other: two requests must not write the
+ * same C, and one must not read a C another writes.
  * ---------------------------------------------------------------------- */
 typedef struct moa_server moa_server;
 
 typedef struct moa_serve_cfg {
-    int64_t hbm_budget_bytes; /* admission bound on bytes held by in-flight
-                                 requests (operands, result and scratch) */
+    int64_t hbm_budget_bytes; /* bound on the bytes admitted requests hold
+                                 (operands, result, scratch) and on the
+                                 server's device memory */
     int32_t slots;            /* concurrent groups in flight (streams), >= 1 */
     int32_t max_group;        /* most requests per grouped launch, >= 1 */
     int32_t device;           /* HIP device ordinal */
-    int32_t reserved;
+    int32_t batch_window_us;  /* batching window, >= 0: a group is launched
+                                 once it has max_group requests or its oldest
+                                 request has waited this long (0: at once) */
 } moa_serve_cfg;
 
+/* A synthetic request: C (m x p, FP32, row-major) := A.B on `path` with
+ * `flags` (as in moa_gemm_desc; no layout flags), A (m x n) and B (n x p)
+ * drawn on the device from `seed`. */
+typedef struct moa_synth_request {
+    int64_t m, n, p;
+    int32_t path;             /* moa_path */
+    uint32_t flags;
+    uint64_t seed;
+} moa_synth_request;
+
 typedef struct moa_req_info {
-    int64_t t_submit_ns;      /* CLOCK_MONOTONIC at moa_serve_submit */
+    int64_t t_submit_ns;      /* CLOCK_MONOTONIC at submit */
     int64_t t_admit_ns;       /* admitted under the budget */
     int64_t t_start_ns;       /* its group's launch was enqueued */
     int64_t t_done_ns;        /* completion observed by the scheduler */
@@ -369,16 +405,32 @@ typedef struct moa_req_info {
     int32_t group_size;       /* members of the launch it ran in */
 } moa_req_info;
 
+typedef struct moa_serve_state {
+    int64_t held_bytes;       /* bytes counted against the budget now */
+    int64_t peak_held_bytes;  /* largest held_bytes so far */
+    int64_t pool_bytes;       /* device memory the server holds now */
+    int64_t peak_pool_bytes;  /* largest pool_bytes so far */
+    int64_t admitted, completed, failed, waiting;   /* request counts */
+} moa_serve_state;
+
 /* Starts the scheduler thread. Errors: MOA_ERR_INVALID (null, slots < 1,
- * max_group < 1, budget <= 0), MOA_ERR_DEVICE. */
+ * max_group < 1, budget <= 0, negative window, no such device),
+ * MOA_ERR_DEVICE. */
 moa_status moa_serve_create(const moa_serve_cfg *cfg, moa_server **out);
 
-/* Queues one product (descriptor copied). The operands are caller-owned
- * device memory that must stay valid until the request completes. Returns a
- * ticket. Errors: argument errors as moa_gemm; MOA_ERR_NOMEM if the request
- * alone exceeds the whole budget. Thread-safe. */
+/* Queues one caller-owned product (descriptor copied; see Ordering above).
+ * Returns a ticket. Errors: argument errors as moa_gemm; MOA_ERR_NOMEM if
+ * the request alone exceeds the whole budget. Thread-safe. */
 moa_status moa_serve_submit(moa_server *srv, const moa_gemm_desc *desc,
                             uint64_t *ticket);
+
+/* Queues one synthetic product. Errors: argument errors as moa_gemm for the
+ * equivalent FP32 descriptor; MOA_ERR_INVALID for layout flags;
+ * MOA_ERR_NOMEM if it alone exceeds the whole budget. A request that the
+ * device cannot hold even with nothing else in the pool completes with
+ * status MOA_ERR_NOMEM. Thread-safe. */
+moa_status moa_serve_submit_synthetic(moa_server *srv, const moa_synth_request *req,
+                                      uint64_t *ticket);
 
 /* MOA_OK and the timestamps once the request is done (its C is final),
  * MOA_NOT_READY before, MOA_ERR_INVALID for an unknown ticket. A completed
@@ -387,18 +439,48 @@ moa_status moa_serve_submit(moa_server *srv, const moa_gemm_desc *desc,
 moa_status moa_serve_poll(moa_server *srv, uint64_t ticket,
                           moa_req_info *out);
 
-/* Frees the record of a completed ticket; later polls of it return
- * MOA_ERR_INVALID. MOA_NOT_READY (nothing changes) while the request runs,
- * MOA_ERR_INVALID for an unknown or already released ticket. Records of
- * tickets never released are kept until moa_serve_destroy, so a long-running
- * server should release each ticket once it has read it. Thread-safe. */
+/* Device address of the C of a done request (the server's for a synthetic
+ * one, valid until release; the caller's otherwise). MOA_NOT_READY before
+ * completion, MOA_ERR_INVALID for an unknown ticket. */
+moa_status moa_serve_result(moa_server *srv, uint64_t ticket, const void **C);
+
+/* Synchronous copy of a done request's C (m p elements) to `dst` (host or
+ * device memory of at least dst_bytes bytes). Errors as moa_serve_result;
+ * MOA_ERR_INVALID if dst_bytes is too small; MOA_ERR_DEVICE for a failed
+ * copy. */
+moa_status moa_serve_read(moa_server *srv, uint64_t ticket, void *dst, int64_t dst_bytes);
+
+/* Frees the record of a completed ticket (and a synthetic request's C);
+ * later calls with it return MOA_ERR_INVALID. MOA_NOT_READY (nothing
+ * changes) while the request runs, MOA_ERR_INVALID for an unknown or already
+ * released ticket. Records and synthetic results of tickets never released
+ * are kept until moa_serve_destroy and keep counting against the budget, so
+ * a long-running server must release each ticket once it has read it.
+ * Thread-safe. */
 moa_status moa_serve_release(moa_server *srv, uint64_t ticket);
 
 /* Waits until every submitted request is done. */
 moa_status moa_serve_drain(moa_server *srv);
 
-/* Drains, stops the scheduler and frees the server. */
+/* Budget and pool figures of the server (host call, thread-safe). */
+moa_status moa_serve_stats(moa_server *srv, moa_serve_state *out);
+
+/* Drains, stops the scheduler and frees the server with its pool. */
 moa_status moa_serve_destroy(moa_server *srv);
+
+/* Synthetic operand draw on the device, asynchronous on `stream`: X[e] for
+ * e < count (FP32, 4-byte aligned device memory) gets element e of operand
+ * `operand` for `seed`. Generator: Philox4x32-10 (Salmon, Moraes, Dror and
+ * Shaw, SC 2011); pair q = e / 2 draws the block with counter
+ * (q mod 2^32, q / 2^32, operand, 0) and key (seed mod 2^32, seed / 2^32);
+ * element 2q takes words 0 and 1, element 2q + 1 words 2 and 3; with S the
+ * sum of the four 16-bit halves of its two words, the value is the FP32
+ * product (2 S - 262140) * c, c the FP32 value nearest sqrt(3) * 2^-17 (a
+ * centred sum of four uniform variates: mean 0, variance 1). Errors:
+ * MOA_ERR_SHAPE (count < 0), MOA_ERR_INVALID (null or misaligned X),
+ * MOA_ERR_DEVICE. */
+moa_status moa_fill_synthetic(float *X, int64_t count, uint64_t seed, uint32_t operand,
+                              void *stream);
 
 /* Static string for a status code. */
 const char *moa_status_string(moa_status s);

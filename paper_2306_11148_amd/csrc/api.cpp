@@ -82,12 +82,18 @@ moa_status validate(const moa_gemm_desc &d, bool need_ptrs) {
     return MOA_OK;
 }
 
-moa_status run_gemm(const moa_gemm_desc &d_in, hipStream_t stream) {
+moa_status run_gemm_in(const moa_gemm_desc &d_in, hipStream_t stream, void *fixed_ws, int64_t fixed_bytes) {
     if (d_in.m == 0 || d_in.p == 0) return MOA_OK;
     const moa_gemm_desc d = row_major_result(d_in);
     Plan pl;
     moa_status s = make_plan(d, &pl);
     if (s != MOA_OK) return s;
+    if (fixed_ws && pl.workspace_bytes > fixed_bytes)
+        return fail(MOA_ERR_NOMEM, "the product needs %lld bytes of scratch, the fixed scratch array holds %lld",
+                    (long long)pl.workspace_bytes, (long long)fixed_bytes);
+    void *ws = fixed_ws;
+    const bool cached = !fixed_ws && pl.path != MOA_PATH_ONF;
+    if (cached && (s = scratch_alloc(&ws, pl.workspace_bytes, stream)) != MOA_OK) return s;
     hipError_t e = hipSuccess;
     switch (pl.path) {
     case MOA_PATH_ONF: {
@@ -96,30 +102,27 @@ moa_status run_gemm(const moa_gemm_desc &d_in, hipStream_t stream) {
         break;
     }
     case MOA_PATH_MFMA_F32: {
-        void *ws = nullptr;
-        s = scratch_alloc(&ws, pl.workspace_bytes, stream);
-        if (s != MOA_OK) return s;
-        {
-            TraceScope ts(pl.kernel, stream);      // record copies and contraction
-            e = launch_mfma_f32(d, pl, ws, stream);
-        }
-        scratch_free(ws, stream);
+        TraceScope ts(pl.kernel, stream);      // record copies and contraction
+        e = launch_mfma_f32(d, pl, ws, stream);
         break;
     }
-    case MOA_PATH_SPLIT_BF16:
-    case MOA_PATH_FP8_SCALED: {
-        void *ws = nullptr;
-        s = scratch_alloc(&ws, pl.workspace_bytes, stream);
-        if (s != MOA_OK) return s;
-        e = pl.path == MOA_PATH_SPLIT_BF16 ? launch_split_bf16(d, pl, ws, stream)
-                                            : launch_fp8(d, pl, ws, stream);
-        scratch_free(ws, stream);
-        break;
+    case MOA_PATH_SPLIT_BF16: e = launch_split_bf16(d, pl, ws, stream); break;
+    case MOA_PATH_FP8_SCALED: e = launch_fp8(d, pl, ws, stream); break;
+    default: s = fail(MOA_ERR_INVALID, "unresolved path");
     }
-    default: return fail(MOA_ERR_INVALID, "unresolved path");
-    }
+    if (cached) scratch_free(ws, stream);
+    if (s != MOA_OK) return s;
     if (e != hipSuccess) return hip_fail(e, "kernel launch");
     return MOA_OK;
+}
+
+moa_status run_gemm(const moa_gemm_desc &d, hipStream_t stream) { return run_gemm_in(d, stream, nullptr, 0); }
+
+int64_t gemm_workspace_bytes(const moa_gemm_desc &d) {
+    if (d.m == 0 || d.p == 0) return 0;
+    Plan pl;
+    if (make_plan(row_major_result(d), &pl) != MOA_OK) return 0;
+    return pl.workspace_bytes;
 }
 
 }  // namespace moa

@@ -93,65 +93,114 @@ moa_status check_group_overlap(const moa_gemm_desc *descs, int64_t count) {
 
 namespace {
 
-// One persistent launch sequence over `list`: workspace from the scratch
-// cache, member table through pinned staging.
+int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
+
+// The next `bytes` of `arena` (256-byte aligned), or null when it is full.
+void *arena_take(ScratchArena *a, int64_t bytes) {
+    const int64_t off = align256(a->used);
+    if (bytes <= 0) return nullptr;
+    if (off + bytes > a->size) return nullptr;
+    a->used = off + bytes;
+    return static_cast<char *>(a->base) + off;
+}
+
+// One persistent launch sequence over `list`: workspace from `arena` when
+// given, else from the scratch cache; member table through pinned staging.
 template <class Bytes, class Launch>
 moa_status run_list(const std::vector<const moa_gemm_desc *> &list, int64_t desc_bytes, Bytes ws_bytes,
-                    Launch launch, hipStream_t stream) {
+                    Launch launch, hipStream_t stream, ScratchArena *arena) {
     if (list.empty()) return MOA_OK;
     if (list.size() > (size_t)INT32_MAX) return fail(MOA_ERR_INVALID, "too many members");
     const int cnt = (int)list.size();
+    const int64_t need = ws_bytes(list.data(), cnt);
     void *ws = nullptr;
-    moa_status s = scratch_alloc(&ws, ws_bytes(list.data(), cnt), stream);
-    if (s != MOA_OK) return s;
+    moa_status s = MOA_OK;
+    if (arena) {
+        if (need > 0 && !(ws = arena_take(arena, need)))
+            return fail(MOA_ERR_NOMEM, "grouped scratch of %lld bytes exceeds the arena", (long long)need);
+    } else if ((s = scratch_alloc(&ws, need, stream)) != MOA_OK) {
+        return s;
+    }
     Staging st;
     s = staging_acquire((size_t)desc_bytes, &st);
     if (s != MOA_OK) {
-        scratch_free(ws, stream);
+        if (!arena) scratch_free(ws, stream);
         return s;
     }
     const hipError_t e = launch(list.data(), cnt, ws, st.ptr);
     staging_release(st, stream);
-    scratch_free(ws, stream);
+    if (!arena) scratch_free(ws, stream);
     if (e != hipSuccess) return hip_fail(e, "grouped launch");
     return MOA_OK;
 }
 
-}  // namespace
+// The members that run as persistent launches (split-BF16; FP8 by term
+// count) and those that run singly, as run_grouped splits them.
+struct Partition {
+    std::vector<const moa_gemm_desc *> single, split, fp8[2];
+};
 
-moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t stream) {
-    std::vector<const moa_gemm_desc *> split, fp8[2];
+Partition partition(const moa_gemm_desc *descs, int64_t count) {
+    Partition pt;
     for (int64_t g = 0; g < count; ++g) {
         const moa_gemm_desc &d = descs[g];
         if (d.m == 0 || d.p == 0) continue;
         const moa_path path = resolve_path(d);
-        if (split_k_requested(d) > 1 || has_col_operand(d)) {   // the persistent launches take
-                                                                  // row-major, unsplit members
-            moa_status s = run_gemm(d, stream);
-            if (s != MOA_OK) return s;
-        } else if (path == MOA_PATH_SPLIT_BF16) {
-            split.push_back(&d);
-        } else if (path == MOA_PATH_FP8_SCALED) {
-            fp8[fp8_two_term(d) ? 1 : 0].push_back(&d);
+        if (split_k_requested(d) > 1 || has_col_operand(d))   // the persistent launches take
+            pt.single.push_back(&d);                          // row-major, unsplit members
+        else if (path == MOA_PATH_SPLIT_BF16)
+            pt.split.push_back(&d);
+        else if (path == MOA_PATH_FP8_SCALED)
+            pt.fp8[fp8_two_term(d) ? 1 : 0].push_back(&d);
+        else
+            pt.single.push_back(&d);
+    }
+    return pt;
+}
+
+}  // namespace
+
+int64_t grouped_scratch_bytes(const moa_gemm_desc *descs, int64_t count) {
+    const Partition pt = partition(descs, count);
+    int64_t total = 0;
+    for (const moa_gemm_desc *d : pt.single) total += align256(gemm_workspace_bytes(*d));
+    if (!pt.split.empty())
+        total += align256(split_grouped_workspace_bytes(pt.split.data(), (int)pt.split.size()));
+    for (int two = 0; two < 2; ++two)
+        if (!pt.fp8[two].empty())
+            total += align256(fp8_grouped_workspace_bytes(pt.fp8[two].data(), (int)pt.fp8[two].size(), two != 0));
+    return total;
+}
+
+moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t stream, ScratchArena *arena) {
+    const Partition pt = partition(descs, count);
+    for (const moa_gemm_desc *d : pt.single) {
+        moa_status s;
+        if (arena) {
+            const int64_t need = gemm_workspace_bytes(*d);
+            void *ws = arena_take(arena, need);
+            if (need > 0 && !ws)
+                return fail(MOA_ERR_NOMEM, "scratch of %lld bytes exceeds the arena", (long long)need);
+            s = run_gemm_in(*d, stream, ws ? ws : arena->base, need);
         } else {
-            moa_status s = run_gemm(d, stream);
-            if (s != MOA_OK) return s;
+            s = run_gemm(*d, stream);
         }
+        if (s != MOA_OK) return s;
     }
     moa_status s = run_list(
-        split, split_grouped_desc_bytes(split.data(), (int)split.size()), split_grouped_workspace_bytes,
+        pt.split, split_grouped_desc_bytes(pt.split.data(), (int)pt.split.size()), split_grouped_workspace_bytes,
         [&](const moa_gemm_desc *const *m, int c, void *ws, void *host) {
             return launch_split_grouped(m, c, ws, host, stream);
         },
-        stream);
+        stream, arena);
     for (int two = 0; two < 2 && s == MOA_OK; ++two)
         s = run_list(
-            fp8[two], fp8_grouped_desc_bytes((int)fp8[two].size()),
+            pt.fp8[two], fp8_grouped_desc_bytes((int)pt.fp8[two].size()),
             [&](const moa_gemm_desc *const *m, int c) { return fp8_grouped_workspace_bytes(m, c, two != 0); },
             [&](const moa_gemm_desc *const *m, int c, void *ws, void *host) {
                 return launch_fp8_grouped(m, c, two != 0, ws, host, stream);
             },
-            stream);
+            stream, arena);
     return s;
 }
 

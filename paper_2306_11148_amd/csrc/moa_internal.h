@@ -191,17 +191,35 @@ hipError_t launch_quantise_fp8(const float *A, int64_t m, int64_t n, const float
                                int64_t p, bool two_term, int32_t *e, uint8_t *qA,
                                uint8_t *lA, int32_t *f, uint8_t *qB, uint8_t *lB,
                                uint32_t *amax_scratch, hipStream_t stream);
+// Synthetic operand fill (Philox4x32-10 counter-based draws; synthetic.hip).
+hipError_t launch_synthetic(float *X, int64_t count, uint64_t seed, uint32_t tag, hipStream_t stream);
 hipError_t launch_error_norm(int64_t count, moa_dtype xt, const void *X, const double *R,
                              double *out, double *partials, int nblocks, hipStream_t stream);
 
 // Runs one product: plan + scratch + launch. Used by moa_gemm and by the
 // grouped and serving paths for members that run alone.
 moa_status run_gemm(const moa_gemm_desc &d, hipStream_t stream);
+// The same with the workspace given: `fixed_ws` of `fixed_bytes` bytes
+// (MOA_ERR_NOMEM if the plan needs more), or the cached scratch when null.
+moa_status run_gemm_in(const moa_gemm_desc &d, hipStream_t stream, void *fixed_ws, int64_t fixed_bytes);
 
 // Grouped products (validated by the caller): split-BF16 members in one
 // persistent launch sequence, scaled-FP8 members in one per term count, the
 // others (and split-k or column-major members) one after another.
-moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t stream);
+// A caller-owned block of device memory that a grouped launch carves its
+// scratch from (256-byte aligned pieces, in launch order) instead of the
+// scratch cache.
+struct ScratchArena {
+    void *base = nullptr;
+    int64_t size = 0;
+    int64_t used = 0;
+};
+moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t stream,
+                       ScratchArena *arena = nullptr);
+// Bytes of scratch run_grouped takes from an arena for these members.
+int64_t grouped_scratch_bytes(const moa_gemm_desc *descs, int64_t count);
+// Scratch bytes of one product under its plan (0 for empty products).
+int64_t gemm_workspace_bytes(const moa_gemm_desc &d);
 moa_status check_group_overlap(const moa_gemm_desc *descs, int64_t count);
 
 // Scratch of one call on `stream` (scratch.cpp): cached device buffers,

@@ -1,161 +1,119 @@
-// Serving loop: continuous batching of independent products.
-//
-// Clients submit descriptors (thread-safe) and receive tickets. One
-// scheduler thread per server
-//   1. retires finished groups (hipEventQuery on each busy slot), releasing
-//      their bytes and marking their requests done;
-//   2. admits waiting requests in arrival order while the bytes held by
-//      in-flight requests stay within the HBM budget (first-come first-served:
-//      a request that does not fit yet blocks those behind it, so none
-//      starves), up to max_group per group;
-//   3. enqueues each admitted group on a free slot's stream as one grouped
-//      launch sequence (moa_gemm_grouped's path) and records a completion
-//      event behind it.
-// Requests that arrive while groups run are admitted as soon as a slot and
-// budget are free, so their work overlaps the running groups on other
-// streams. A request's bytes are its operands, its result and its scratch.
-#include <sys/prctl.h>
-
-#include <chrono>
-#include <condition_variable>
-#include <deque>
-#include <mutex>
-#include <thread>
-#include <unordered_map>
-#include <vector>
+// Serving loop on HIP: the scheduler of serve_core.h driven through one
+// stream and one completion event per slot. The pool's chunks are plain
+// device allocations of the server; a group's scratch is carved from them
+// (run_grouped with an arena), synthetic operands are drawn on the slot's
+// stream right before the group's launch.
+#include <memory>
 
 #include "moa_internal.h"
+#include "serve_core.h"
 
 namespace {
 
-int64_t now_ns() {
-    return std::chrono::duration_cast<std::chrono::nanoseconds>(
-               std::chrono::steady_clock::now().time_since_epoch())
-        .count();
-}
+class HipBackend final : public moa::serve::Backend {
+  public:
+    explicit HipBackend(int device) : device_(device) {}
+    ~HipBackend() override {
+        for (size_t k = 0; k < streams_.size(); ++k) {
+            if (streams_[k]) {
+                (void)hipStreamSynchronize(streams_[k]);
+                (void)hipStreamDestroy(streams_[k]);
+            }
+            if (events_[k]) (void)hipEventDestroy(events_[k]);
+        }
+    }
 
-struct Request {
-    moa_gemm_desc d;
-    uint64_t ticket = 0;
-    int64_t bytes = 0;
-    moa_req_info info{};
-    bool done = false;
+    moa_status init(int slots) {
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(device_);
+        streams_.assign((size_t)slots, nullptr);
+        events_.assign((size_t)slots, nullptr);
+        moa_status s = MOA_OK;
+        for (int k = 0; k < slots && s == MOA_OK; ++k) {
+            hipError_t e;
+            if ((e = hipStreamCreateWithFlags(&streams_[k], hipStreamNonBlocking)) != hipSuccess ||
+                (e = hipEventCreateWithFlags(&events_[k], hipEventDisableTiming)) != hipSuccess)
+                s = moa::hip_fail(e, "slot stream/event");
+        }
+        (void)hipSetDevice(prev);
+        return s;
+    }
+
+    void thread_start() override { (void)hipSetDevice(device_); }
+
+    void *device_alloc(int64_t bytes) override {
+        void *p = nullptr;
+        if (hipMalloc(&p, (size_t)bytes) != hipSuccess) {
+            (void)hipGetLastError();
+            return nullptr;
+        }
+        return p;
+    }
+    void device_free(void *p) override { (void)hipFree(p); }
+
+    int64_t group_scratch_bytes(const moa_gemm_desc *d, int64_t count) override {
+        return moa::grouped_scratch_bytes(d, count);
+    }
+
+    moa_status fill(int slot, float *x, int64_t count, uint64_t seed, uint32_t tag) override {
+        const hipError_t e = moa::launch_synthetic(x, count, seed, tag, streams_[slot]);
+        return e == hipSuccess ? MOA_OK : moa::hip_fail(e, "synthetic fill");
+    }
+
+    moa_status launch(int slot, const moa_gemm_desc *d, int64_t count, void *scratch, int64_t bytes) override {
+        moa::ScratchArena arena;
+        arena.base = scratch;
+        arena.size = scratch ? bytes : 0;
+        return moa::run_grouped(d, count, streams_[slot], &arena);
+    }
+
+    moa_status mark(int slot) override {
+        const hipError_t e = hipEventRecord(events_[slot], streams_[slot]);
+        return e == hipSuccess ? MOA_OK : moa::hip_fail(e, "completion event");
+    }
+
+    moa_status query(int slot) override {
+        const hipError_t q = hipEventQuery(events_[slot]);
+        if (q == hipSuccess) return MOA_OK;
+        if (q == hipErrorNotReady) return MOA_NOT_READY;
+        (void)hipGetLastError();
+        return MOA_ERR_DEVICE;
+    }
+
+    void wait(int slot) override {
+        if ((size_t)slot < streams_.size() && streams_[slot]) (void)hipStreamSynchronize(streams_[slot]);
+    }
+
+  private:
+    int device_;
+    std::vector<hipStream_t> streams_;
+    std::vector<hipEvent_t> events_;
 };
-
-struct Slot {
-    hipStream_t stream = nullptr;
-    hipEvent_t done = nullptr;
-    std::vector<Request *> members;
-    int64_t bytes = 0;
-    bool busy = false;
-};
-
-int64_t request_bytes(const moa_gemm_desc &d) {
-    const int64_t es = d.dtype == MOA_F64 ? 8 : 4;
-    int64_t b = (d.m * d.n + d.n * d.p + d.m * d.p) * es;
-    moa::Plan pl;
-    if (d.m > 0 && d.p > 0 && moa::make_plan(d, &pl) == MOA_OK) b += pl.workspace_bytes;
-    return b;
-}
 
 }  // namespace
 
+// The backend outlives the scheduler: members are destroyed in reverse order.
 struct moa_server {
-    moa_serve_cfg cfg{};
-    std::mutex mu;
-    std::condition_variable cv_work;    // scheduler: new submissions / stop
-    std::condition_variable cv_done;    // drain: completions
-    std::deque<Request *> waiting;
-    std::unordered_map<uint64_t, Request *> all;
-    std::vector<Slot> slots;
-    uint64_t next_ticket = 1;
-    int64_t held_bytes = 0;
-    int64_t outstanding = 0;            // submitted and not done
-    bool stop = false;
-    std::thread sched;
-
-    void run();
-    bool retire_locked();
+    HipBackend backend;
+    std::unique_ptr<moa::serve::Server> server;
+    int64_t budget;
+    explicit moa_server(int device, int64_t b) : backend(device), budget(b) {}
 };
 
-bool moa_server::retire_locked() {
-    bool any = false;
-    for (Slot &s : slots) {
-        if (!s.busy) continue;
-        const hipError_t q = hipEventQuery(s.done);
-        if (q == hipErrorNotReady) continue;
-        const int64_t t = now_ns();
-        for (Request *r : s.members) {
-            r->info.t_done_ns = t;
-            if (q != hipSuccess) r->info.status = MOA_ERR_DEVICE;
-            r->done = true;
-        }
-        outstanding -= (int64_t)s.members.size();
-        held_bytes -= s.bytes;
-        s.members.clear();
-        s.bytes = 0;
-        s.busy = false;
-        any = true;
-    }
-    return any;
-}
-
-void moa_server::run() {
-    (void)hipSetDevice(cfg.device);
-    // the completion polls below wait 20 us; the default timer slack of a
-    // thread (50 us) would stretch each of them to about 70 us
-    (void)prctl(PR_SET_TIMERSLACK, 1000UL, 0UL, 0UL, 0UL);
-    std::unique_lock<std::mutex> lk(mu);
-    std::vector<moa_gemm_desc> descs;
-    for (;;) {
-        if (retire_locked()) cv_done.notify_all();
-        // admit and launch while there is a free slot and admissible work
-        bool launched = false;
-        for (Slot &s : slots) {
-            if (s.busy || waiting.empty()) continue;
-            if (held_bytes + waiting.front()->bytes > cfg.hbm_budget_bytes) break;
-            const int64_t t_admit = now_ns();
-            while (!waiting.empty() && (int)s.members.size() < cfg.max_group &&
-                   held_bytes + s.bytes + waiting.front()->bytes <= cfg.hbm_budget_bytes) {
-                Request *r = waiting.front();
-                waiting.pop_front();
-                r->info.t_admit_ns = t_admit;
-                s.bytes += r->bytes;
-                s.members.push_back(r);
-            }
-            held_bytes += s.bytes;
-            s.busy = true;
-            descs.clear();
-            for (Request *r : s.members) descs.push_back(r->d);
-            const int64_t t_start = now_ns();
-            for (Request *r : s.members) {
-                r->info.t_start_ns = t_start;
-                r->info.group_size = (int32_t)s.members.size();
-            }
-            lk.unlock();   // enqueue without blocking submitters
-            moa_status st = moa::run_grouped(descs.data(), (int64_t)descs.size(), s.stream);
-            hipError_t e = hipEventRecord(s.done, s.stream);
-            lk.lock();
-            if (st != MOA_OK || e != hipSuccess)
-                for (Request *r : s.members) r->info.status = st != MOA_OK ? st : MOA_ERR_DEVICE;
-            launched = true;
-        }
-        if (stop && outstanding == 0) break;
-        bool busy = false;
-        for (const Slot &s : slots) busy = busy || s.busy;
-        if (launched) continue;
-        if (busy) {
-            // groups in flight: poll their events at a fine interval
-            cv_work.wait_for(lk, std::chrono::microseconds(20));
-        } else if (waiting.empty()) {
-            cv_work.wait(lk, [&] { return stop || !waiting.empty(); });
-        } else {
-            cv_work.wait_for(lk, std::chrono::microseconds(20));
-        }
-    }
-}
-
 using namespace moa;
+
+namespace {
+
+moa_status status_of(moa_status s, moa_server *srv, uint64_t ticket) {
+    switch (s) {
+    case MOA_ERR_INVALID: return fail(s, "unknown ticket %llu", (unsigned long long)ticket);
+    case MOA_ERR_NOMEM: return fail(s, "request needs more than the budget of %lld bytes", (long long)srv->budget);
+    default: return s;
+    }
+}
+
+}  // namespace
 
 extern "C" {
 
@@ -163,32 +121,20 @@ moa_status moa_serve_create(const moa_serve_cfg *cfg, moa_server **out) {
     try {
         if (!cfg || !out) return fail(MOA_ERR_INVALID, "null argument");
         *out = nullptr;
-        if (cfg->slots < 1 || cfg->max_group < 1 || cfg->hbm_budget_bytes <= 0)
-            return fail(MOA_ERR_INVALID, "slots and max_group must be >= 1 and the budget positive");
+        if (cfg->slots < 1 || cfg->max_group < 1 || cfg->hbm_budget_bytes <= 0 || cfg->batch_window_us < 0)
+            return fail(MOA_ERR_INVALID,
+                        "slots and max_group must be >= 1, the budget positive and the window not negative");
         int ndev = 0;
         hipError_t e = hipGetDeviceCount(&ndev);
         if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
         if (cfg->device < 0 || cfg->device >= ndev) return fail(MOA_ERR_INVALID, "no device %d", cfg->device);
-        auto *srv = new moa_server();
-        srv->cfg = *cfg;
-        int prev = 0;
-        (void)hipGetDevice(&prev);
-        (void)hipSetDevice(cfg->device);
-        srv->slots.resize((size_t)cfg->slots);
-        for (Slot &s : srv->slots) {
-            if ((e = hipStreamCreateWithFlags(&s.stream, hipStreamNonBlocking)) != hipSuccess ||
-                (e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming)) != hipSuccess) {
-                for (Slot &t : srv->slots) {
-                    if (t.stream) (void)hipStreamDestroy(t.stream);
-                    if (t.done) (void)hipEventDestroy(t.done);
-                }
-                (void)hipSetDevice(prev);
-                delete srv;
-                return hip_fail(e, "slot stream/event");
-            }
+        auto *srv = new moa_server(cfg->device, cfg->hbm_budget_bytes);
+        moa_status s = srv->backend.init(cfg->slots);
+        if (s != MOA_OK) {
+            delete srv;
+            return s;
         }
-        (void)hipSetDevice(prev);
-        srv->sched = std::thread([srv] { srv->run(); });
+        srv->server.reset(new serve::Server(*cfg, &srv->backend));
         *out = srv;
         return MOA_OK;
     } catch (...) {
@@ -203,31 +149,33 @@ moa_status moa_serve_submit(moa_server *srv, const moa_gemm_desc *desc, uint64_t
         if (s != MOA_OK) return s;
         Plan pl;
         if (desc->m > 0 && desc->p > 0 && (s = make_plan(*desc, &pl)) != MOA_OK) return s;
-        auto *r = new Request();
-        r->d = *desc;
-        r->bytes = request_bytes(*desc);
-        r->info.t_submit_ns = now_ns();
-        r->info.status = MOA_OK;
-        if (r->bytes > srv->cfg.hbm_budget_bytes) {
-            const long long need = (long long)r->bytes;
-            delete r;
-            return fail(MOA_ERR_NOMEM, "request needs %lld bytes, budget is %lld", need,
-                        (long long)srv->cfg.hbm_budget_bytes);
-        }
-        {
-            std::lock_guard<std::mutex> lk(srv->mu);
-            if (srv->stop) {
-                delete r;
-                return fail(MOA_ERR_INVALID, "server is shutting down");
-            }
-            r->ticket = srv->next_ticket++;
-            srv->all[r->ticket] = r;
-            srv->waiting.push_back(r);
-            ++srv->outstanding;
-            *ticket = r->ticket;
-        }
-        srv->cv_work.notify_one();
-        return MOA_OK;
+        s = srv->server->submit(*desc, ticket);
+        if (s == MOA_ERR_INVALID) return fail(s, "server is shutting down");
+        return status_of(s, srv, 0);
+    } catch (...) {
+        return fail(MOA_ERR_DEVICE, "internal error");
+    }
+}
+
+moa_status moa_serve_submit_synthetic(moa_server *srv, const moa_synth_request *req, uint64_t *ticket) {
+    try {
+        if (!srv || !req || !ticket) return fail(MOA_ERR_INVALID, "null argument");
+        if (req->flags & MOA_FLAG_LAYOUT_MASK)
+            return fail(MOA_ERR_INVALID, "synthetic operands are row-major: no layout flags");
+        moa_gemm_desc d{};
+        d.m = req->m;
+        d.n = req->n;
+        d.p = req->p;
+        d.dtype = MOA_F32;
+        d.path = (moa_path)req->path;
+        d.flags = req->flags;
+        moa_status s = validate(d, false);
+        if (s != MOA_OK) return s;
+        Plan pl;
+        if (d.m > 0 && d.p > 0 && (s = make_plan(d, &pl)) != MOA_OK) return s;
+        s = srv->server->submit_synthetic(*req, ticket);
+        if (s == MOA_ERR_INVALID) return fail(s, "server is shutting down");
+        return status_of(s, srv, 0);
     } catch (...) {
         return fail(MOA_ERR_DEVICE, "internal error");
     }
@@ -235,47 +183,53 @@ moa_status moa_serve_submit(moa_server *srv, const moa_gemm_desc *desc, uint64_t
 
 moa_status moa_serve_poll(moa_server *srv, uint64_t ticket, moa_req_info *out) {
     if (!srv || !out) return fail(MOA_ERR_INVALID, "null argument");
-    std::lock_guard<std::mutex> lk(srv->mu);
-    auto it = srv->all.find(ticket);
-    if (it == srv->all.end()) return fail(MOA_ERR_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
-    if (!it->second->done) return MOA_NOT_READY;
-    *out = it->second->info;
-    return MOA_OK;
+    return status_of(srv->server->poll(ticket, out), srv, ticket);
+}
+
+moa_status moa_serve_result(moa_server *srv, uint64_t ticket, const void **C) {
+    if (!srv || !C) return fail(MOA_ERR_INVALID, "null argument");
+    int64_t bytes = 0;
+    return status_of(srv->server->result(ticket, C, &bytes), srv, ticket);
+}
+
+moa_status moa_serve_read(moa_server *srv, uint64_t ticket, void *dst, int64_t dst_bytes) {
+    try {
+        if (!srv || !dst) return fail(MOA_ERR_INVALID, "null argument");
+        const void *C = nullptr;
+        int64_t bytes = 0;
+        moa_status s = srv->server->result(ticket, &C, &bytes);
+        if (s != MOA_OK) return status_of(s, srv, ticket);
+        if (dst_bytes < bytes) return fail(MOA_ERR_INVALID, "destination holds %lld bytes, C has %lld",
+                                           (long long)dst_bytes, (long long)bytes);
+        if (bytes == 0) return MOA_OK;
+        const hipError_t e = hipMemcpy(dst, C, (size_t)bytes, hipMemcpyDefault);
+        if (e != hipSuccess) return hip_fail(e, "copy of a result");
+        return MOA_OK;
+    } catch (...) {
+        return fail(MOA_ERR_DEVICE, "internal error");
+    }
 }
 
 moa_status moa_serve_release(moa_server *srv, uint64_t ticket) {
     if (!srv) return fail(MOA_ERR_INVALID, "null server");
-    std::lock_guard<std::mutex> lk(srv->mu);
-    auto it = srv->all.find(ticket);
-    if (it == srv->all.end()) return fail(MOA_ERR_INVALID, "unknown ticket %llu", (unsigned long long)ticket);
-    if (!it->second->done) return MOA_NOT_READY;
-    // a done request is referenced by no queue or slot any more
-    delete it->second;
-    srv->all.erase(it);
-    return MOA_OK;
+    return status_of(srv->server->release(ticket), srv, ticket);
 }
 
 moa_status moa_serve_drain(moa_server *srv) {
     if (!srv) return fail(MOA_ERR_INVALID, "null server");
-    std::unique_lock<std::mutex> lk(srv->mu);
-    srv->cv_done.wait(lk, [&] { return srv->outstanding == 0; });
+    srv->server->drain();
+    return MOA_OK;
+}
+
+moa_status moa_serve_stats(moa_server *srv, moa_serve_state *out) {
+    if (!srv || !out) return fail(MOA_ERR_INVALID, "null argument");
+    srv->server->stats(out);
     return MOA_OK;
 }
 
 moa_status moa_serve_destroy(moa_server *srv) {
     if (!srv) return MOA_OK;
-    {
-        std::lock_guard<std::mutex> lk(srv->mu);
-        srv->stop = true;
-    }
-    srv->cv_work.notify_all();
-    if (srv->sched.joinable()) srv->sched.join();
-    for (Slot &s : srv->slots) {
-        (void)hipStreamSynchronize(s.stream);
-        (void)hipStreamDestroy(s.stream);
-        (void)hipEventDestroy(s.done);
-    }
-    for (auto &kv : srv->all) delete kv.second;
+    srv->server.reset();
     delete srv;
     return MOA_OK;
 }

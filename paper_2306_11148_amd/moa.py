@@ -64,7 +64,19 @@ class moa_plan_info(ctypes.Structure):
 class moa_serve_cfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("slots", ctypes.c_int32),
                 ("max_group", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("reserved", ctypes.c_int32)]
+                ("batch_window_us", ctypes.c_int32)]
+
+
+class moa_synth_request(ctypes.Structure):
+    _fields_ = [("m", ctypes.c_int64), ("n", ctypes.c_int64), ("p", ctypes.c_int64),
+                ("path", ctypes.c_int32), ("flags", ctypes.c_uint32), ("seed", ctypes.c_uint64)]
+
+
+class moa_serve_state(ctypes.Structure):
+    _fields_ = [("held_bytes", ctypes.c_int64), ("peak_held_bytes", ctypes.c_int64),
+                ("pool_bytes", ctypes.c_int64), ("peak_pool_bytes", ctypes.c_int64),
+                ("admitted", ctypes.c_int64), ("completed", ctypes.c_int64),
+                ("failed", ctypes.c_int64), ("waiting", ctypes.c_int64)]
 
 
 class moa_req_info(ctypes.Structure):
@@ -76,7 +88,8 @@ class moa_req_info(ctypes.Structure):
 EXPORTS = [
     "moa_gemm", "moa_gemm_grouped", "moa_plan_query", "moa_static_block_components",
     "moa_split_bf16", "moa_quantise_fp8", "moa_error_norm", "moa_serve_create",
-    "moa_serve_submit", "moa_serve_poll", "moa_serve_release", "moa_serve_drain", "moa_serve_destroy",
+    "moa_serve_submit", "moa_serve_submit_synthetic", "moa_serve_poll", "moa_serve_result", "moa_serve_read",
+    "moa_serve_release", "moa_serve_drain", "moa_serve_stats", "moa_serve_destroy", "moa_fill_synthetic",
     "moa_status_string", "moa_last_error", "moa_trace_enable", "moa_trace_read",
     "moa_group_create", "moa_group_launch", "moa_group_destroy",
     "moa_autotune", "moa_autotune_save", "moa_autotune_load", "moa_autotune_clear",
@@ -117,6 +130,11 @@ def lib():
         "moa_serve_create": ([P(moa_serve_cfg), P(vp)], i32),
         "moa_serve_submit": ([vp, P(moa_gemm_desc), P(ctypes.c_uint64)], i32),
         "moa_serve_poll": ([vp, ctypes.c_uint64, P(moa_req_info)], i32),
+        "moa_serve_submit_synthetic": ([vp, P(moa_synth_request), P(ctypes.c_uint64)], i32),
+        "moa_serve_result": ([vp, ctypes.c_uint64, P(vp)], i32),
+        "moa_serve_read": ([vp, ctypes.c_uint64, vp, i64], i32),
+        "moa_serve_stats": ([vp, P(moa_serve_state)], i32),
+        "moa_fill_synthetic": ([vp, i64, ctypes.c_uint64, ctypes.c_uint32, vp], i32),
         "moa_serve_release": ([vp, ctypes.c_uint64], i32),
         "moa_serve_drain": ([vp], i32),
         "moa_serve_destroy": ([vp], i32),
@@ -265,9 +283,10 @@ def moa_error_norm(X, R, out, stream=None):
 
 # ------------------------------------------------------------------ serving --
 
-def moa_serve_create(hbm_budget_bytes: int, slots: int = 4, max_group: int = 16, device: int = 0):
+def moa_serve_create(hbm_budget_bytes: int, slots: int = 4, max_group: int = 16, device: int = 0,
+                     batch_window_us: int = 0):
     """Start a server; returns an opaque handle (int)."""
-    cfg = moa_serve_cfg(hbm_budget_bytes, slots, max_group, device, 0)
+    cfg = moa_serve_cfg(hbm_budget_bytes, slots, max_group, device, batch_window_us)
     h = ctypes.c_void_p()
     _check(lib().moa_serve_create(ctypes.byref(cfg), ctypes.byref(h)), "moa_serve_create")
     return h.value
@@ -277,6 +296,47 @@ def moa_serve_submit(srv, desc: moa_gemm_desc) -> int:
     t = ctypes.c_uint64()
     _check(lib().moa_serve_submit(srv, ctypes.byref(desc), ctypes.byref(t)), "moa_serve_submit")
     return t.value
+
+
+def moa_serve_submit_synthetic(srv, m: int, n: int, p: int, path, seed: int, flags: int = 0) -> int:
+    if isinstance(path, str):
+        path = PATHS[path]
+    req = moa_synth_request(m, n, p, path, flags, seed)
+    t = ctypes.c_uint64()
+    _check(lib().moa_serve_submit_synthetic(srv, ctypes.byref(req), ctypes.byref(t)),
+           "moa_serve_submit_synthetic")
+    return t.value
+
+
+def moa_serve_result(srv, ticket: int) -> int:
+    """Device address of a done request's C."""
+    c = ctypes.c_void_p()
+    _check(lib().moa_serve_result(srv, ticket, ctypes.byref(c)), "moa_serve_result")
+    return c.value or 0
+
+
+def moa_serve_read(srv, ticket: int, out):
+    """Copies a done request's C into `out` (a C-contiguous numpy array or
+    device tensor of m x p elements)."""
+    if hasattr(out, "data_ptr"):
+        ptr, nbytes = out.data_ptr(), out.numel() * out.element_size()
+    else:
+        ptr, nbytes = out.ctypes.data, out.nbytes
+    _check(lib().moa_serve_read(srv, ticket, ptr, nbytes), "moa_serve_read")
+    return out
+
+
+def moa_serve_stats(srv) -> dict:
+    st = moa_serve_state()
+    _check(lib().moa_serve_stats(srv, ctypes.byref(st)), "moa_serve_stats")
+    return {f: getattr(st, f) for f, _ in moa_serve_state._fields_}
+
+
+def moa_fill_synthetic(X, seed: int, operand: int, stream=None):
+    """Draws X (an FP32 device tensor) as operand `operand` of a request with `seed`."""
+    _check(lib().moa_fill_synthetic(X.data_ptr() if X.numel() else None, X.numel(), seed, operand,
+                                    _stream_handle(stream)), "moa_fill_synthetic")
+    return X
 
 
 def moa_serve_poll(srv, ticket: int):
