@@ -174,6 +174,23 @@ typedef struct moa_plan_info {
  * MOA_ERR_NOMEM (scratch), MOA_ERR_DEVICE (launch failure). */
 moa_status moa_gemm(const moa_gemm_desc *desc, void *stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops and harnesses that forbid hipMalloc): the product of
+ * moa_gemm -- same plan, same kernels, bitwise the same C -- with every
+ * scratch buffer (conditioned record tiles, exponents, split-k partials)
+ * placed in one fixed array of MOA_NOALLOC_SCRATCH_BYTES bytes that the
+ * library holds per GPU from the first call on that GPU until the process
+ * ends. The call allocates and frees nothing and records no memset; the
+ * caller still owns A, B and C. Every call on one GPU shares that GPU's
+ * array and leaves its contents behind: calls that overlap on one GPU (on
+ * different streams without ordering) race and give undefined results;
+ * calls ordered on one stream do not. Errors: as moa_gemm; MOA_ERR_NOMEM,
+ * with nothing launched, if the product needs more scratch than the array
+ * holds (moa_plan_info::workspace_bytes reports the need); the ONF path
+ * needs none. */
+#define MOA_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
+moa_status moa_gemm_noalloc(const moa_gemm_desc *desc, void *stream);
+
 /* `count` independent products. Members on the split-BF16 path (including
  * F32 with MOA_PATH_AUTO) are conditioned together and contracted by ONE
  * persistent launch that walks a shared tile list; scaled-FP8 members

@@ -86,7 +86,7 @@ class moa_req_info(ctypes.Structure):
 
 
 EXPORTS = [
-    "moa_gemm", "moa_gemm_grouped", "moa_plan_query", "moa_static_block_components",
+    "moa_gemm", "moa_gemm_noalloc", "moa_gemm_grouped", "moa_plan_query", "moa_static_block_components",
     "moa_split_bf16", "moa_quantise_fp8", "moa_error_norm", "moa_serve_create",
     "moa_serve_submit", "moa_serve_submit_synthetic", "moa_serve_poll", "moa_serve_result", "moa_serve_read",
     "moa_serve_release", "moa_serve_drain", "moa_serve_stats", "moa_serve_destroy", "moa_fill_synthetic",
@@ -121,6 +121,7 @@ def lib():
     P = ctypes.POINTER
     sig = {
         "moa_gemm": ([P(moa_gemm_desc), vp], i32),
+        "moa_gemm_noalloc": ([P(moa_gemm_desc), vp], i32),
         "moa_gemm_grouped": ([P(moa_gemm_desc), i64, vp], i32),
         "moa_plan_query": ([P(moa_gemm_desc), P(moa_plan_info)], i32),
         "moa_static_block_components": ([i64, i64, i64], i64),
@@ -230,6 +231,15 @@ def moa_gemm(A, B, C, path=MOA_PATH_AUTO, accumulate=False, flags=0, stream=None
     d = make_desc(A, B, C, path, accumulate, flags)
     _check(lib().moa_gemm(ctypes.byref(d), _stream_handle(stream)), "moa_gemm")
     return C
+
+
+def moa_gemm_noalloc(A, B, C, path=MOA_PATH_AUTO, accumulate=False, flags=0, stream=None):
+    d = make_desc(A, B, C, path, accumulate, flags)
+    _check(lib().moa_gemm_noalloc(ctypes.byref(d), _stream_handle(stream)), "moa_gemm_noalloc")
+    return C
+
+
+MOA_NOALLOC_SCRATCH_BYTES = 64 << 20
 
 
 def moa_gemm_desc_call(desc: moa_gemm_desc, stream=None) -> int:
