@@ -71,8 +71,8 @@ def parse():
                     help="time the N x N product for every row-/column-major combination of A, B, C "
                          "(gamma_row / gamma_col), one JSON line per point")
     ap.add_argument("--split-k", type=str, default=None,
-                    help="comma-separated chunk counts: time skinny products (few blocks of C, long k) "
-                         "with each, one JSON line per point")
+                    help="comma-separated chunk counts (0: the planner's choice, 1: unsplit): time skinny "
+                         "products (few blocks of C, long k) with each, one JSON line per point")
     ap.add_argument("--serve-rates", type=str, default=None,
                     help="comma-separated offered loads (req/s): run only the serving loop at each, "
                          "one JSON line per rate")
@@ -279,8 +279,10 @@ def cpu_baseline(A, B, C_gpu, n, target_s, onf_rows=None, precision=None):
 
 def grouped_section(torch, moa, inputs, reps=10):
     """512 products, m, n, p log-uniform in [32, 2048] (seed 4), N(0,1) FP32
-    operands drawn on the device from a seeded generator: one grouped launch
-    versus one launch per product."""
+    operands drawn on the device from a seeded generator: one grouped launch,
+    the same group prepared once and replayed as a HIP graph, and one launch
+    per product. The roofline of the set is the sum over products of
+    max(3 x 2 m n p / BF16 peak, 4 (m n + n p + m p) bytes / 8 TB/s)."""
     shapes = inputs.grouped_shapes(512, 32, 2048, seed=4)
     gen = torch.Generator(device="cuda").manual_seed(4)
     descs, keep = [], []
@@ -291,30 +293,53 @@ def grouped_section(torch, moa, inputs, reps=10):
         keep.append((A, B, C))
         descs.append(moa.make_desc(A, B, C, path=moa.MOA_PATH_SPLIT_BF16))
     flops = float(sum(2.0 * m * n * p for m, n, p in shapes))
+    roof_ms = float(sum(max(3 * 2.0 * m * n * p / (BF16_PEAK_TF * 1e12), 4.0 * (m * n + n * p + m * p) / 8e12)
+                        for m, n, p in shapes)) * 1e3
     import ctypes
     arr = (moa.moa_gemm_desc * len(descs))(*descs)
     L, st = moa.lib(), torch.cuda.current_stream().cuda_stream
+    group = moa.moa_group_create(descs)
 
     def grouped():
         if L.moa_gemm_grouped(arr, len(descs), st) != 0:
+            raise RuntimeError(moa.moa_last_error())
+
+    def replay():
+        if L.moa_group_launch(ctypes.c_void_p(group), st) != 0:
             raise RuntimeError(moa.moa_last_error())
 
     def singles():
         for d in descs:
             if L.moa_gemm(ctypes.byref(d), st) != 0:
                 raise RuntimeError(moa.moa_last_error())
-    for _ in range(2):
-        grouped()
-        singles()
-    per_g, tot_g = timed_loop(grouped, reps, torch)
-    per_s, tot_s = timed_loop(singles, reps, torch)
-    ms_g, ms_s = tot_g / reps, tot_s / reps
+    try:
+        for _ in range(2):
+            grouped()
+            replay()
+            singles()
+        per_g, tot_g = timed_loop(grouped, reps, torch)
+        per_r, tot_r = timed_loop(replay, reps, torch)
+        per_s, tot_s = timed_loop(singles, reps, torch)
+        moa.moa_trace_read(reset=True)
+        moa.moa_trace_enable(True)
+        timed_loop(grouped, reps, torch)
+        moa.moa_trace_enable(False)
+        traced = moa.moa_trace_read(reset=True)
+    finally:
+        moa.moa_group_destroy(group)
+    ms_g, ms_r, ms_s = tot_g / reps, tot_r / reps, tot_s / reps
+    n_k, t_k = traced.get("split_grouped", (0, 0.0))
     del keep
+    best = min(ms_g, ms_r)
     return {"workload": "512 products, m,n,p log-uniform [32,2048], split-BF16, seed 4",
-            "flop": flops, "grouped_ms": round(ms_g, 4), "per_gemm_launches_ms": round(ms_s, 4),
-            "grouped_tflops": round(flops / ms_g / 1e9, 2),
+            "flop": flops, "grouped_ms": round(ms_g, 4), "graph_replay_ms": round(ms_r, 4),
+            "per_gemm_launches_ms": round(ms_s, 4),
+            "grouped_tflops": round(flops / ms_g / 1e9, 2), "graph_replay_tflops": round(flops / ms_r / 1e9, 2),
             "per_gemm_tflops": round(flops / ms_s / 1e9, 2),
-            "speedup": round(ms_s / ms_g, 3)}
+            "speedup": round(ms_s / best, 3),
+            "contraction_kernel_ms": round(t_k / n_k, 4) if n_k else None,
+            "roofline": {"bound": "sum over products of max(matrix-core, HBM) time", "ideal_ms": round(roof_ms, 4),
+                         "frac": round(roof_ms / best, 4)}}
 
 
 def serving_section(torch, moa, inputs, rate, seconds, max_requests, seed=5, verify_share=0.01):
@@ -337,7 +362,8 @@ def serving_section(torch, moa, inputs, rate, seconds, max_requests, seed=5, ver
     seed_of = lambda q: (seed << 32) + q      # noqa: E731
     path_of = lambda q: "split_bf16" if split[q] else "fp8"   # noqa: E731
     budget = 200 << 30
-    srv = moa.moa_serve_create(budget, slots=4, max_group=16)
+    reserve = 16 << 30       # taken at creation: no allocation while requests run
+    srv = moa.moa_serve_create(budget, slots=4, max_group=16, pool_reserve_bytes=reserve)
     kept, infos, sched_ns = {}, [None] * count, [0] * count
     try:
         # untimed warm-up: the first shapes once through the server (code
@@ -404,7 +430,8 @@ def serving_section(torch, moa, inputs, rate, seconds, max_requests, seed=5, ver
            "mix": "70% split-BF16 / 30% two-term FP8, synthetic requests (operands drawn on the device "
                   "at admission), HBM budget 200 GB, 4 slots, groups <= 16",
            "first_5pct_discarded": skip,
-           "device_memory": {"budget_bytes": budget, "peak_pool_bytes": stats["peak_pool_bytes"],
+           "device_memory": {"budget_bytes": budget, "pool_reserve_bytes": reserve,
+                             "peak_pool_bytes": stats["peak_pool_bytes"],
                              "peak_held_bytes": stats["peak_held_bytes"]},
            "verified": None}
     return out, kept
@@ -619,10 +646,9 @@ def layout_sweep(args, torch, moa):
     C0 = torch.empty((N, N), device="cuda")
     for name, path, flags in (("split_bf16", moa.MOA_PATH_SPLIT_BF16, 0),
                               ("fp8_1term", moa.MOA_PATH_FP8_SCALED, moa.MOA_FLAG_FP8_ONE_TERM),
+                              ("mfma_f32", moa.MOA_PATH_MFMA_F32, 0),
                               ("onf_f32", moa.MOA_PATH_ONF, 0)):
         for ac, bc, cc in itertools.product([False, True], repeat=3):
-            if name == "onf_f32" and len({ac, bc, cc}) > 1:
-                continue
             d = moa.make_desc(A0.t() if ac else A0, B0.t() if bc else B0, C0.t() if cc else C0,
                               path=path, flags=flags)
 
@@ -652,7 +678,8 @@ def split_k_sweep(args, torch, moa, inputs):
         for name, path, base in (("split_bf16", moa.MOA_PATH_SPLIT_BF16, 0),
                                  ("fp8_2term", moa.MOA_PATH_FP8_SCALED, moa.MOA_FLAG_FP8_TWO_TERM)):
             for c in [int(x) for x in args.split_k.split(",")]:
-                d = moa.make_desc(A, B, C, path=path, flags=base | (moa.MOA_FLAG_SPLIT_K(c) if c > 1 else 0))
+                # c = 0: the planner's choice; c = 1: kept whole; c > 1: c chunks asked for
+                d = moa.make_desc(A, B, C, path=path, flags=base | (moa.MOA_FLAG_SPLIT_K(c) if c >= 1 else 0))
                 plan = moa.moa_plan_query(d)
 
                 def f():
@@ -662,7 +689,8 @@ def split_k_sweep(args, torch, moa, inputs):
                     f()
                 per, tot = timed_loop(f, 20, torch)
                 ms = tot / 20
-                print(json.dumps({"split_k_sweep": {"m": m, "n": n, "p": p, "path": name, "chunks": plan["split_k"],
+                print(json.dumps({"split_k_sweep": {"m": m, "n": n, "p": p, "path": name, "asked": c or "planner",
+                                                    "chunks": plan["split_k"],
                                                     "workgroups": plan["workgroups"], "ms": round(ms, 4),
                                                     "tflops": round(2.0 * m * n * p / ms / 1e9, 2),
                                                     "p50_ms": round(pct(per, 50), 4)}}), flush=True)

@@ -29,7 +29,13 @@
  *    its own arguments and, where it needs scratch space, a device buffer
  *    of the library's cache that no unfinished work on another stream still
  *    uses (the stream-ordered allocator while the stream is being captured).
- *    The cache keeps buffers between calls (at most 64 GiB per device).
+ *    A buffer last used on the calling stream is reused at once (stream
+ *    order covers the earlier use), so synchronize a stream before
+ *    destroying it: a new stream that receives the same handle would
+ *    otherwise not be ordered after the old stream's pending calls.
+ *    The cache keeps buffers between calls (at most 64 GiB per device); the
+ *    serving loop does not use it (its scratch comes from its budgeted
+ *    pool).
  */
 #ifndef MOA_H
 #define MOA_H
@@ -108,12 +114,16 @@ typedef enum moa_path {
  * chunk of one block of C into an FP32 partial, and a second kernel adds the
  * partials in chunk order, then applies the FP8 descale and the accumulate
  * form. For products with fewer blocks of C than compute units and a long k
- * walk. Split-BF16 and FP8 paths only (MOA_ERR_UNSUPPORTED otherwise). The
- * result is deterministic and within the path's error bound, but its
- * summation order differs from the unsplit product's, so it is not bitwise
- * equal to it. Grouped launches and the serving loop run such members as
- * single launches; prepared groups refuse them. The partials (c m p FP32
- * values) are part of the workspace. Occupies flag bits 16..23. */
+ * walk. Split-BF16 and FP8 paths only (MOA_ERR_UNSUPPORTED otherwise).
+ * Without the flag the planner splits by itself when the product's 128 x 128
+ * blocks number at most 64 and n >= 4096 (about 512 workgroups, chunks of at
+ * least 512 k); MOA_FLAG_SPLIT_K(1) keeps such a product unsplit. The result
+ * is deterministic and within the path's error bound, but its summation order
+ * differs from the unsplit product's, so it is not bitwise equal to it.
+ * Grouped launches and the serving loop run split members as single launches
+ * (the same plan as alone, so the same result); prepared groups refuse them.
+ * The partials (c m p FP32 values) are part of the workspace. Occupies flag
+ * bits 16..23. */
 #define MOA_FLAG_SPLIT_K(c) (((uint32_t)(c) & 0xFFu) << 16)
 #define MOA_FLAG_SPLIT_K_MASK 0xFF0000u
 /* Operand layouts from the paper's family of layout functions gamma (gamma_row,
@@ -121,11 +131,13 @@ typedef enum moa_path {
  * the m x n matrix A is stored column by column, element (i, k) at offset
  * i + k m; MOA_FLAG_B_COL likewise stores B (n x p) as k + j n and
  * MOA_FLAG_C_COL stores C (m x p) as i + j m. Shapes keep their meaning.
- * Split-BF16 and FP8 take any combination (the layout only changes how the
- * operands are conditioned; a column-major C is computed as C^T = B^T A^T).
- * ONF and FP32 matrix-core paths take all three row-major or all three
- * column-major (the same kernel on C^T = B^T A^T, no copies); other
- * combinations are MOA_ERR_UNSUPPORTED. Grouped launches run members with a
+ * Every path takes any combination; a column-major C is computed as
+ * C^T = B^T A^T with a row-major result (no copies). The split-BF16, FP8 and
+ * FP32 matrix-core ring paths condition a column-major operand with the other
+ * packer; the ONF kernel reads it along its contiguous extent and transposes
+ * it into its LDS slab, its k loop unchanged (bitwise the same result). The
+ * register-staged FP32 variant (MOA_FLAG_VARIANT(2)) takes row-major operands
+ * only (MOA_ERR_UNSUPPORTED otherwise). Grouped launches run members with a
  * column-major operand singly; prepared groups refuse them. */
 #define MOA_FLAG_A_COL 0x1000000u
 #define MOA_FLAG_B_COL 0x2000000u
@@ -401,6 +413,11 @@ typedef struct moa_serve_cfg {
     int32_t batch_window_us;  /* batching window, >= 0: a group is launched
                                  once it has max_group requests or its oldest
                                  request has waited this long (0: at once) */
+    int64_t pool_reserve_bytes; /* device memory the pool takes at creation
+                                 (0 .. budget); the pool grows beyond it on
+                                 demand. Allocating while groups run can stall
+                                 the device, so a serving loop reserves what
+                                 its load will hold. */
 } moa_serve_cfg;
 
 /* A synthetic request: C (m x p, FP32, row-major) := A.B on `path` with
@@ -430,9 +447,10 @@ typedef struct moa_serve_state {
     int64_t admitted, completed, failed, waiting;   /* request counts */
 } moa_serve_state;
 
-/* Starts the scheduler thread. Errors: MOA_ERR_INVALID (null, slots < 1,
- * max_group < 1, budget <= 0, negative window, no such device),
- * MOA_ERR_DEVICE. */
+/* Reserves the pool and starts the scheduler thread. Errors:
+ * MOA_ERR_INVALID (null, slots < 1, max_group < 1, budget <= 0, negative
+ * window, a reserve outside 0 .. budget, no such device), MOA_ERR_NOMEM (the
+ * reserve cannot be allocated), MOA_ERR_DEVICE. */
 moa_status moa_serve_create(const moa_serve_cfg *cfg, moa_server **out);
 
 /* Queues one caller-owned product (descriptor copied; see Ordering above).

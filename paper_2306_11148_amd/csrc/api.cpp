@@ -55,9 +55,6 @@ moa_status validate(const moa_gemm_desc &d, bool need_ptrs) {
         return fail(MOA_ERR_UNSUPPORTED, "FP64 runs on the ONF path only (path %d)", (int)path);
     if (split_k_requested(d) > 1 && path != MOA_PATH_SPLIT_BF16 && path != MOA_PATH_FP8_SCALED)
         return fail(MOA_ERR_UNSUPPORTED, "split-k needs the split-BF16 or FP8 path (path %d)", (int)path);
-    const uint32_t lay = d.flags & MOA_FLAG_LAYOUT_MASK;
-    if ((path == MOA_PATH_ONF || path == MOA_PATH_MFMA_F32) && lay != 0 && lay != MOA_FLAG_LAYOUT_MASK)
-        return fail(MOA_ERR_UNSUPPORTED, "path %d takes all operands row-major or all column-major", (int)path);
     const int64_t es = d.dtype == MOA_F64 ? 8 : 4;
     int64_t na, nb, nc, ba, bb, bc;
     if (!mul_ok(d.m, d.n, &na) || !mul_ok(d.n, d.p, &nb) || !mul_ok(d.m, d.p, &nc) ||

@@ -59,9 +59,11 @@ moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group
             if (d.m == 0 || d.p == 0) continue;
             Plan pl;
             if ((s = make_plan(d, &pl)) != MOA_OK) return s;
-            if (split_k_requested(d) > 1 || has_col_operand(d))
-                return fail(MOA_ERR_UNSUPPORTED, "member %lld asks for split-k or a column-major operand: "
-                            "not in a prepared group", (long long)k);
+            if (pl.split_k > 1 || has_col_operand(d))
+                return fail(MOA_ERR_UNSUPPORTED, "member %lld runs split-k (MOA_FLAG_SPLIT_K(1) turns it off) or "
+                            "has a column-major operand: not in a prepared group", (long long)k);
+            if (pl.path == MOA_PATH_SPLIT_BF16 && !split_grouped_fits(d))
+                return fail(MOA_ERR_UNSUPPORTED, "member %lld is too large for the persistent launch", (long long)k);
             if (pl.path == MOA_PATH_SPLIT_BF16) split.push_back(&d);
             else if (pl.path == MOA_PATH_FP8_SCALED) fp8[fp8_two_term(d) ? 1 : 0].push_back(&d);
             else if (pl.workspace_bytes == 0) single.push_back(d);

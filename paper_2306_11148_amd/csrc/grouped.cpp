@@ -146,9 +146,9 @@ Partition partition(const moa_gemm_desc *descs, int64_t count) {
         const moa_gemm_desc &d = descs[g];
         if (d.m == 0 || d.p == 0) continue;
         const moa_path path = resolve_path(d);
-        if (split_k_requested(d) > 1 || has_col_operand(d))   // the persistent launches take
-            pt.single.push_back(&d);                          // row-major, unsplit members
-        else if (path == MOA_PATH_SPLIT_BF16)
+        if (has_col_operand(d) || plans_split_k(d))   // the persistent launches take
+            pt.single.push_back(&d);                  // row-major, unsplit members
+        else if (path == MOA_PATH_SPLIT_BF16 && split_grouped_fits(d))
             pt.split.push_back(&d);
         else if (path == MOA_PATH_FP8_SCALED)
             pt.fp8[fp8_two_term(d) ? 1 : 0].push_back(&d);

@@ -362,13 +362,23 @@ hipError_t launch_mfma_f32(const moa_gemm_desc &d, const Plan &plan, void *ws, h
         uint8_t *Ap = static_cast<uint8_t *>(ws);
         uint8_t *Bp = Ap + ring::array_bytes(d.m, S);
         if (S > 0) {
-            const int vec_a = (d.n % 8 == 0) && ((uintptr_t)A % 16 == 0);
-            const int vec_b = (d.p % 4 == 0) && ((uintptr_t)B % 16 == 0);
-            const int64_t rb = std::min<int64_t>((padded_rows(d.m) * S * 2 + 255) / 256, 65536);
-            hipLaunchKernelGGL(f32_rows_kernel, dim3((unsigned)rb), dim3(256), 0, st, A, d.m, d.n, S, vec_a, Ap);
-            const int64_t by = std::min<int64_t>((S + 3) / 4, 65535);
-            hipLaunchKernelGGL(f32_cols_kernel, dim3((unsigned)((d.p + 63) / 64), (unsigned)by), dim3(256), 0, st,
-                               B, d.n, d.p, S, vec_b, Bp);
+            // A's rows and B's columns as records. A column-major A (element
+            // (i, k) at i + k m) is a row-major n x m array whose columns are
+            // A's rows; a column-major B is a row-major p x n array whose rows
+            // are B's columns.
+            auto rows = [&](const float *X, int64_t r, uint8_t *P) {
+                const int vec = (d.n % 8 == 0) && ((uintptr_t)X % 16 == 0);
+                const int64_t rb = std::min<int64_t>((padded_rows(r) * S * 2 + 255) / 256, 65536);
+                hipLaunchKernelGGL(f32_rows_kernel, dim3((unsigned)rb), dim3(256), 0, st, X, r, d.n, S, vec, P);
+            };
+            auto cols = [&](const float *X, int64_t c, uint8_t *P) {
+                const int vec = (c % 4 == 0) && ((uintptr_t)X % 16 == 0);
+                const int64_t by = std::min<int64_t>((S + 3) / 4, 65535);
+                hipLaunchKernelGGL(f32_cols_kernel, dim3((unsigned)((c + 63) / 64), (unsigned)by), dim3(256), 0, st,
+                                   X, d.n, c, S, vec, P);
+            };
+            if (d.flags & MOA_FLAG_A_COL) cols(A, d.m, Ap); else rows(A, d.m, Ap);
+            if (d.flags & MOA_FLAG_B_COL) rows(B, d.p, Bp); else cols(B, d.p, Bp);
         }
         switch (plan.variant) {
         case 1: return launch_ring<256, 256, 128, 64>(d, Ap, Bp, S, st);

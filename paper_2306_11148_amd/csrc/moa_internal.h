@@ -70,7 +70,7 @@ inline bool has_col_operand(const moa_gemm_desc &d) { return (d.flags & MOA_FLAG
 // Term count of a scaled-FP8 descriptor: two unless MOA_FLAG_FP8_ONE_TERM.
 inline bool fp8_two_term(const moa_gemm_desc &d) { return !(d.flags & MOA_FLAG_FP8_ONE_TERM); }
 
-// Chunk count asked for by MOA_FLAG_SPLIT_K (0 or 1: none).
+// Chunk count asked for by MOA_FLAG_SPLIT_K (0: the planner decides, 1: none).
 inline int split_k_requested(const moa_gemm_desc &d) { return (int)((d.flags & MOA_FLAG_SPLIT_K_MASK) >> 16); }
 // Chunks actually used for S slabs: ceil(S / ceil(S / c)), so none is empty.
 inline int split_k_chunks(int requested, int64_t S) {
@@ -84,6 +84,12 @@ inline int split_k_chunks(int requested, int64_t S) {
 moa_status validate(const moa_gemm_desc &d, bool need_ptrs);
 moa_path resolve_path(const moa_gemm_desc &d);
 moa_status make_plan(const moa_gemm_desc &d, Plan *out);
+// Whether the plan of `d` sums k in chunks over separate workgroups (asked
+// for or chosen by the planner).
+inline bool plans_split_k(const moa_gemm_desc &d) {
+    Plan pl;
+    return d.m > 0 && d.p > 0 && make_plan(d, &pl) == MOA_OK && pl.split_k > 1;
+}
 
 // gfx950 constants used by the static rule and the planner.
 constexpr int64_t kL1Bytes = 32 * 1024;        // vector L1 per CU
@@ -145,6 +151,9 @@ int64_t split_bf16_workspace_bytes(int64_t m, int64_t n, int64_t p);
 // split_grouped_desc_bytes(count) bytes that stays untouched until the
 // stream has passed this call.
 int64_t split_grouped_workspace_bytes(const moa_gemm_desc *const *members, int count);
+// Whether a split-BF16 member fits the persistent launch's 32-bit offsets
+// (else it runs as a single launch).
+bool split_grouped_fits(const moa_gemm_desc &d);
 int64_t split_grouped_desc_bytes(const moa_gemm_desc *const *members, int count);
 hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, void *workspace,
                                 void *host_staging, hipStream_t stream);

@@ -14,7 +14,9 @@
 //   k -> (LDS slab of BK, in-slab index)
 // Rows of A and B enter LDS as contiguous 16-byte vectors (coalesced row
 // reads, the contiguous access Eq. 3 prescribes), double-buffered through
-// registers. Each lane keeps its R x VJ block of C in registers for the whole
+// registers. A column-major operand (the paper's gamma_col layout) is read
+// along its contiguous extent and transposed on the way into the same
+// row-major LDS slab, so the k loop below is the same for every layout. Each lane keeps its R x VJ block of C in registers for the whole
 // k loop, so the k-sum of every element is the plain ascending sequence of
 // fma(A[i,k], B[k,j], acc) -- bitwise the paper's loop with fma.
 #include "moa_internal.h"
@@ -35,7 +37,8 @@ __global__ __launch_bounds__(256) void onf_kernel(const T *__restrict__ A,
                                                   T *__restrict__ C, int64_t m,
                                                   int64_t n, int64_t p,
                                                   int accumulate, int vec_a,
-                                                  int vec_b, int vec_c) {
+                                                  int vec_b, int vec_c, int a_col,
+                                                  int b_col) {
     using V = typename Vec<T>::type;
     constexpr int VW = Vec<T>::W;          // elements per 16-byte vector
     constexpr int TC = TN / VJ;            // lane column groups
@@ -84,7 +87,7 @@ __global__ __launch_bounds__(256) void onf_kernel(const T *__restrict__ A,
     V ra[A_PER], rb[B_PER];
     // whole blocks (inside m and p, the slab inside n, vector-aligned rows)
     // load without per-vector checks
-    const bool inner = i0 + TM <= m && j0 + TN <= p && vec_a && vec_b;
+    const bool inner = i0 + TM <= m && j0 + TN <= p && vec_a && vec_b && !a_col && !b_col;
     auto load_slab = [&](int64_t k0) {
         if (inner && k0 + BK <= n) {
 #pragma unroll
@@ -107,7 +110,7 @@ __global__ __launch_bounds__(256) void onf_kernel(const T *__restrict__ A,
             V val;
 #pragma unroll
             for (int e = 0; e < VW; ++e) ((T *)&val)[e] = T(0);
-            if (v < A_VECS) {
+            if (v < A_VECS && !a_col) {
                 const int row = v / (BK / VW);
                 const int kv = (v % (BK / VW)) * VW;
                 const int64_t i = i0 + row, k = k0 + kv;
@@ -120,6 +123,20 @@ __global__ __launch_bounds__(256) void onf_kernel(const T *__restrict__ A,
                             if (k + e < n) ((T *)&val)[e] = A[i * n + k + e];
                     }
                 }
+            } else if (v < A_VECS) {
+                // column-major A: element (i, k) at i + k m; a vector runs along i
+                const int kk = v / (TM / VW);
+                const int iv = (v % (TM / VW)) * VW;
+                const int64_t i = i0 + iv, k = k0 + kk;
+                if (k < n) {
+                    if (vec_a && i + VW <= m) {
+                        val = *reinterpret_cast<const V *>(A + k * m + i);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VW; ++e)
+                            if (i + e < m) ((T *)&val)[e] = A[k * m + i + e];
+                    }
+                }
             }
             ra[s] = val;
         }
@@ -129,7 +146,7 @@ __global__ __launch_bounds__(256) void onf_kernel(const T *__restrict__ A,
             V val;
 #pragma unroll
             for (int e = 0; e < VW; ++e) ((T *)&val)[e] = T(0);
-            if (v < B_VECS) {
+            if (v < B_VECS && !b_col) {
                 const int kk = v / (TN / VW);
                 const int jv = (v % (TN / VW)) * VW;
                 const int64_t k = k0 + kk, j = j0 + jv;
@@ -142,6 +159,20 @@ __global__ __launch_bounds__(256) void onf_kernel(const T *__restrict__ A,
                             if (j + e < p) ((T *)&val)[e] = B[k * p + j + e];
                     }
                 }
+            } else if (v < B_VECS) {
+                // column-major B: element (k, j) at k + j n; a vector runs along k
+                const int jj = v / (BK / VW);
+                const int kv = (v % (BK / VW)) * VW;
+                const int64_t j = j0 + jj, k = k0 + kv;
+                if (j < p) {
+                    if (vec_b && k + VW <= n) {
+                        val = *reinterpret_cast<const V *>(B + j * n + k);
+                    } else {
+#pragma unroll
+                        for (int e = 0; e < VW; ++e)
+                            if (k + e < n) ((T *)&val)[e] = B[j * n + k + e];
+                    }
+                }
             }
             rb[s] = val;
         }
@@ -150,19 +181,29 @@ __global__ __launch_bounds__(256) void onf_kernel(const T *__restrict__ A,
 #pragma unroll
         for (int s = 0; s < A_PER; ++s) {
             const int v = t + 256 * s;
-            if (v < A_VECS) {
+            if (v < A_VECS && !a_col) {
                 const int row = v / (BK / VW);
                 const int kv = (v % (BK / VW)) * VW;
                 *reinterpret_cast<V *>(&As[buf][row * LDA + kv]) = ra[s];
+            } else if (v < A_VECS) {           // transposed into the row-major slab
+                const int kk = v / (TM / VW);
+                const int iv = (v % (TM / VW)) * VW;
+#pragma unroll
+                for (int e = 0; e < VW; ++e) As[buf][(iv + e) * LDA + kk] = ((const T *)&ra[s])[e];
             }
         }
 #pragma unroll
         for (int s = 0; s < B_PER; ++s) {
             const int v = t + 256 * s;
-            if (v < B_VECS) {
+            if (v < B_VECS && !b_col) {
                 const int kk = v / (TN / VW);
                 const int jv = (v % (TN / VW)) * VW;
                 *reinterpret_cast<V *>(&Bs[buf][kk * TN + jv]) = rb[s];
+            } else if (v < B_VECS) {
+                const int jj = v / (BK / VW);
+                const int kv = (v % (BK / VW)) * VW;
+#pragma unroll
+                for (int e = 0; e < VW; ++e) Bs[buf][(kv + e) * TN + jj] = ((const T *)&rb[s])[e];
             }
         }
     };
@@ -268,12 +309,14 @@ hipError_t launch_one(const moa_gemm_desc &d, hipStream_t st) {
     const T *B = static_cast<const T *>(d.B);
     T *C = static_cast<T *>(d.C);
     constexpr int VW = Vec<T>::W;
-    const int vec_a = (d.n % VW == 0) && ((uintptr_t)A % 16 == 0);
-    const int vec_b = (d.p % VW == 0) && ((uintptr_t)B % 16 == 0);
+    const int a_col = (d.flags & MOA_FLAG_A_COL) != 0, b_col = (d.flags & MOA_FLAG_B_COL) != 0;
+    // 16-byte vectors run along the contiguous extent of each operand
+    const int vec_a = ((a_col ? d.m : d.n) % VW == 0) && ((uintptr_t)A % 16 == 0);
+    const int vec_b = ((b_col ? d.n : d.p) % VW == 0) && ((uintptr_t)B % 16 == 0);
     const int vec_c = (d.p % VW == 0) && ((uintptr_t)C % 16 == 0);
     dim3 grid((unsigned)((d.p + TN - 1) / TN), (unsigned)((d.m + TM - 1) / TM));
     hipLaunchKernelGGL((onf_kernel<T, TM, TN, BK, R, VJ>), grid, dim3(256), 0, st, A, B, C,
-                       d.m, d.n, d.p, d.accumulate, vec_a, vec_b, vec_c);
+                       d.m, d.n, d.p, d.accumulate, vec_a, vec_b, vec_c, a_col, b_col);
     return hipGetLastError();
 }
 

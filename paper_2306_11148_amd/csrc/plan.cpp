@@ -17,6 +17,8 @@
 #include <map>
 #include <mutex>
 
+#include <algorithm>
+
 #include "moa_internal.h"
 
 namespace moa {
@@ -127,6 +129,24 @@ static int64_t tiles_for(int64_t m, int64_t p, int tm, int tn) {
     return ((m + tm - 1) / tm) * ((p + tn - 1) / tn);
 }
 
+// Split-k chosen by the planner (MOA_FLAG_SPLIT_K absent): a product whose
+// 128 x 128 blocks leave most of the 256 CUs idle (at most 64 blocks) and
+// whose k walk is long (n >= 4096) gets about 512 workgroups, each summing
+// at least 512 k (measured on 256 x 65536 x 256, 512 x 32768 x 512 and
+// 1024 x 16384 x 1024: 3 to 12 times faster than one workgroup per block).
+static int auto_split_k(int64_t m, int64_t n, int64_t p) {
+    const int64_t tiles = tiles_for(m, p, 128, 128);
+    if (tiles > 64 || n < 4096) return 1;
+    int64_t c = (512 + tiles - 1) / tiles;
+    c = std::min<int64_t>(std::min<int64_t>(c, n / 512), 255);
+    return c >= 2 ? (int)c : 1;
+}
+
+static int split_k_of(const moa_gemm_desc &d, int64_t slabs) {
+    const int req = split_k_requested(d);
+    return split_k_chunks(req == 0 ? auto_split_k(d.m, d.n, d.p) : req, slabs);
+}
+
 moa_status make_plan(const moa_gemm_desc &d_in, Plan *out) {
     const moa_gemm_desc d = row_major_result(d_in);   // a column-major C is planned as C^T
     Plan pl;
@@ -168,11 +188,15 @@ moa_status make_plan(const moa_gemm_desc &d_in, Plan *out) {
         if (forced >= 0) {
             if (forced >= nv) return fail(MOA_ERR_INVALID, "variant %d out of range (MFMA_F32 has %d)", forced, nv);
             v = forced;
-        } else if ((v = tuned_variant(d, pl.path)) >= 0) {
+        } else if ((v = tuned_variant(d, pl.path)) >= 0 && !(has_col_operand(d) && v == mfma_f32_staged_variant())) {
             pl.tuned = true;
         } else {
             v = mfma_f32_default_variant(d.m, d.p);
         }
+        // the register-staged kernel reads row-major operands only; the ring
+        // variants condition a column-major operand with the other packer
+        if (v == mfma_f32_staged_variant() && has_col_operand(d))
+            return fail(MOA_ERR_UNSUPPORTED, "the register-staged FP32 variant takes row-major operands only");
         mfma_f32_shape(v, &pl);
         pl.workspace_bytes = mfma_f32_workspace_bytes(d.m, d.n, d.p, v);
         // the record ring's 32-bit offsets inside a row tile, as on split-BF16
@@ -194,7 +218,7 @@ moa_status make_plan(const moa_gemm_desc &d_in, Plan *out) {
         }
         split_bf16_shape(v, &pl);
         pl.workspace_bytes = split_bf16_workspace_bytes(d.m, d.n, d.p);
-        pl.split_k = split_k_chunks(split_k_requested(d), (d.n + 15) / 16);
+        pl.split_k = split_k_of(d, (d.n + 15) / 16);
         if (pl.split_k > 1) split_bf16_shape(0, &pl);   // split-k runs the first block variant
         // 256 record rows of (n/16) 64-byte records must stay below 2^31 bytes
         // (32-bit buffer offsets of one tile).
@@ -232,7 +256,7 @@ moa_status make_plan(const moa_gemm_desc &d_in, Plan *out) {
         }
         fp8_shape(two, v, &pl);
         pl.workspace_bytes = fp8_workspace_bytes(d.m, d.n, d.p, two);
-        pl.split_k = split_k_chunks(split_k_requested(d), (d.n + 63) / 64);
+        pl.split_k = split_k_of(d, (d.n + 63) / 64);
         if (pl.split_k > 1) fp8_shape(two, 0, &pl);     // split-k runs the first block variant
         // 256 record rows of (n/64) 64-byte records must stay below 2^31 bytes
         // (32-bit buffer offsets of one tile).

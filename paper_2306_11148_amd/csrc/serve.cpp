@@ -121,10 +121,11 @@ moa_status moa_serve_create(const moa_serve_cfg *cfg, moa_server **out) {
     try {
         if (!cfg || !out) return fail(MOA_ERR_INVALID, "null argument");
         *out = nullptr;
-        if (cfg->slots < 1 || cfg->max_group < 1 || cfg->hbm_budget_bytes <= 0 || cfg->batch_window_us < 0)
-            return fail(MOA_ERR_INVALID,
-                        "slots and max_group must be >= 1, the budget positive and the window not negative");
-        int ndev = 0;
+        if (cfg->slots < 1 || cfg->max_group < 1 || cfg->hbm_budget_bytes <= 0 || cfg->batch_window_us < 0 ||
+            cfg->pool_reserve_bytes < 0 || cfg->pool_reserve_bytes > cfg->hbm_budget_bytes)
+            return fail(MOA_ERR_INVALID, "slots and max_group must be >= 1, the budget positive, the window not "
+                                         "negative and the reserve within the budget");
+        int ndev = 0, prev = 0;
         hipError_t e = hipGetDeviceCount(&ndev);
         if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
         if (cfg->device < 0 || cfg->device >= ndev) return fail(MOA_ERR_INVALID, "no device %d", cfg->device);
@@ -134,7 +135,16 @@ moa_status moa_serve_create(const moa_serve_cfg *cfg, moa_server **out) {
             delete srv;
             return s;
         }
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(cfg->device);       // the reserve is allocated on the server's device
         srv->server.reset(new serve::Server(*cfg, &srv->backend));
+        (void)hipSetDevice(prev);
+        if (!srv->server->reserved()) {
+            const long long want = (long long)cfg->pool_reserve_bytes;
+            srv->server.reset();
+            delete srv;
+            return fail(MOA_ERR_NOMEM, "pool reserve of %lld bytes", want);
+        }
         *out = srv;
         return MOA_OK;
     } catch (...) {

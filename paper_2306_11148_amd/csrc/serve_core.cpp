@@ -60,6 +60,21 @@ void *Pool::alloc(int64_t bytes) {
     return carve(chunks_.size() - 1, bytes);
 }
 
+bool Pool::reserve(int64_t bytes) {
+    bytes = align256(bytes);
+    if (bytes <= 0) return true;
+    if (total_ + bytes > cap_) return false;
+    char *base = static_cast<char *>(b_->device_alloc(bytes));
+    if (!base) return false;
+    Chunk ch;
+    ch.base = base;
+    ch.size = bytes;
+    ch.free.emplace(0, bytes);
+    chunks_.push_back(std::move(ch));
+    total_ += bytes;
+    return true;
+}
+
 void Pool::release(void *p) {
     if (!p) return;
     auto it = blocks_.find(p);
@@ -94,6 +109,8 @@ void Pool::trim() {
 
 Server::Server(const moa_serve_cfg &cfg, Backend *b)
     : cfg_(cfg), b_(b), pool_(b, cfg.hbm_budget_bytes), slots_((size_t)cfg.slots) {
+    reserved_ = pool_.reserve(cfg.pool_reserve_bytes);
+    peak_pool_ = pool_.chunk_bytes();
     sched_ = std::thread([this] { run(); });
 }
 

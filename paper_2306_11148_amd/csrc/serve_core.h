@@ -75,6 +75,7 @@ class Pool {
     Pool(const Pool &) = delete;
     Pool &operator=(const Pool &) = delete;
     void *alloc(int64_t bytes);          // nullptr if no block can be found or added
+    bool reserve(int64_t bytes);         // one chunk of `bytes` now (within the cap)
     void release(void *p);
     void trim();                         // with no live block: every chunk back to the backend
     int64_t live_bytes() const { return live_; }
@@ -96,8 +97,10 @@ class Pool {
 
 class Server {
   public:
+    // reserves cfg.pool_reserve_bytes (reserved() says whether that worked)
     Server(const moa_serve_cfg &cfg, Backend *b);
     ~Server();                           // waits for every submitted request, then stops
+    bool reserved() const { return reserved_; }
     Server(const Server &) = delete;
     Server &operator=(const Server &) = delete;
 
@@ -158,6 +161,7 @@ class Server {
     int64_t held_ = 0, peak_held_ = 0, peak_pool_ = 0;
     int64_t outstanding_ = 0, admitted_ = 0, completed_ = 0, failed_ = 0;
     bool trimmed_ = false;
+    bool reserved_ = true;
     bool stop_ = false;
     std::thread sched_;
 };

@@ -234,32 +234,211 @@ ring::Operands split_operands(const uint8_t *Ap, const uint8_t *Bp, float *C, in
 // Independent products share one launch. Members are listed longest k walk
 // first; their tiles form one work list (member g owns tile ids
 // [first[g], first[g+1])), and persistent workgroups claim tile ids from an
-// atomic counter until the list is exhausted. Every element of every member
-// receives exactly the operation sequence of the single-product kernel (the
-// per-element order depends only on the slab walk, not on the block shape),
-// so grouped and single results are bitwise equal.
+// atomic counter until the list is exhausted.
+//
+// Grouped members skip the conditioning pass: a tile streams the FP32 slabs
+// of its rows of A and columns of B straight from memory into an LDS ring
+// (direct loads, as the record ring does with records) and splits them into
+// hi/lo BF16 fragments in registers when it reads them (split_pair, as the
+// conditioning kernels do). Every element of every member receives exactly
+// the operation sequence of the single-product kernel -- the same hi/lo
+// values, zero past n, the same matrix-core steps slab by slab -- so grouped
+// and single results are bitwise equal.
+//
+// LDS stage of one slab (16 k):
+//   A: BM rows of 64 bytes (16 FP32), 16-byte chunk c of row r at physical
+//      chunk c ^ ((r / 4) mod 4) (the record ring's swizzle);
+//   B: the slab's 16 rows of BN FP32, loaded in pairs (k, k + 8) per KiB: row
+//      k at bytes [0, 4 BN) of pair k mod 8, row k + 8 at [4 BN, 8 BN) rotated
+//      by 128 bytes, so that the two halves of a wave (k and k + 8 of the same
+//      columns) read disjoint banks.
 struct GroupMember {
-    ring::Operands op;                  // the contraction's view (read by ring::tile in place)
     const float *A, *B;
     float *C;
-    uint8_t *Ap, *Bp;                   // records of this member in the workspace
     int64_t m, n, p, S;
     int64_t first_tile;                 // first contraction work-list id of this member
-    int64_t pack_first;                 // first conditioning work-list id of this member
     int32_t tiles_n, accumulate;
-    int32_t row_items;                  // conditioning items: row_items chunk blocks of A,
-    int32_t col_blocks_x;               // then col_blocks_x * ceil(S/4) 64 x 64 blocks of B
 };
 
+template <int BM, int BN, int WM, int WN, int NST>
+struct RawCfg {
+    static constexpr int WAVES_N = BN / WN, NW = (BM / WM) * WAVES_N;
+    static constexpr int FM = WM / 32, FN = WN / 32;
+    static constexpr int A_BYTES = BM * 64, B_BYTES = SLAB * BN * 4;
+    static constexpr int STAGE = A_BYTES + B_BYTES;
+    static constexpr int LOADS = STAGE / 1024;            // KiB direct loads per slab
+    static constexpr int LPW = LOADS / NW;
+    static constexpr int LDS = NST * STAGE;
+    static_assert(NW == 4 && BN == 128 && BM % 16 == 0 && LOADS % NW == 0, "shape of the raw ring");
+};
 
-template <int BM, int BN, int WM, int WN>
-__global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, 3) void split_grouped_kernel(
-    const GroupMember *__restrict__ g, const int32_t *__restrict__ tile_owner, int64_t total_tiles,
-    unsigned long long *__restrict__ counter) {
-    __shared__ __attribute__((aligned(1024))) uint8_t lds[ring::Cfg<BM, BN, WM, WN, 1>::LDS];
+// 8 FP32 values -> hi and lo BF16 fragments
+__device__ __forceinline__ void split8(const float (&x)[8], bf16x8_t &hi, bf16x8_t &lo) {
+    uint4 h, l;
+    split_pair(x[0], x[1], &h.x, &l.x);
+    split_pair(x[2], x[3], &h.y, &l.y);
+    split_pair(x[4], x[5], &h.z, &l.z);
+    split_pair(x[6], x[7], &h.w, &l.w);
+    hi = __builtin_bit_cast(bf16x8_t, h);
+    lo = __builtin_bit_cast(bf16x8_t, l);
+}
+
+template <int BM, int BN, int WM, int WN, int NST>
+__device__ __forceinline__ void raw_tile(const GroupMember &d, int64_t i0, int64_t j0, uint8_t *lds) {
+    using G = RawCfg<BM, BN, WM, WN, NST>;
+    constexpr int FM = G::FM, FN = G::FN, STAGE = G::STAGE, LPW = G::LPW;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wm = wave / G::WAVES_N, wn = wave % G::WAVES_N;
+    const int L = (int)d.S;
+    const int64_t n = d.n, p = d.p;
+
+    // A: one resource over the tile's live rows; lane offsets advance by 64
+    // bytes per slab. Rows past m and k past the last live row's end are out
+    // of range (zeros); k past n inside earlier rows reads the next row and is
+    // masked when split.
+    const int64_t rows_live = d.m - i0 < BM ? d.m - i0 : BM;
+    const int64_t a_range = rows_live * n * 4;
+    const __amdgpu_buffer_rsrc_t a_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(d.A + i0 * n), (short)0, (int)(a_range < 0x7FFFFFFF ? a_range : 0x7FFFFFFF), 0x00020000);
+    const float *b_tile = d.B + j0;
+    const int64_t b_total = n * p - j0;                  // elements from b_tile to the end of B
+
+    auto issue = [&](int s) {
+        uint8_t *buf = lds + (s % NST) * STAGE;
+        const int64_t k0 = (int64_t)s * SLAB;
+#pragma unroll
+        for (int q = 0; q < LPW; ++q) {
+            const int g = wave * LPW + q;                // wave-uniform load index
+            if (g < BM / 16) {
+                const int r = 16 * g + (lane >> 2);
+                const int c = (lane & 3) ^ ((lane >> 4) & 3);
+                const int voff = r < rows_live ? (int)(((int64_t)r * n + k0 + 4 * c) * 4) : ring::kDeadVoffset;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(a_rsrc, (ring::lds_void_t *)(buf + g * 1024), 16, voff,
+                                                         0, 0, 0);
+            } else {
+                const int h = g - BM / 16;               // pair h: rows h and h + 8 of the slab
+                const int upper = lane >> 5;
+                const int gc = upper ? ((lane & 31) + 8) & 31 : lane & 31;
+                const int64_t rel = (k0 + h + 8 * upper) * p + 4 * gc;
+                const int64_t left = b_total - k0 * p;   // elements from row k0 on
+                const __amdgpu_buffer_rsrc_t b_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+                    (void *)(b_tile + k0 * p), (short)0,
+                    (int)(left * 4 < 0x7FFFFFFF ? (left > 0 ? left * 4 : 0) : 0x7FFFFFFF), 0x00020000);
+                const int voff = (int)((rel - k0 * p) * 4);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(b_rsrc, (ring::lds_void_t *)(buf + G::A_BYTES + h * 1024),
+                                                         16, voff, 0, 0, 0);
+            }
+        }
+    };
+
+    const int frow = lane & 31, fhalf = lane >> 5;
+    float ra[FM][8], rb[FN][8];
+    // raw fragments of slab s: A rows (8 k of half fhalf), B columns (8 k rows)
+    auto read_raw = [&](int s) {
+        const uint8_t *buf = lds + (s % NST) * STAGE;
+#pragma unroll
+        for (int a = 0; a < FM; ++a) {
+            const int r = wm * WM + a * 32 + frow;
+            const int sw = (r >> 2) & 3;
+            const float4 lo4 = *reinterpret_cast<const float4 *>(buf + r * 64 + (((2 * fhalf) ^ sw) << 4));
+            const float4 hi4 = *reinterpret_cast<const float4 *>(buf + r * 64 + (((2 * fhalf + 1) ^ sw) << 4));
+            ra[a][0] = lo4.x; ra[a][1] = lo4.y; ra[a][2] = lo4.z; ra[a][3] = lo4.w;
+            ra[a][4] = hi4.x; ra[a][5] = hi4.y; ra[a][6] = hi4.z; ra[a][7] = hi4.w;
+        }
+        const uint8_t *bb = buf + G::A_BYTES;
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+            const int cb = wn * WN + b * 32 + frow;
+            const int off = fhalf ? 512 + ((((cb >> 2) + 24) & 31) << 4) + ((cb & 3) << 2) : cb << 2;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) rb[b][e] = *reinterpret_cast<const float *>(bb + e * 1024 + off);
+        }
+    };
+    SplitMode::Frags<FM, FN> f;
+    // split into fragments; k past n (the last slab) counts as zero
+    auto convert = [&](int s) {
+        const int64_t kb = (int64_t)s * SLAB + 8 * fhalf;
+        if (kb + 8 > n) {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                if (kb + e >= n) {
+#pragma unroll
+                    for (int a = 0; a < FM; ++a) ra[a][e] = 0.0f;
+#pragma unroll
+                    for (int b = 0; b < FN; ++b) rb[b][e] = 0.0f;
+                }
+        }
+#pragma unroll
+        for (int a = 0; a < FM; ++a) split8(ra[a], f.ah[a], f.al[a]);
+#pragma unroll
+        for (int b = 0; b < FN; ++b) split8(rb[b], f.bh[b], f.bl[b]);
+    };
+
+    f32x16_t acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = f32x16_t{};
+
+    auto wait_loads = [&](int stages) {
+        switch (stages <= 0 ? 0 : stages >= 2 ? 2 : stages) {
+        case 0: __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(0)); break;
+        case 1: __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(LPW)); break;
+        default: __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(2 * LPW)); break;
+        }
+    };
+    static_assert(NST >= 3 && NST <= 4, "up to two slabs in flight");
+
+    if (L > 0) {
+        for (int q = 0; q < NST - 1; ++q)
+            if (q < L) issue(q);
+        wait_loads(min(NST - 2, L - 1));
+        ring::ring_barrier();
+        read_raw(0);
+        convert(0);
+        for (int s = 0; s < L; ++s) {
+            if (s + 1 < L) {
+                // slab s + 1 landed in every wave; the buffer of slab s - 1 is free
+                wait_loads(min(NST - 3, L - s - 2));
+                ring::ring_barrier();
+                if (s + NST - 1 < L) issue(s + NST - 1);
+                read_raw(s + 1);
+            }
+            SplitMode::mma<FM, FN>(f, acc);
+            if (s + 1 < L) convert(s + 1);
+        }
+    }
+    __syncthreads();                    // every wave done with the ring before the next tile's loads
+
+    ring::global_f32 *C = (ring::global_f32 *)d.C;
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+            const int64_t j = j0 + wn * WN + b * 32 + (lane & 31);
+            if (j >= p) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t i = i0 + wm * WM + a * 32 + mfma32_row(r, lane);
+                if (i < d.m) {
+                    float v = acc[a][b][r];
+                    if (d.accumulate) v += C[i * p + j];
+                    C[i * p + j] = v;
+                }
+            }
+        }
+}
+
+template <int BM, int BN, int WM, int WN, int NST>
+__global__ __launch_bounds__(256, 2) void split_grouped_kernel(const GroupMember *__restrict__ g,
+                                                               const int32_t *__restrict__ tile_owner,
+                                                               int64_t total_tiles,
+                                                               unsigned long long *__restrict__ counter) {
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[RawCfg<BM, BN, WM, WN, NST>::LDS];
     __shared__ int64_t s_tile;
     for (;;) {
-        __syncthreads();                // nobody still reads lds or s_tile
+        __syncthreads();                // nobody still reads s_tile
         if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(counter, 1ull);
         __syncthreads();
         const int64_t tile = s_tile;
@@ -268,34 +447,8 @@ __global__ __launch_bounds__((BM / WM) * (BN / WN) * 64, 3) void split_grouped_k
         const GroupMember &d = g[k];
         const int64_t local = tile - d.first_tile;
         const int64_t tm = local / d.tiles_n, tn = local - tm * d.tiles_n;
-        ring::tile<BM, BN, WM, WN, 1, SplitMode>(d.op, __builtin_amdgcn_readfirstlane((int)tm) * (int64_t)BM,
-                                                 __builtin_amdgcn_readfirstlane((int)tn) * (int64_t)BN, lds);
-    }
-}
-
-// Grouped conditioning: one work list over every member, each member
-// contributing row items (256 chunks of A each) followed by 64-column x 64-k
-// blocks of B; workgroups stride through the list, so large and small members
-// share the machine evenly. item_owner[item] names the member (a table built
-// on the host: one load instead of a search through the member list).
-constexpr int PACK_ROW_ITEM = 256;      // chunks per row item (one per thread)
-
-__global__ __launch_bounds__(256) void grouped_pack_kernel(const GroupMember *__restrict__ g,
-                                                           const int32_t *__restrict__ item_owner, int64_t total) {
-    __shared__ __attribute__((aligned(16))) float tile[4 * SLAB][64 + 4];
-    for (int64_t item = blockIdx.x; item < total; item += gridDim.x) {
-        const int k = __builtin_amdgcn_readfirstlane(item_owner[item]);
-        const GroupMember &d = g[k];
-        const int64_t local = item - d.pack_first;
-        if (local < d.row_items) {
-            const int vec = (d.n % 8 == 0) && ((uintptr_t)d.A % 16 == 0);
-            const int64_t q = local * PACK_ROW_ITEM + threadIdx.x;
-            if (q < padded_rows(d.m) * d.S * 2) pack_rows_chunk(d.A, d.m, d.n, d.S, vec, d.Ap, q);
-        } else {
-            const int vec = (d.p % 4 == 0) && ((uintptr_t)d.B % 16 == 0);
-            const int64_t b = local - d.row_items;
-            pack_cols_block(d.B, d.n, d.p, d.S, d.Bp, b % d.col_blocks_x, b / d.col_blocks_x, tile, vec);
-        }
+        raw_tile<BM, BN, WM, WN, NST>(d, __builtin_amdgcn_readfirstlane((int)tm) * (int64_t)BM,
+                                      __builtin_amdgcn_readfirstlane((int)tn) * (int64_t)BN, lds);
     }
 }
 
@@ -432,89 +585,75 @@ hipError_t launch_split_bf16(const moa_gemm_desc &d, const Plan &plan, void *ws,
 
 namespace {
 __global__ void zero_u64_kernel(unsigned long long *x) { *x = 0ull; }
-constexpr int GB_M = 128, GB_N = 128, GW_M = 64, GW_N = 64;   // grouped block shape
+constexpr int GB_M = 128, GB_N = 128, GW_M = 64, GW_N = 64, G_NST = 4;   // grouped block shape, ring depth
 int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
-}  // namespace
 
-namespace {
-// Tiles and conditioning items of a member list (independent of the order).
+// Contraction tiles of a member list (independent of the order).
 GroupedWork grouped_counts(const moa_gemm_desc *const *members, int count) {
     GroupedWork w{0, 0};
     for (int k = 0; k < count; ++k) {
         const moa_gemm_desc &d = *members[k];
-        const int64_t S = (d.n + SLAB - 1) / SLAB;
         w.tiles += ((d.m + GB_M - 1) / GB_M) * ((d.p + GB_N - 1) / GB_N);
-        w.pack_items += (padded_rows(d.m) * S * 2 + PACK_ROW_ITEM - 1) / PACK_ROW_ITEM + ((d.p + 63) / 64) * ((S + 3) / 4);
     }
     return w;
 }
-// Member table, then tile -> member and item -> member tables (int32).
+// Member table, then the tile -> member table (int32).
 int64_t table_bytes(int count, const GroupedWork &w) {
-    return align256((int64_t)count * (int64_t)sizeof(GroupMember)) + align256(4 * w.tiles) + align256(4 * w.pack_items);
+    return align256((int64_t)count * (int64_t)sizeof(GroupMember)) + align256(4 * w.tiles);
 }
 }  // namespace
+
+// The raw ring addresses a tile's rows of A with 32-bit offsets (128 rows of
+// n FP32) and a slab of B likewise (16 rows of p FP32).
+bool split_grouped_fits(const moa_gemm_desc &d) {
+    return ((int64_t)GB_M + 1) * d.n * 4 < 0x7FFFFFFF && ((int64_t)SLAB + 1) * d.p * 4 < 0x7FFFFFFF;
+}
 
 int64_t split_grouped_desc_bytes(const moa_gemm_desc *const *members, int count) {
     return table_bytes(count, grouped_counts(members, count));
 }
 
 int64_t split_grouped_workspace_bytes(const moa_gemm_desc *const *members, int count) {
-    int64_t b = 256 + split_grouped_desc_bytes(members, count);
-    for (int k = 0; k < count; ++k)
-        b += align256(split_bf16_workspace_bytes(members[k]->m, members[k]->n, members[k]->p));
-    return b;
+    return 256 + split_grouped_desc_bytes(members, count);
 }
 
 // Lays out the members (longest k walk first: the tail of the work list holds
-// the cheapest tiles) in `host_staging` and the workspace; returns the tile
-// count. The device member array is at ws + 256, the claim counter at ws.
+// the cheapest tiles) in `host_staging`; returns the tile count. The device
+// member array is at ws + 256, the claim counter at ws.
 GroupedWork split_grouped_layout(const moa_gemm_desc *const *members, int count, void *ws,
                                  void *host_staging) {
+    (void)ws;
     std::vector<int> order(count);
     for (int k = 0; k < count; ++k) order[k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
         return members[a]->n > members[b]->n;
     });
-    const GroupedWork totals = grouped_counts(members, count);
-    char *base = static_cast<char *>(ws);
-    char *rec = base + 256 + table_bytes(count, totals);
     GroupMember *h = static_cast<GroupMember *>(host_staging);
     int32_t *tile_owner = reinterpret_cast<int32_t *>(static_cast<char *>(host_staging) +
                                                       align256((int64_t)count * (int64_t)sizeof(GroupMember)));
-    int32_t *item_owner = tile_owner + align256(4 * totals.tiles) / 4;
-    int64_t tiles = 0, items = 0;
+    int64_t tiles = 0;
     for (int q = 0; q < count; ++q) {
         const moa_gemm_desc &d = *members[order[q]];
-        GroupMember g;
+        GroupMember g{};
         g.A = static_cast<const float *>(d.A);
         g.B = static_cast<const float *>(d.B);
         g.C = static_cast<float *>(d.C);
         g.m = d.m; g.n = d.n; g.p = d.p;
         g.S = (d.n + SLAB - 1) / SLAB;
-        g.Ap = reinterpret_cast<uint8_t *>(rec);
-        g.Bp = g.Ap + ring::array_bytes(d.m, g.S);
-        rec += align256(split_bf16_workspace_bytes(d.m, d.n, d.p));
-        g.op = split_operands(g.Ap, g.Bp, g.C, d.m, d.p, g.S, d.accumulate);
         g.first_tile = tiles;
         g.tiles_n = (int32_t)((d.p + GB_N - 1) / GB_N);
         g.accumulate = d.accumulate;
         const int64_t mt = ((d.m + GB_M - 1) / GB_M) * g.tiles_n;
         for (int64_t t = 0; t < mt; ++t) tile_owner[tiles + t] = q;
         tiles += mt;
-        g.pack_first = items;
-        g.row_items = (int32_t)((padded_rows(d.m) * g.S * 2 + PACK_ROW_ITEM - 1) / PACK_ROW_ITEM);
-        g.col_blocks_x = (int32_t)((d.p + 63) / 64);
-        const int64_t mi = g.row_items + (int64_t)g.col_blocks_x * ((g.S + 3) / 4);
-        for (int64_t t = 0; t < mi; ++t) item_owner[items + t] = q;
-        items += mi;
         h[q] = g;
     }
-    return {tiles, items};
+    return {tiles, 0};
 }
 
-// The device part of a grouped launch: reset the claim counter, condition
-// every member, run the persistent contraction. Contains no allocation, copy
-// or memset, so it can be captured in a graph and replayed.
+// The device part of a grouped launch: reset the claim counter, run the
+// persistent contraction. Contains no allocation, copy or memset, so it can
+// be captured in a graph and replayed.
 hipError_t split_grouped_enqueue(void *ws, int count, const GroupedWork &work, hipStream_t st) {
     const int64_t tiles = work.tiles;
     char *base = static_cast<char *>(ws);
@@ -522,20 +661,12 @@ hipError_t split_grouped_enqueue(void *ws, int count, const GroupedWork &work, h
     const GroupMember *dev_members = reinterpret_cast<const GroupMember *>(base + 256);
     const int32_t *tile_owner = reinterpret_cast<const int32_t *>(
         base + 256 + align256((int64_t)count * (int64_t)sizeof(GroupMember)));
-    const int32_t *item_owner = tile_owner + align256(4 * tiles) / 4;
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, st, counter);
-    if (work.pack_items > 0) {
-        TraceScope ts(MOA_K_SPLIT_PACK, st);
-        const int64_t g = std::min<int64_t>(work.pack_items, 8 * kNumCUs);
-        hipLaunchKernelGGL(grouped_pack_kernel, dim3((unsigned)g), dim3(256), 0, st, dev_members, item_owner,
-                           work.pack_items);
-    }
-    const int64_t grid = std::min<int64_t>(tiles, 3 * kNumCUs);   // three 48 KiB-LDS blocks per CU
+    const int64_t grid = std::min<int64_t>(tiles, 2 * kNumCUs);   // two blocks per CU
     TraceScope ts(MOA_K_SPLIT_GROUPED, st);
     if (grid > 0)
-        hipLaunchKernelGGL((split_grouped_kernel<GB_M, GB_N, GW_M, GW_N>), dim3((unsigned)grid),
-                           dim3(ring::Cfg<GB_M, GB_N, GW_M, GW_N, 1>::THREADS), 0, st, dev_members, tile_owner,
-                           tiles, counter);
+        hipLaunchKernelGGL((split_grouped_kernel<GB_M, GB_N, GW_M, GW_N, G_NST>), dim3((unsigned)grid), dim3(256),
+                           0, st, dev_members, tile_owner, tiles, counter);
     return hipGetLastError();
 }
 

@@ -64,7 +64,7 @@ class moa_plan_info(ctypes.Structure):
 class moa_serve_cfg(ctypes.Structure):
     _fields_ = [("hbm_budget_bytes", ctypes.c_int64), ("slots", ctypes.c_int32),
                 ("max_group", ctypes.c_int32), ("device", ctypes.c_int32),
-                ("batch_window_us", ctypes.c_int32)]
+                ("batch_window_us", ctypes.c_int32), ("pool_reserve_bytes", ctypes.c_int64)]
 
 
 class moa_synth_request(ctypes.Structure):
@@ -294,9 +294,9 @@ def moa_error_norm(X, R, out, stream=None):
 # ------------------------------------------------------------------ serving --
 
 def moa_serve_create(hbm_budget_bytes: int, slots: int = 4, max_group: int = 16, device: int = 0,
-                     batch_window_us: int = 0):
+                     batch_window_us: int = 0, pool_reserve_bytes: int = 0):
     """Start a server; returns an opaque handle (int)."""
-    cfg = moa_serve_cfg(hbm_budget_bytes, slots, max_group, device, batch_window_us)
+    cfg = moa_serve_cfg(hbm_budget_bytes, slots, max_group, device, batch_window_us, pool_reserve_bytes)
     h = ctypes.c_void_p()
     _check(lib().moa_serve_create(ctypes.byref(cfg), ctypes.byref(h)), "moa_serve_create")
     return h.value

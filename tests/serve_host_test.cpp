@@ -39,6 +39,7 @@ struct Fake final : Backend {
     std::mutex mu;
     int64_t device_cap = int64_t(1) << 40;   // bytes the fake device can hand out
     int64_t device_used = 0;
+    int device_allocs = 0;
     std::map<char *, int64_t> chunks;         // live device allocations
     int64_t scratch_per_member = 256;         // scratch model: this + 4 m p per member
     struct SlotState {
@@ -65,6 +66,7 @@ struct Fake final : Backend {
         if (!p) return nullptr;
         chunks[p] = bytes;
         device_used += bytes;
+        ++device_allocs;
         return p;
     }
     void device_free(void *p) override {
@@ -378,6 +380,34 @@ void test_batching_window() {
     std::printf("ok batching_window\n");
 }
 
+void test_pool_reserve() {
+    {
+        Fake f(2);
+        moa_serve_cfg c = cfg(int64_t(64) << 20, 2, 4);
+        c.pool_reserve_bytes = int64_t(8) << 20;
+        Server s(c, &f);
+        CHECK(s.reserved() && f.device_allocs == 1 && f.device_used == (int64_t(8) << 20), "reserve taken at creation");
+        std::vector<uint64_t> t(12);
+        for (int k = 0; k < 12; ++k) s.submit_synthetic(synth(32, 48, 40, k), &t[k]);
+        s.drain();
+        for (uint64_t x : t) {
+            CHECK(info_of(s, x).status == MOA_OK, "served");
+            s.release(x);
+        }
+        CHECK(f.device_allocs == 1, "no allocation while serving within the reserve: %d", f.device_allocs);
+        CHECK(f.errors.empty(), "%s", f.errors.empty() ? "" : f.errors[0].c_str());
+    }
+    {
+        Fake f(1);
+        f.device_cap = int64_t(1) << 20;
+        moa_serve_cfg c = cfg(int64_t(64) << 20, 1, 1);
+        c.pool_reserve_bytes = int64_t(8) << 20;
+        Server s(c, &f);
+        CHECK(!s.reserved(), "a reserve the device cannot give is reported");
+    }
+    std::printf("ok pool_reserve\n");
+}
+
 void test_ticket_errors() {
     Fake f(1);
     f.hold = true;
@@ -410,6 +440,7 @@ int main() {
     test_release_frees_budget_for_waiting_requests();
     test_batching_window();
     test_ticket_errors();
+    test_pool_reserve();
     if (g_failures) {
         std::printf("%d failure(s)\n", g_failures);
         return 1;

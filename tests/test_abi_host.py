@@ -124,7 +124,7 @@ def test_split_k_plan():
     """Split-k: chunks clamped so none is empty, partials in the workspace,
     one workgroup per (block, chunk), first block variant; ring paths only."""
     S16 = moa.MOA_PATH_SPLIT_BF16
-    base = moa.moa_plan_query(_desc(100, 20000, 100, path=S16))
+    base = moa.moa_plan_query(_desc(100, 20000, 100, path=S16, flags=moa.MOA_FLAG_SPLIT_K(1)))
     q = moa.moa_plan_query(_desc(100, 20000, 100, path=S16, flags=moa.MOA_FLAG_SPLIT_K(8)))
     assert base["split_k"] == 1 and q["split_k"] == 8
     assert q["workgroups"] == 8 * base["workgroups"] and q["tile_m"] == 128
@@ -139,6 +139,27 @@ def test_split_k_plan():
     assert call(_desc(8, 8, 8, moa.MOA_F32, moa.MOA_PATH_ONF, flags=moa.MOA_FLAG_SPLIT_K(2))) == \
         moa.MOA_ERR_UNSUPPORTED
     assert call(_desc(8, 8, 8, flags=1 << 28)) == moa.MOA_ERR_INVALID
+
+
+def test_split_k_chosen_by_the_planner():
+    """Without MOA_FLAG_SPLIT_K the planner splits products of at most 64
+    blocks of 128 x 128 with n >= 4096 into about 512 workgroups of at least
+    512 k each; MOA_FLAG_SPLIT_K(1) keeps them whole."""
+    S16, F8 = moa.MOA_PATH_SPLIT_BF16, moa.MOA_PATH_FP8_SCALED
+    q = lambda m, n, p, path=S16, fl=0: moa.moa_plan_query(_desc(m, n, p, path=path, flags=fl))  # noqa: E731
+    assert q(256, 65536, 256)["split_k"] == 128                  # 4 blocks: 512 / 4, n / 512 = 128
+    assert q(512, 32768, 512)["split_k"] == 32                   # 16 blocks
+    assert q(1024, 16384, 1024)["split_k"] == 8                  # 64 blocks
+    assert q(1024, 16384, 1024)["workgroups"] == 512
+    assert q(100, 20000, 100)["split_k"] == 38                   # 39 asked: 1250 slabs in chunks of 33
+    assert q(128, 4096, 128)["split_k"] == 8                     # capped by n / 512
+    assert q(1152, 16384, 1024)["split_k"] == 1                  # 72 blocks: enough to spread
+    assert q(256, 4095, 256)["split_k"] == 1                     # short k walk
+    assert q(256, 65536, 256, fl=moa.MOA_FLAG_SPLIT_K(1))["split_k"] == 1
+    assert q(256, 65536, 256, fl=moa.MOA_FLAG_SPLIT_K(3))["split_k"] == 3
+    assert q(256, 65536, 256, path=F8)["split_k"] == 128         # FP8: the same rule (its slabs are 64 k)
+    assert q(256, 65536, 256, path=moa.MOA_PATH_ONF)["split_k"] == 1
+    assert q(256, 65536, 256, path=moa.MOA_PATH_MFMA_F32)["split_k"] == 1
 
 
 def test_size_limits_at_the_boundary():
@@ -181,14 +202,25 @@ def test_mfma_f32_plan_variants():
 
 
 def test_layout_flags():
-    """gamma_col operands: any combination on the ring paths, all-or-nothing on
-    ONF / FP32 matrix cores; make_desc reads the layout from the strides."""
+    """gamma_col operands: any combination on every path except the
+    register-staged FP32 variant (row-major only); make_desc reads the layout
+    from the strides."""
     import torch
     F32 = moa.MOA_F32
     allcol = moa.MOA_FLAG_A_COL | moa.MOA_FLAG_B_COL | moa.MOA_FLAG_C_COL
-    assert call(_desc(8, 8, 8, F32, moa.MOA_PATH_ONF, flags=moa.MOA_FLAG_A_COL)) == moa.MOA_ERR_UNSUPPORTED
-    assert call(_desc(8, 8, 8, F32, moa.MOA_PATH_MFMA_F32, flags=moa.MOA_FLAG_C_COL)) == moa.MOA_ERR_UNSUPPORTED
-    assert moa.moa_plan_query(_desc(8, 8, 8, F32, moa.MOA_PATH_ONF, flags=allcol))["path"] == moa.MOA_PATH_ONF
+    for f in range(8):
+        for path in (moa.MOA_PATH_ONF, moa.MOA_PATH_MFMA_F32):
+            assert moa.moa_plan_query(_desc(8, 8, 8, F32, path, flags=f << 24))["path"] == path
+        assert moa.moa_plan_query(_desc(8, 8, 8, moa.MOA_F64, moa.MOA_PATH_ONF, flags=f << 24))["path"] == 1
+    staged = moa.MOA_FLAG_VARIANT(2)
+    assert moa.moa_plan_query(_desc(8, 8, 8, F32, moa.MOA_PATH_MFMA_F32, flags=staged))["workspace_bytes"] == 0
+    # all-column: C^T = B^T A^T is all row-major, so the staged kernel serves it
+    assert moa.moa_plan_query(_desc(8, 8, 8, F32, moa.MOA_PATH_MFMA_F32, flags=staged | allcol))["variant"] == 2
+    for f in (moa.MOA_FLAG_A_COL, moa.MOA_FLAG_B_COL, moa.MOA_FLAG_C_COL):
+        with pytest.raises(moa.MoaError) as ei:
+            moa.moa_plan_query(_desc(8, 8, 8, F32, moa.MOA_PATH_MFMA_F32, flags=staged | f))
+        assert ei.value.status == moa.MOA_ERR_UNSUPPORTED
+        assert call(_desc(8, 8, 8, F32, moa.MOA_PATH_MFMA_F32, flags=staged | f)) == moa.MOA_ERR_UNSUPPORTED
     for f in range(8):
         q = moa.moa_plan_query(_desc(100, 300, 2000, F32, moa.MOA_PATH_SPLIT_BF16, flags=f << 24))
         assert q["workgroups"] == 16

@@ -124,9 +124,21 @@ def test_grouped_batching_workload_full_size():
     assert worst <= 1e-5, worst
 
 
+def _oracle_check(A, B, got, path, fl=0):
+    """A member's result against the CPU oracle at its path's bar."""
+    if path == "onf":
+        assert np.array_equal(got, O.gemm_f32_fma(A, B))
+    elif path == "fp8":
+        Q = O.fp8_gemm(A, B) if fl == moa.MOA_FLAG_FP8_ONE_TERM else O.fp8_gemm_2term(A, B)
+        assert O.rel_err(got, Q) <= 1e-4
+    else:
+        assert O.rel_err(got, O.gemm_f64(A.astype(np.float64), B.astype(np.float64))) <= 1e-5
+
+
 def test_prepared_group_graph_replays_match_single_launches():
     """Captured once, replayed three times with eager work and synchronisation
-    in between; every replay is checked against single launches."""
+    in between; every replay is checked against single launches and every
+    member against the CPU oracle."""
     shapes = inputs.grouped_shapes(18, lo=3, hi=400, seed=31)
     ops = inputs.grouped_operands(shapes, seed=31)
     paths = ["split_bf16"] * 14 + ["onf", "mfma_f32", "onf", "split_bf16"]
@@ -149,13 +161,16 @@ def test_prepared_group_graph_replays_match_single_launches():
             torch.cuda.synchronize()
             for (_, _, Ct, _), Rt in zip(members, refs):
                 assert torch.equal(Ct, Rt), f"replay {replay}"
+        for (A, B), path, (_, _, Ct, _) in zip(ops, paths, members):
+            _oracle_check(A, B, Ct.cpu().numpy(), path)
     finally:
         moa.moa_group_destroy(g)
 
 
 def test_prepared_group_with_fp8_members_replays():
     """FP8 members of both term counts join the captured sequence; three replays
-    with eager work in between all match single launches bitwise."""
+    with eager work in between all match single launches bitwise, and every
+    member meets its bar against the CPU oracle."""
     shapes = inputs.grouped_shapes(16, lo=3, hi=500, seed=33)
     ops = inputs.grouped_operands(shapes, seed=33)
     flags = [moa.MOA_FLAG_FP8_ONE_TERM, moa.MOA_FLAG_FP8_TWO_TERM] * 6 + [0, 0, 0, 0]
@@ -179,6 +194,8 @@ def test_prepared_group_with_fp8_members_replays():
             torch.cuda.synchronize()
             for k, ((_, _, Ct, _), Rt) in enumerate(zip(members, refs)):
                 assert torch.equal(Ct, Rt), f"replay {replay} member {k}"
+        for (A, B), path, fl, (_, _, Ct, _) in zip(ops, paths, flags, members):
+            _oracle_check(A, B, Ct.cpu().numpy(), path, fl)
     finally:
         moa.moa_group_destroy(g)
 

@@ -99,7 +99,7 @@ def test_split_k_writes_only_c(path, flags, shape):
 
 
 @pytest.mark.parametrize("combo", list(itertools.product([False, True], repeat=3)))
-@pytest.mark.parametrize("path", ["split_bf16", "fp8"])
+@pytest.mark.parametrize("path", ["split_bf16", "fp8", "onf", "mfma_f32"])
 def test_column_major_operands_write_only_c(path, combo):
     m, n, p = 130, 300, 77
     a_col, b_col, c_col = combo

@@ -7,9 +7,12 @@ A column-major operand is handed over as the transpose of a contiguous tensor
   the path's bar against the oracle (split-BF16 <= 1e-5 against Eq. 3 in FP64,
   FP8 <= 1e-4 against the exact product of the quantised operands) and
   bit-exact on integer-valued inputs.
-* ONF, all operands column-major: bitwise the fma-ordered oracle, FP64 and FP32
-  (the kernel runs C^T = B^T A^T; fma(b, a, c) = fma(a, b, c)). FP32 matrix
-  cores all column-major: <= 1e-5. Mixed layouts on these paths are refused.
+* ONF, every layout combination, FP64 and FP32, on ragged shapes: bitwise the
+  fma-ordered oracle (a column-major operand is transposed on its way into the
+  kernel's LDS slab; a column-major C runs as C^T = B^T A^T, and
+  fma(b, a, c) = fma(a, b, c)). FP32 matrix cores, every combination: <= 1e-5
+  against Eq. 3 and bit-exact on integers; the register-staged variant refuses
+  a column-major operand.
 * Grouped launches run members with a column-major operand singly: bitwise
   equal to moa_gemm.
 """
@@ -78,25 +81,38 @@ def test_every_layout_integer_exact(path, combo):
     assert np.array_equal(C.astype(np.float64), O.gemm_f64(A.astype(np.float64), B.astype(np.float64)))
 
 
+@pytest.mark.parametrize("combo", COMBOS)
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
-def test_onf_all_column_major_bitwise(dt):
-    A, B = inputs.uniform_f64(200, 77, 333, seed=6)
+@pytest.mark.parametrize("shape", [(200, 77, 333), (33, 130, 65), (1, 9, 130)])
+def test_onf_every_layout_bitwise(shape, dt, combo):
+    m, n, p = shape
+    A, B = inputs.uniform_f64(m, n, p, seed=6 + m)
     A, B = A.astype(dt), B.astype(dt)
-    C = run(A, B, "onf", True, True, True, dtype=dt)
+    C = run(A, B, "onf", *combo, dtype=dt)
     assert np.array_equal(C, O.gemm_f64_fma(A, B) if dt == np.float64 else O.gemm_f32_fma(A, B))
 
 
-def test_mfma_f32_all_column_major():
-    A, B = inputs.normal_f32(200, 300, 130, seed=7)
-    C = run(A, B, "mfma_f32", True, True, True)
+@pytest.mark.parametrize("combo", COMBOS)
+@pytest.mark.parametrize("shape", [(200, 300, 130), (65, 47, 300)])
+def test_mfma_f32_every_layout(shape, combo):
+    m, n, p = shape
+    A, B = inputs.normal_f32(m, n, p, seed=7 + n)
+    C = run(A, B, "mfma_f32", *combo)
     assert O.rel_err(C, O.gemm_f64(A.astype(np.float64), B.astype(np.float64))) <= 1e-5
 
 
-@pytest.mark.parametrize("path", ["onf", "mfma_f32"])
-def test_mixed_layouts_refused_on_row_major_kernels(path):
+@pytest.mark.parametrize("combo", COMBOS)
+@pytest.mark.parametrize("path", ["mfma_f32", "onf"])
+def test_row_kernels_every_layout_integer_exact(path, combo):
+    A, B = inputs.integer_valued(70, 150, 50, seed=5, dtype=np.float32)
+    C = run(A, B, path, *combo)
+    assert np.array_equal(C.astype(np.float64), O.gemm_f64(A.astype(np.float64), B.astype(np.float64)))
+
+
+def test_register_staged_fp32_refuses_column_operands():
     A, B = inputs.normal_f32(20, 30, 40, seed=1)
     with pytest.raises(moa.MoaError) as ei:
-        run(A, B, path, True, False, False)
+        run(A, B, "mfma_f32", True, False, False, flags=moa.MOA_FLAG_VARIANT(2))
     assert ei.value.status == moa.MOA_ERR_UNSUPPORTED
 
 

@@ -126,9 +126,9 @@ def test_serve_release_frees_completed_tickets_only():
 
 
 def test_serve_refuses_request_beyond_budget_and_unknown_ticket():
-    A = torch.zeros((256, 256), device=DEV)
-    B = torch.zeros((256, 256), device=DEV)
-    C = torch.zeros((256, 256), device=DEV)
+    A = torch.zeros((512, 512), device=DEV)           # 3 MiB of operands and result
+    B = torch.zeros((512, 512), device=DEV)
+    C = torch.zeros((512, 512), device=DEV)
     srv = moa.moa_serve_create(1 << 20, slots=1, max_group=1)
     try:
         with pytest.raises(moa.MoaError) as ei:

@@ -95,3 +95,32 @@ def test_grouped_split_k_member_equals_single_and_prepared_group_refuses():
     with pytest.raises(moa.MoaError) as ei:
         moa.moa_group_create(descs)
     assert ei.value.status == moa.MOA_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("path,flags", [("split_bf16", 0), ("fp8", moa.MOA_FLAG_FP8_TWO_TERM)])
+def test_planner_chosen_split_k(path, flags):
+    """A skinny product with a long k walk is split by the planner itself: the
+    same bits as asking for the planner's chunk count, the path's bar against
+    the oracle, and a grouped launch runs it singly (alone = in the group)."""
+    m, n, p = 96, 6000, 130
+    A, B = inputs.normal_f32(m, n, p, seed=41)
+    At, Bt = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+    C = torch.full((m, p), float("nan"), device=DEV)
+    chunks = moa.moa_plan_query(moa.make_desc(At, Bt, C, path=path, flags=flags))["split_k"]
+    assert chunks > 1
+    auto = run(A, B, path, flags)
+    assert np.array_equal(auto, run(A, B, path, flags | moa.MOA_FLAG_SPLIT_K(chunks)))
+    whole = run(A, B, path, flags | moa.MOA_FLAG_SPLIT_K(1))
+    if path == "split_bf16":
+        R = O.gemm_f64(A.astype(np.float64), B.astype(np.float64))
+        assert O.rel_err(auto, R) <= 1e-5 and O.rel_err(whole, R) <= 1e-5
+    else:
+        Q = O.fp8_gemm_2term(A, B)
+        assert O.rel_err(auto, Q) <= 1e-4 and O.rel_err(whole, Q) <= 1e-4
+    small = inputs.normal_f32(70, 90, 50, seed=42)
+    S = [torch.from_numpy(x).to(DEV) for x in small]
+    Cs = torch.empty((70, 50), device=DEV)
+    moa.moa_gemm_grouped([moa.make_desc(At, Bt, C, path=path, flags=flags),
+                          moa.make_desc(S[0], S[1], Cs, path=path, flags=flags)])
+    torch.cuda.synchronize()
+    assert np.array_equal(C.cpu().numpy(), auto)

@@ -33,7 +33,7 @@ def test_scheduler_on_a_fake_device(tmp_path):
     assert "all ok" in run.stdout
     for name in ("pool_blocks", "synthetic_lifecycle", "device_error_on_completion", "launch_and_marker_failures",
                  "device_out_of_memory", "budget_and_fcfs", "release_frees_budget", "batching_window",
-                 "ticket_errors"):
+                 "ticket_errors", "pool_reserve"):
         assert f"ok {name}" in run.stdout
 
 
