@@ -710,7 +710,7 @@ def block_sweep(args, torch, moa):
         A = torch.rand((N, N), generator=gen, device="cuda", dtype=torch.float64) * 2 - 1
         B = torch.rand((N, N), generator=gen, device="cuda", dtype=torch.float64) * 2 - 1
         C = torch.empty((N, N), device="cuda", dtype=torch.float64)
-        for v in range(4):
+        for v in range(5):
             d = moa.make_desc(A, B, C, path=moa.MOA_PATH_ONF, flags=moa.MOA_FLAG_VARIANT(v))
             plan = moa.moa_plan_query(d)
 

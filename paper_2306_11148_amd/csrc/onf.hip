@@ -20,6 +20,7 @@
 // k loop, so the k-sum of every element is the plain ascending sequence of
 // fma(A[i,k], B[k,j], acc) -- bitwise the paper's loop with fma.
 #include "moa_internal.h"
+#include "ring_gemm.h"
 
 namespace moa {
 namespace {
@@ -294,13 +295,195 @@ __global__ __launch_bounds__(256) void onf_kernel(const T *__restrict__ A,
     }
 }
 
+// FP64 on a direct-load LDS ring: 128 x 128 blocks of C, 8 x 8 elements per
+// lane. A lane reads 2 doubles of LDS per FMA-pair of work (8 of A and 8 of B
+// per k for 64 FMAs: 2 bytes per FMA, which the LDS delivers at the FP64 FMA
+// rate), where the register-staged kernel's 4 x 8 lane block reads 3; the
+// slabs go from memory straight into LDS (`buffer_load ... lds`, 8 k per
+// slab, three slabs in the ring), so no registers hold them in flight and the
+// 64 accumulator pairs fit two waves per SIMD. Per slab:
+//   A: 128 rows of 64 bytes (8 doubles), 16-byte chunk c of row r at physical
+//      chunk c ^ ((r / 4) mod 4);
+//   B: the slab's 8 rows of 128 doubles, one KiB each.
+// Rows past m and slab rows past n read as zeros (buffer ranges); columns past
+// p are never stored. The k loop is the same ascending fma sequence per
+// element as the register-staged kernel, and the last slab stops at n (no
+// padded steps), so results are bitwise the same.
+constexpr int ONF64_NST = 3;
+
+__global__ __launch_bounds__(256, 2) void onf64_ring_kernel(const double *__restrict__ A, const double *__restrict__ B,
+                                                           double *__restrict__ C, int64_t m, int64_t n, int64_t p,
+                                                           int accumulate, int vec_c) {
+    constexpr int TM = 128, TN = 128, BK = 8, R = 8, VJ = 8, TR = 16, TC = 16;
+    constexpr int A_BYTES = TM * BK * 8, B_BYTES = BK * TN * 8, STAGE = A_BYTES + B_BYTES, LPW = 4;
+    static_assert(STAGE / 1024 == 4 * LPW, "four waves, LPW KiB loads each");
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[ONF64_NST * STAGE];
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int tr = t / TC, tc = t % TC;
+    const int64_t i0 = (int64_t)blockIdx.y * TM, j0 = (int64_t)blockIdx.x * TN;
+
+    // the accumulate form starts from C (lane columns j0 + 32 g + 2 tc + {0, 1})
+    double acc[R][VJ];
+#pragma unroll
+    for (int q = 0; q < R; ++q)
+#pragma unroll
+        for (int v = 0; v < VJ; ++v) acc[q][v] = 0.0;
+    if (accumulate) {
+#pragma unroll
+        for (int q = 0; q < R; ++q) {
+            const int64_t i = i0 + tr + TR * q;
+            if (i >= m) continue;
+            const double *row = C + i * p + j0 + 2 * tc;
+#pragma unroll
+            for (int v = 0; v < VJ; ++v) {
+                const int64_t j = j0 + 32 * (v >> 1) + 2 * tc + (v & 1);
+                if (j < p) acc[q][v] = row[32 * (v >> 1) + (v & 1)];
+            }
+        }
+    }
+
+    const int64_t rows_live = m - i0 < TM ? m - i0 : TM;
+    const int64_t a_range = rows_live * n * 8;
+    const __amdgpu_buffer_rsrc_t a_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(A + i0 * n), (short)0, (int)(a_range < 0x7FFFFFFF ? a_range : 0x7FFFFFFF), 0x00020000);
+    const int64_t b_total = n * p - j0;        // elements from B + j0 to the end of B
+    const int64_t S = (n + BK - 1) / BK;
+
+    auto issue = [&](int64_t s) {
+        uint8_t *buf = lds + (s % ONF64_NST) * STAGE;
+        const int64_t k0 = s * BK;
+        const int64_t left = b_total - k0 * p;
+        const __amdgpu_buffer_rsrc_t b_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(B + j0 + k0 * p), (short)0, (int)(left * 8 < 0x7FFFFFFF ? left * 8 : 0x7FFFFFFF), 0x00020000);
+#pragma unroll
+        for (int q = 0; q < LPW; ++q) {
+            const int g = wave * LPW + q;                 // wave-uniform
+            if (g < A_BYTES / 1024) {
+                const int r = 16 * g + (lane >> 2);
+                const int c = (lane & 3) ^ ((lane >> 4) & 3);
+                const int voff = r < rows_live ? (int)(((int64_t)r * n + k0 + 2 * c) * 8) : ring::kDeadVoffset;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(a_rsrc, (ring::lds_void_t *)(buf + g * 1024), 16, voff, 0, 0,
+                                                         0);
+            } else {
+                const int h = g - A_BYTES / 1024;          // slab row h: 128 doubles, 2 per lane
+                const int voff = (int)(((int64_t)h * p + 2 * lane) * 8);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(b_rsrc, (ring::lds_void_t *)(buf + A_BYTES + h * 1024), 16,
+                                                         voff, 0, 0, 0);
+            }
+        }
+    };
+
+    // one whole slab (8 k, ascending) from `buf`
+    auto compute_full = [&](const uint8_t *buf) {
+        const uint8_t *bs = buf + A_BYTES;
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 2) {
+            double2 av[R];
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int r = tr + TR * q;
+                av[q] = *reinterpret_cast<const double2 *>(buf + r * 64 + (((kk >> 1) ^ ((r >> 2) & 3)) << 4));
+            }
+#pragma unroll
+            for (int e = 0; e < 2; ++e) {
+                double b[VJ];
+#pragma unroll
+                for (int g = 0; g < VJ / 2; ++g) {
+                    const double2 bv = *reinterpret_cast<const double2 *>(bs + (kk + e) * 1024 + (32 * g + 2 * tc) * 8);
+                    b[2 * g] = bv.x;
+                    b[2 * g + 1] = bv.y;
+                }
+#pragma unroll
+                for (int q = 0; q < R; ++q) {
+                    const double a = e ? av[q].y : av[q].x;
+#pragma unroll
+                    for (int v = 0; v < VJ; ++v) acc[q][v] = __builtin_fma(a, b[v], acc[q][v]);
+                }
+            }
+        }
+    };
+    // the last, partial slab: k values 0 .. kc - 1 only (no padded steps)
+    auto compute_tail = [&](const uint8_t *buf, int kc) {
+        const uint8_t *bs = buf + A_BYTES;
+        for (int kk = 0; kk < kc; ++kk) {
+            double a[R], b[VJ];
+#pragma unroll
+            for (int q = 0; q < R; ++q) {
+                const int r = tr + TR * q;
+                const double2 v2 = *reinterpret_cast<const double2 *>(buf + r * 64 + (((kk >> 1) ^ ((r >> 2) & 3)) << 4));
+                a[q] = (kk & 1) ? v2.y : v2.x;
+            }
+#pragma unroll
+            for (int g = 0; g < VJ / 2; ++g) {
+                const double2 bv = *reinterpret_cast<const double2 *>(bs + kk * 1024 + (32 * g + 2 * tc) * 8);
+                b[2 * g] = bv.x;
+                b[2 * g + 1] = bv.y;
+            }
+#pragma unroll
+            for (int q = 0; q < R; ++q)
+#pragma unroll
+                for (int v = 0; v < VJ; ++v) acc[q][v] = __builtin_fma(a[q], b[v], acc[q][v]);
+        }
+    };
+
+    // Per slab: slab s has landed in every wave (at most slab s + 1 still in
+    // flight) and every wave is done with slab s - 1, whose buffer slab
+    // s + 2 then takes.
+    const int64_t full = n / BK;
+    if (S > 0) {
+        issue(0);
+        if (S > 1) issue(1);
+    }
+    for (int64_t s = 0; s < full; ++s) {
+        if (s + 1 < S) __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(LPW));
+        else __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(0));
+        ring::ring_barrier();
+        if (s + 2 < S) issue(s + 2);
+        compute_full(lds + (s % ONF64_NST) * STAGE);
+    }
+    if (full < S) {
+        __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(0));
+        ring::ring_barrier();
+        compute_tail(lds + (full % ONF64_NST) * STAGE, (int)(n - full * BK));
+    }
+
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int64_t i = i0 + tr + TR * q;
+        if (i >= m) continue;
+#pragma unroll
+        for (int g = 0; g < VJ / 2; ++g) {
+            const int64_t j = j0 + 32 * g + 2 * tc;
+            if (vec_c && j + 2 <= p) {
+                *reinterpret_cast<double2 *>(C + i * p + j) = make_double2(acc[q][2 * g], acc[q][2 * g + 1]);
+            } else {
+                if (j < p) C[i * p + j] = acc[q][2 * g];
+                if (j + 1 < p) C[i * p + j + 1] = acc[q][2 * g + 1];
+            }
+        }
+    }
+}
+
+hipError_t launch_onf64_ring(const moa_gemm_desc &d, hipStream_t st) {
+    const double *A = static_cast<const double *>(d.A);
+    const double *B = static_cast<const double *>(d.B);
+    double *C = static_cast<double *>(d.C);
+    const int vec_c = (d.p % 2 == 0) && ((uintptr_t)C % 16 == 0);
+    dim3 grid((unsigned)((d.p + 127) / 128), (unsigned)((d.m + 127) / 128));
+    hipLaunchKernelGGL(onf64_ring_kernel, grid, dim3(256), 0, st, A, B, C, d.m, d.n, d.p, d.accumulate, vec_c);
+    return hipGetLastError();
+}
+
 struct OnfShape { int tm, tn, bk, r, vj; };
 
 // Instantiation tables. The first entry per type is the paper's static block
 // for the 32 KB vector L1 (three blocks of A, B and C): 1024 FP64 components
 // (32 x 32) and 2048 FP32 components (32 x 64). Larger entries trade LDS for
 // register blocking; the planner picks among them.
-constexpr OnfShape kF64[] = {{32, 32, 16, 2, 2}, {64, 64, 16, 4, 4}, {64, 128, 16, 4, 8}, {128, 128, 16, 8, 8}};
+// FP64 entry 4 is the direct-load ring kernel above (row-major operands).
+constexpr OnfShape kF64[] = {{32, 32, 16, 2, 2}, {64, 64, 16, 4, 4}, {64, 128, 16, 4, 8}, {128, 128, 16, 8, 8},
+                             {128, 128, 8, 8, 8}};
 constexpr OnfShape kF32[] = {{32, 64, 16, 2, 4}, {64, 64, 16, 4, 4}, {64, 128, 16, 4, 8}, {128, 128, 16, 8, 8}};
 
 template <typename T, int TM, int TN, int BK, int R, int VJ>
@@ -340,7 +523,14 @@ void onf_variant_shape(moa_dtype t, int v, Plan *p) {
     p->wave_n = s.tn;
     p->threads = 256;
     p->lds_bytes = 2 * (s.tm * (s.bk + 16 / es) + s.bk * s.tn) * es;
+    if (t == MOA_F64 && v == onf_f64_ring_variant()) p->lds_bytes = ONF64_NST * (s.tm + s.tn) * s.bk * es;
 }
+
+int onf_f64_ring_variant() { return 4; }
+
+// The ring kernel's 32-bit buffer offsets: 128 rows of n doubles of A, 8 rows
+// of p doubles of B.
+bool onf_f64_ring_fits(int64_t n, int64_t p) { return 130 * n * 8 < 0x7FFFFFFF && 9 * p * 8 < 0x7FFFFFFF; }
 
 hipError_t launch_onf(const moa_gemm_desc &d, const Plan &plan, hipStream_t st) {
     if (d.dtype == MOA_F64) {
@@ -348,7 +538,8 @@ hipError_t launch_onf(const moa_gemm_desc &d, const Plan &plan, hipStream_t st) 
         case 0: return launch_one<double, 32, 32, 16, 2, 2>(d, st);
         case 1: return launch_one<double, 64, 64, 16, 4, 4>(d, st);
         case 2: return launch_one<double, 64, 128, 16, 4, 8>(d, st);
-        default: return launch_one<double, 128, 128, 16, 8, 8>(d, st);
+        case 3: return launch_one<double, 128, 128, 16, 8, 8>(d, st);
+        default: return launch_onf64_ring(d, st);
         }
     }
     switch (plan.variant) {

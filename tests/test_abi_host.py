@@ -141,6 +141,30 @@ def test_split_k_plan():
     assert call(_desc(8, 8, 8, flags=1 << 28)) == moa.MOA_ERR_INVALID
 
 
+def test_onf_f64_ring_plan():
+    """FP64 products with every CU given a 128 x 128 block run the direct-load
+    ring kernel (variant 4) when their operands are row-major and their
+    offsets fit; the others stay on the register-staged blocks."""
+    F64, ONF = moa.MOA_F64, moa.MOA_PATH_ONF
+    q = lambda m, n, p, fl=0: moa.moa_plan_query(_desc(m, n, p, F64, ONF, flags=fl))  # noqa: E731
+    big = q(8192, 8192, 8192)
+    assert big["variant"] == 4 and (big["tile_m"], big["tile_n"], big["tile_k"]) == (128, 128, 8)
+    assert (big["lane_m"], big["lane_n"]) == (8, 8) and big["lds_bytes"] == 3 * 16384
+    assert q(2048, 2048, 2048)["variant"] == 4                   # 256 blocks
+    assert q(2048, 2048, 1920)["variant"] != 4                   # 240 blocks
+    assert q(256, 256, 256)["variant"] == 0                      # the static rule's 32 x 32 block
+    allcol = moa.MOA_FLAG_A_COL | moa.MOA_FLAG_B_COL | moa.MOA_FLAG_C_COL
+    assert q(8192, 8192, 8192, allcol)["variant"] == 4          # C^T = B^T A^T is all row-major
+    assert q(8192, 8192, 8192, moa.MOA_FLAG_A_COL)["variant"] == 2
+    assert q(4096, 2100000, 4096)["variant"] == 2                # A's offsets would not fit
+    with pytest.raises(moa.MoaError) as ei:
+        q(256, 256, 256, moa.MOA_FLAG_VARIANT(4) | moa.MOA_FLAG_B_COL)
+    assert ei.value.status == moa.MOA_ERR_UNSUPPORTED
+    assert q(256, 256, 256, moa.MOA_FLAG_VARIANT(4))["variant"] == 4
+    with pytest.raises(moa.MoaError):
+        q(256, 256, 256, moa.MOA_FLAG_VARIANT(5))
+
+
 def test_split_k_chosen_by_the_planner():
     """Without MOA_FLAG_SPLIT_K the planner splits products of at most 64
     blocks of 128 x 128 with n >= 4096 into about 512 workgroups of at least

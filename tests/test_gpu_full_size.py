@@ -124,3 +124,20 @@ def test_cube_256_f64_onf():
     got = run(At, Bt, "onf").cpu().numpy()
     assert np.array_equal(got, O.gemm_f64_fma(A, B))
     assert O.rel_err(got, O.gemm_f64(A, B)) <= 1e-12
+
+
+def test_square_8192_onf_f64_ring_bitwise():
+    """The FP64 workload of the benchmark (8192^3, uniform[-1, 1), seed 8192) in
+    its launch configuration (the direct-load ring kernel): sampled rows
+    bitwise the fma-ordered oracle, every element written."""
+    A, B = inputs.uniform_f64(8192, 8192, 8192, seed=8192)
+    At, Bt = torch.from_numpy(A).to(DEV), torch.from_numpy(B).to(DEV)
+    Ct = torch.full((8192, 8192), float("nan"), dtype=torch.float64, device=DEV)
+    d = moa.make_desc(At, Bt, Ct, path="onf")
+    assert moa.moa_plan_query(d)["variant"] == 4
+    moa.moa_gemm(At, Bt, Ct, path="onf")
+    torch.cuda.synchronize()
+    rows = sample_rows(8192, 12, seed=83)
+    got = Ct[torch.from_numpy(rows).to(DEV)].cpu().numpy()
+    assert np.array_equal(got, O.gemm_f64_fma(A[rows], B))
+    assert bool(torch.isfinite(Ct).all())

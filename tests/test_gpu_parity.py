@@ -91,23 +91,32 @@ def onf_variants(dt):
         v += 1
 
 
-@pytest.mark.parametrize("shape", [(200, 77, 333), (1, 16, 5), (70, 1000, 600)])
+@pytest.mark.parametrize("shape", [(200, 77, 333), (1, 16, 5), (70, 1000, 600), (130, 5, 257), (129, 8, 255),
+                                   (300, 1, 140)])
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
 def test_onf_every_block_size_is_bitwise_the_same(dt, shape):
     """Changing the dimension lift (block sizes) never changes a result:
-    every variant, overwrite and accumulate, bitwise the fma-ordered oracle."""
+    every variant (FP64 also its direct-load ring kernel: whole 8-k slabs,
+    a partial last slab, n < 8), overwrite and accumulate, bitwise the
+    fma-ordered oracle -- including a zero row of A over a -0 row of C,
+    where one padded k step would turn -0 into +0."""
     m, n, p = shape
     A, B = inputs.uniform_f64(m, n, p, seed=5)
     A, B = A.astype(dt), B.astype(dt)
+    A[0, :] = 0.0
     C0 = (np.arange(m * p).reshape(m, p) % 13 - 6).astype(dt)
+    C0[0, :] = -0.0
     ref = O.gemm_f64_fma(A, B) if dt == np.float64 else O.gemm_f32_fma(A, B)
     ref_acc = O.gemm_f64_fma(A, B, C0, True) if dt == np.float64 else O.gemm_f32_fma(A, B, C0, True)
     count = onf_variants(dt)
-    assert count == 4
+    assert count == (5 if dt == np.float64 else 4)
     for v in range(count):
         fl = moa.MOA_FLAG_VARIANT(v)
-        assert np.array_equal(run(A, B, "onf", flags=fl), ref), f"variant {v}"
-        assert np.array_equal(run(A, B, "onf", accumulate=True, C0=C0, flags=fl), ref_acc), f"variant {v}"
+        got, got_acc = run(A, B, "onf", flags=fl), run(A, B, "onf", accumulate=True, C0=C0, flags=fl)
+        assert np.array_equal(got.view(np.uint64 if dt == np.float64 else np.uint32),
+                              ref.view(np.uint64 if dt == np.float64 else np.uint32)), f"variant {v}"
+        assert np.array_equal(got_acc.view(np.uint64 if dt == np.float64 else np.uint32),
+                              ref_acc.view(np.uint64 if dt == np.float64 else np.uint32)), f"variant {v}"
 
 
 @pytest.mark.parametrize("path", ["onf", "mfma_f32", "split_bf16", "fp8"])
