@@ -203,13 +203,16 @@ moa_status moa_gemm(const moa_gemm_desc *desc, void *stream);
 #define MOA_NOALLOC_SCRATCH_BYTES ((int64_t)64 << 20)
 moa_status moa_gemm_noalloc(const moa_gemm_desc *desc, void *stream);
 
-/* `count` independent products. Members on the split-BF16 path (including
- * F32 with MOA_PATH_AUTO) are conditioned together and contracted by ONE
- * persistent launch that walks a shared tile list; scaled-FP8 members
- * likewise, one persistent launch per term count; members on the ONF and
- * FP32 matrix-core paths run as single launches on the same stream. No
- * ordering among members. Each result is bitwise the result moa_gemm gives
- * for the same descriptor.
+/* `count` independent products (the blocked inner product of Fig. 2 over
+ * many products at once). Row-major members on the split-BF16 path
+ * (including F32 with MOA_PATH_AUTO) are contracted by ONE persistent launch
+ * that walks a shared tile list and splits the FP32 operands into hi/lo BF16
+ * on the way through LDS (no conditioning pass); scaled-FP8 members are
+ * conditioned together and contracted by one persistent launch per term
+ * count; members on the ONF and FP32 matrix-core paths, and members with a
+ * column-major operand or a split k walk, run as single launches on the same
+ * stream. No ordering among members. Each result is bitwise the result
+ * moa_gemm gives for the same descriptor, whichever persistent kernel runs.
  * Descriptors are read on the host during the call; the array may be reused
  * when the call returns.
  * Errors: as moa_gemm, checked for every member before anything launches;
@@ -217,6 +220,45 @@ moa_status moa_gemm_noalloc(const moa_gemm_desc *desc, void *stream);
  * C overlapping any member's A, B or C. */
 moa_status moa_gemm_grouped(const moa_gemm_desc *descs, int64_t count,
                             void *stream);
+
+/* The persistent split-BF16 kernel of a grouped launch (the dimension lift of
+ * section "Dimension Lifting to Machine Coordinates" applied to a work list
+ * of blocks from many products):
+ *   0  128 x 128 blocks, each slab split once into one LDS plane set, three
+ *      workgroups per CU;
+ *   1  128 x 128, two plane sets and a deeper ring, two per CU;
+ *   2  128 x 128, split in registers by every wave that reads a fragment,
+ *      two per CU;
+ *   3  64 x 128 blocks, split once, four per CU;
+ *   4  128 x 64 blocks, split once, four per CU.
+ * moa_gemm_grouped and moa_group_create use the autotuner's record for the
+ * members' class if there is one, else the static rule: the block among 0, 3
+ * and 4 with the fewest slab steps over the members, weighted by the
+ * measured time of one slab step of that block. moa_gemm_grouped_variant runs
+ * moa_gemm_grouped with `variant` forced (-1: that choice); MOA_ERR_INVALID
+ * for a variant outside -1 .. 4. */
+#define MOA_GROUPED_VARIANTS 5
+moa_status moa_gemm_grouped_variant(const moa_gemm_desc *descs, int64_t count, int32_t variant, void *stream);
+
+/* The persistent split-BF16 kernel moa_gemm_grouped would use for these
+ * members (no launch): `variant` (-1 when no member runs in it), `tuned` 1 if
+ * it came from the autotuner, `persistent_members` the number of members in
+ * that launch. Any output may be null. Errors: as moa_gemm_grouped. */
+moa_status moa_grouped_plan_query(const moa_gemm_desc *descs, int64_t count, int32_t *variant, int32_t *tuned,
+                                  int64_t *persistent_members);
+
+/* Grouped autotuner: runs the whole grouped launch with each persistent
+ * kernel in turn (one warm-up, then `reps` timed runs each, on `stream`,
+ * overwriting every C), waits, and records the fastest for the class of the
+ * persistent members -- ceil(log2) of their count and of their median m, n
+ * and p -- which later grouped launches and prepared groups of that class
+ * then use. The record is saved and loaded with the single-product records
+ * (moa_autotune_save / _load) and cleared with them. `chosen` / `best_ms`
+ * (may be null) receive the winner and its time per launch. Errors: as
+ * moa_gemm_grouped; MOA_ERR_INVALID for reps < 1; MOA_ERR_UNSUPPORTED when no
+ * member runs in the persistent split-BF16 launch. */
+moa_status moa_autotune_grouped(const moa_gemm_desc *descs, int64_t count, int32_t reps, void *stream,
+                                int32_t *chosen, double *best_ms);
 
 /* The ipophp family (conclusion and appendix: the Hadamard, Kronecker and
  * matrix products in one formulation, higher-dimensional contractions as

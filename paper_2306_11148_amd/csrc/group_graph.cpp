@@ -84,7 +84,7 @@ moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group
             release(g);
             return hip_fail(e, "hipEventCreateWithFlags");
         }
-        GroupedWork work{0, 0};
+        GroupedWork work{0, 0, 0};
         const int cnt = (int)split.size();
         if (cnt > 0) {
             e = hipMalloc(&g->ws, (size_t)split_grouped_workspace_bytes(split.data(), cnt));
@@ -93,7 +93,8 @@ moa_status moa_group_create(const moa_gemm_desc *descs, int64_t count, moa_group
                 return fail(MOA_ERR_NOMEM, "group workspace: %s", hipGetErrorString(e));
             }
             std::vector<char> host((size_t)split_grouped_desc_bytes(split.data(), cnt));
-            work = split_grouped_layout(split.data(), cnt, g->ws, host.data());
+            work = split_grouped_layout(split.data(), cnt, g->ws, host.data(),
+                                        split_grouped_choose(split.data(), cnt, -1, nullptr));
             e = hipMemcpy(static_cast<char *>(g->ws) + 256, host.data(), host.size(), hipMemcpyHostToDevice);
             if (e != hipSuccess) {
                 release(g);

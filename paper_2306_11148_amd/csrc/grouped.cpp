@@ -172,8 +172,11 @@ int64_t grouped_scratch_bytes(const moa_gemm_desc *descs, int64_t count) {
     return total;
 }
 
-moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t stream, ScratchArena *arena) {
+moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t stream, ScratchArena *arena,
+                       int split_variant) {
     const Partition pt = partition(descs, count);
+    const int sv = pt.split.empty() ? 0 : split_grouped_choose(pt.split.data(), (int)pt.split.size(), split_variant,
+                                                               nullptr);
     for (const moa_gemm_desc *d : pt.single) {
         moa_status s;
         if (arena) {
@@ -190,7 +193,7 @@ moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t st
     moa_status s = run_list(
         pt.split, split_grouped_desc_bytes(pt.split.data(), (int)pt.split.size()), split_grouped_workspace_bytes,
         [&](const moa_gemm_desc *const *m, int c, void *ws, void *host) {
-            return launch_split_grouped(m, c, ws, host, stream);
+            return launch_split_grouped(m, c, sv, ws, host, stream);
         },
         stream, arena);
     for (int two = 0; two < 2 && s == MOA_OK; ++two)
@@ -208,19 +211,94 @@ moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t st
 
 using namespace moa;
 
-extern "C" moa_status moa_gemm_grouped(const moa_gemm_desc *descs, int64_t count, void *stream) {
-    try {
-        if (count < 0) return fail(MOA_ERR_INVALID, "negative count");
-        if (count > 0 && !descs) return fail(MOA_ERR_INVALID, "null descriptor array");
-        for (int64_t g = 0; g < count; ++g) {
-            moa_status s = validate(descs[g], true);
-            if (s != MOA_OK) return s;
-            Plan pl;
-            if (descs[g].m > 0 && descs[g].p > 0 && (s = make_plan(descs[g], &pl)) != MOA_OK) return s;
-        }
-        moa_status s = check_group_overlap(descs, count);
+namespace {
+
+moa_status check_grouped_args(const moa_gemm_desc *descs, int64_t count) {
+    if (count < 0) return fail(MOA_ERR_INVALID, "negative count");
+    if (count > 0 && !descs) return fail(MOA_ERR_INVALID, "null descriptor array");
+    for (int64_t g = 0; g < count; ++g) {
+        moa_status s = validate(descs[g], true);
         if (s != MOA_OK) return s;
-        return run_grouped(descs, count, static_cast<hipStream_t>(stream));
+        Plan pl;
+        if (descs[g].m > 0 && descs[g].p > 0 && (s = make_plan(descs[g], &pl)) != MOA_OK) return s;
+    }
+    return check_group_overlap(descs, count);
+}
+
+}  // namespace
+
+extern "C" moa_status moa_gemm_grouped(const moa_gemm_desc *descs, int64_t count, void *stream) {
+    return moa_gemm_grouped_variant(descs, count, -1, stream);
+}
+
+extern "C" moa_status moa_gemm_grouped_variant(const moa_gemm_desc *descs, int64_t count, int32_t variant,
+                                               void *stream) {
+    try {
+        if (variant < -1 || variant >= split_grouped_variant_count())
+            return fail(MOA_ERR_INVALID, "grouped variant %d out of range", (int)variant);
+        moa_status s = check_grouped_args(descs, count);
+        if (s != MOA_OK) return s;
+        return run_grouped(descs, count, static_cast<hipStream_t>(stream), nullptr, variant);
+    } catch (...) {
+        return fail(MOA_ERR_DEVICE, "internal error");
+    }
+}
+
+extern "C" moa_status moa_grouped_plan_query(const moa_gemm_desc *descs, int64_t count, int32_t *variant,
+                                             int32_t *tuned, int64_t *persistent_members) {
+    try {
+        moa_status s = check_grouped_args(descs, count);
+        if (s != MOA_OK) return s;
+        const Partition pt = partition(descs, count);
+        bool t = false;
+        const int v = pt.split.empty() ? -1 : split_grouped_choose(pt.split.data(), (int)pt.split.size(), -1, &t);
+        if (variant) *variant = v;
+        if (tuned) *tuned = t ? 1 : 0;
+        if (persistent_members) *persistent_members = (int64_t)pt.split.size();
+        return MOA_OK;
+    } catch (...) {
+        return fail(MOA_ERR_DEVICE, "internal error");
+    }
+}
+
+extern "C" moa_status moa_autotune_grouped(const moa_gemm_desc *descs, int64_t count, int32_t reps, void *stream,
+                                           int32_t *chosen, double *best_ms) {
+    try {
+        if (reps < 1) return fail(MOA_ERR_INVALID, "reps must be >= 1");
+        moa_status s = check_grouped_args(descs, count);
+        if (s != MOA_OK) return s;
+        const Partition pt = partition(descs, count);
+        if (pt.split.empty()) return fail(MOA_ERR_UNSUPPORTED, "no member runs in the persistent split-BF16 launch");
+        hipStream_t st = static_cast<hipStream_t>(stream);
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        hipError_t e = hipEventCreate(&e0);
+        if (e == hipSuccess) e = hipEventCreate(&e1);
+        if (e != hipSuccess) {
+            if (e0) (void)hipEventDestroy(e0);
+            return hip_fail(e, "hipEventCreate");
+        }
+        int best = -1;
+        double best_t = 0;
+        for (int v = 0; v < split_grouped_variant_count() && s == MOA_OK; ++v) {
+            s = run_grouped(descs, count, st, nullptr, v);                     // warm-up
+            if (s == MOA_OK && (e = hipEventRecord(e0, st)) != hipSuccess) s = hip_fail(e, "autotune timing");
+            for (int r = 0; r < reps && s == MOA_OK; ++r) s = run_grouped(descs, count, st, nullptr, v);
+            if (s == MOA_OK && (e = hipEventRecord(e1, st)) != hipSuccess) s = hip_fail(e, "autotune timing");
+            if (s == MOA_OK && (e = hipEventSynchronize(e1)) != hipSuccess) s = hip_fail(e, "autotune timing");
+            float ms = 0;
+            if (s == MOA_OK && (e = hipEventElapsedTime(&ms, e0, e1)) != hipSuccess) s = hip_fail(e, "autotune timing");
+            if (s == MOA_OK && (best < 0 || ms / reps < best_t)) {
+                best = v;
+                best_t = ms / reps;
+            }
+        }
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        if (s != MOA_OK) return s;
+        record_tuned_group_variant(pt.split.data(), (int)pt.split.size(), best, best_t);
+        if (chosen) *chosen = best;
+        if (best_ms) *best_ms = best_t;
+        return MOA_OK;
     } catch (...) {
         return fail(MOA_ERR_DEVICE, "internal error");
     }

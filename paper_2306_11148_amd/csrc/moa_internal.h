@@ -157,8 +157,18 @@ int64_t split_grouped_workspace_bytes(const moa_gemm_desc *const *members, int c
 // (else it runs as a single launch).
 bool split_grouped_fits(const moa_gemm_desc &d);
 int64_t split_grouped_desc_bytes(const moa_gemm_desc *const *members, int count);
-hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, void *workspace,
+hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, int variant, void *workspace,
                                 void *host_staging, hipStream_t stream);
+// Persistent split-BF16 kernels of a grouped launch (blocks 128 x 128 split
+// once with three or two blocks per CU, 128 x 128 split in registers,
+// 64 x 128, 128 x 64), the static rule's choice among them, and the choice a
+// grouped launch makes: `forced` when >= 0, else the autotuner's record for
+// the members' class, else the static rule.
+int split_grouped_variant_count();
+int split_grouped_default_variant(const moa_gemm_desc *const *members, int count);
+int split_grouped_choose(const moa_gemm_desc *const *members, int count, int forced, bool *tuned);
+int tuned_group_variant(const moa_gemm_desc *const *members, int count);
+void record_tuned_group_variant(const moa_gemm_desc *const *members, int count, int variant, double ms);
 // The two halves of launch_split_grouped: host layout (returns the sizes of
 // the contraction and conditioning work lists; the member array to upload is
 // in host_staging) and the device sequence, which allocates, copies and clears
@@ -166,9 +176,10 @@ hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, 
 struct GroupedWork {
     int64_t tiles;                      // contraction tiles over all members
     int64_t pack_items;                 // conditioning items over all members
+    int variant;                        // persistent kernel
 };
 GroupedWork split_grouped_layout(const moa_gemm_desc *const *members, int count, void *workspace,
-                                 void *host_staging);
+                                 void *host_staging, int variant);
 hipError_t split_grouped_enqueue(void *workspace, int count, const GroupedWork &work, hipStream_t stream);
 
 hipError_t launch_fp8(const moa_gemm_desc &d, const Plan &plan, void *workspace,
@@ -226,7 +237,7 @@ struct ScratchArena {
     int64_t used = 0;
 };
 moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t stream,
-                       ScratchArena *arena = nullptr);
+                       ScratchArena *arena = nullptr, int split_variant = -1);
 // Bytes of scratch run_grouped takes from an arena for these members.
 int64_t grouped_scratch_bytes(const moa_gemm_desc *descs, int64_t count);
 // Scratch bytes of one product under its plan (0 for empty products).

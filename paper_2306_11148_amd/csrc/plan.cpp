@@ -12,6 +12,7 @@
 // CUs several times over, so the planner takes the largest block that still
 // yields at least one workgroup per CU and falls back to the smallest.
 #include <array>
+#include <vector>
 #include <cstdio>
 #include <cstdlib>
 #include <map>
@@ -41,7 +42,49 @@ ClassKey class_key(const moa_gemm_desc &d, moa_path path) {
             ceil_log2(d.n), ceil_log2(d.p)};
 }
 
+// Class of a grouped launch's persistent split-BF16 members: member count and
+// the medians of m, n and p, each as ceil(log2); marked by a path code no
+// single product has.
+constexpr int kGroupClass = 16;
+ClassKey group_key(const moa_gemm_desc *const *members, int count) {
+    std::vector<int64_t> m(count), n(count), p(count);
+    for (int k = 0; k < count; ++k) {
+        m[k] = members[k]->m;
+        n[k] = members[k]->n;
+        p[k] = members[k]->p;
+    }
+    auto median = [](std::vector<int64_t> &v) {
+        std::nth_element(v.begin(), v.begin() + (long)(v.size() / 2), v.end());
+        return v[v.size() / 2];
+    };
+    return {MOA_F32, kGroupClass, ceil_log2(count), ceil_log2(median(m)), ceil_log2(median(n)), ceil_log2(median(p))};
+}
+
 }  // namespace
+
+int tuned_group_variant(const moa_gemm_desc *const *members, int count) {
+    if (count <= 0) return -1;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tuned.find(group_key(members, count));
+    return it == g_tuned.end() ? -1 : it->second.variant;
+}
+
+void record_tuned_group_variant(const moa_gemm_desc *const *members, int count, int variant, double ms) {
+    if (count <= 0) return;
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tuned[group_key(members, count)] = {variant, ms};
+}
+
+int split_grouped_choose(const moa_gemm_desc *const *members, int count, int forced, bool *tuned) {
+    if (tuned) *tuned = false;
+    if (forced >= 0) return forced;
+    const int t = tuned_group_variant(members, count);
+    if (t >= 0) {
+        if (tuned) *tuned = true;
+        return t;
+    }
+    return split_grouped_default_variant(members, count);
+}
 
 int tuned_variant(const moa_gemm_desc &d, moa_path path) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
@@ -68,7 +111,8 @@ moa_status autotune_save(const char *path) {
     FILE *f = std::fopen(path, "w");
     if (!f) return fail(MOA_ERR_INVALID, "cannot write %s", path);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    std::fprintf(f, "# moa autotune v1: dtype path terms log2m log2n log2p variant ms\n");
+    std::fprintf(f, "# moa autotune v1: dtype path terms log2m log2n log2p variant ms "
+                    "(path %d: grouped split-BF16, fields count and median m, n, p)\n", kGroupClass);
     for (const auto &kv : g_tuned)
         std::fprintf(f, "%d %d %d %d %d %d %d %.6f\n", kv.first[0], kv.first[1], kv.first[2], kv.first[3],
                      kv.first[4], kv.first[5], kv.second.variant, kv.second.ms);
@@ -93,8 +137,12 @@ moa_status autotune_load(const char *path) {
         moa_gemm_desc probe{};
         probe.dtype = k[0];
         probe.flags = k[2] == 2 ? 0 : MOA_FLAG_FP8_ONE_TERM;
-        if (k[1] < MOA_PATH_ONF || k[1] > MOA_PATH_FP8_SCALED || (k[0] != MOA_F64 && k[0] != MOA_F32) ||
-            t.variant < 0 || t.variant >= variant_count(probe, (moa_path)k[1])) {
+        const bool group = k[1] == kGroupClass && k[0] == MOA_F32;
+        const int nvar = group ? split_grouped_variant_count()
+                               : (k[1] < MOA_PATH_ONF || k[1] > MOA_PATH_FP8_SCALED) ? 0
+                                                                                      : variant_count(probe, (moa_path)k[1]);
+        if ((!group && (k[1] < MOA_PATH_ONF || k[1] > MOA_PATH_FP8_SCALED)) || (k[0] != MOA_F64 && k[0] != MOA_F32) ||
+            t.variant < 0 || t.variant >= nvar) {
             std::fclose(f);
             return fail(MOA_ERR_INVALID, "out-of-range entry in %s: %s", path, line);
         }

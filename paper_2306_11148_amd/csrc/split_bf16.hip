@@ -239,13 +239,15 @@ ring::Operands split_operands(const uint8_t *Ap, const uint8_t *Bp, float *C, in
 // Grouped members skip the conditioning pass: a tile streams the FP32 slabs
 // of its rows of A and columns of B straight from memory into an LDS ring
 // (direct loads, as the record ring does with records) and splits them into
-// hi/lo BF16 fragments in registers when it reads them (split_pair, as the
-// conditioning kernels do). Every element of every member receives exactly
-// the operation sequence of the single-product kernel -- the same hi/lo
-// values, zero past n, the same matrix-core steps slab by slab -- so grouped
-// and single results are bitwise equal.
+// hi/lo BF16 with split_pair, as the conditioning kernels do -- either once
+// per element into LDS planes (conv_tile, the default kernels) or in
+// registers by every wave that reads a fragment (raw_tile). Every element of
+// every member receives exactly the operation sequence of the single-product
+// kernel -- the same hi/lo values, zero past n, the same matrix-core steps
+// slab by slab -- so grouped and single results are bitwise equal, whichever
+// kernel and block shape run.
 //
-// LDS stage of one slab (16 k):
+// LDS stage of one slab (16 k) of raw_tile:
 //   A: BM rows of 64 bytes (16 FP32), 16-byte chunk c of row r at physical
 //      chunk c ^ ((r / 4) mod 4) (the record ring's swizzle);
 //   B: the slab's 16 rows of BN FP32, loaded in pairs (k, k + 8) per KiB: row
@@ -281,6 +283,32 @@ __device__ __forceinline__ void split8(const float (&x)[8], bf16x8_t &hi, bf16x8
     split_pair(x[6], x[7], &h.w, &l.w);
     hi = __builtin_bit_cast(bf16x8_t, h);
     lo = __builtin_bit_cast(bf16x8_t, l);
+}
+
+// A wave's FM x FN blocks of 32 x 32 accumulators to C (rows from i0,
+// columns from j0), skipping what lies past m or p.
+template <int FM, int FN>
+__device__ __forceinline__ void store_block(const GroupMember &d, int64_t i0, int64_t j0,
+                                            const f32x16_t (&acc)[FM][FN]) {
+    const int lane = threadIdx.x & 63;
+    const int64_t p = d.p;
+    ring::global_f32 *C = (ring::global_f32 *)d.C;
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+            const int64_t j = j0 + b * 32 + (lane & 31);
+            if (j >= p) continue;
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+                const int64_t i = i0 + a * 32 + mfma32_row(r, lane);
+                if (i < d.m) {
+                    float v = acc[a][b][r];
+                    if (d.accumulate) v += C[i * p + j];
+                    C[i * p + j] = v;
+                }
+            }
+        }
 }
 
 template <int BM, int BN, int WM, int WN, int NST>
@@ -410,24 +438,7 @@ __device__ __forceinline__ void raw_tile(const GroupMember &d, int64_t i0, int64
         }
     }
     __syncthreads();                    // every wave done with the ring before the next tile's loads
-
-    ring::global_f32 *C = (ring::global_f32 *)d.C;
-#pragma unroll
-    for (int a = 0; a < FM; ++a)
-#pragma unroll
-        for (int b = 0; b < FN; ++b) {
-            const int64_t j = j0 + wn * WN + b * 32 + (lane & 31);
-            if (j >= p) continue;
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t i = i0 + wm * WM + a * 32 + mfma32_row(r, lane);
-                if (i < d.m) {
-                    float v = acc[a][b][r];
-                    if (d.accumulate) v += C[i * p + j];
-                    C[i * p + j] = v;
-                }
-            }
-        }
+    store_block<FM, FN>(d, i0 + wm * WM, j0 + wn * WN, acc);
 }
 
 template <int BM, int BN, int WM, int WN, int NST>
@@ -449,6 +460,220 @@ __global__ __launch_bounds__(256, 2) void split_grouped_kernel(const GroupMember
         const int64_t tm = local / d.tiles_n, tn = local - tm * d.tiles_n;
         raw_tile<BM, BN, WM, WN, NST>(d, __builtin_amdgcn_readfirstlane((int)tm) * (int64_t)BM,
                                       __builtin_amdgcn_readfirstlane((int)tn) * (int64_t)BN, lds);
+    }
+}
+
+// Grouped block that splits every element of a slab once. The FP32 slab
+// lands in an LDS ring by direct loads as above (A swizzled; B as plain rows
+// of BN FP32); one pass of the whole workgroup turns it into hi and lo BF16
+// planes in a second, double-buffered LDS area; the four waves (2 x 2, each
+// BM/2 x BN/2) read their matrix-core fragments straight from the planes.
+// Per slab and wave this costs a quarter of the splits of the raw ring (no
+// element is split by two waves) and one barrier, which at once publishes
+// the planes just written, confirms the next raw slab landed in every wave
+// and frees the raw stage just split for the next load.
+//
+// Plane layout, per plane (A hi, A lo, B hi, B lo): [half h][row or column]
+// [8 BF16 of k in 8h .. 8h + 7], i.e. 16 bytes per row and half, so that a
+// fragment (32 rows, two halves) is two runs of 512 contiguous bytes.
+template <int BM, int BN, int NST, int NCV> struct ConvCfg {
+    static constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 32, FN = WN / 32;
+    static constexpr int RAW_A = BM * 64, RAW_B = SLAB * BN * 4, RAW = RAW_A + RAW_B;
+    static constexpr int PL_A = BM * 32, PL_B = BN * 32;       // bytes of one A or B plane
+    static constexpr int CONV = 2 * (PL_A + PL_B);
+    static constexpr int LOADS = RAW / 1024, LPW = LOADS / 4;  // KiB direct loads per slab, per wave
+    static constexpr int UNITS = 2 * (BM + BN);                // half rows of A, half columns of B
+    static constexpr int LDS = NST * RAW + NCV * CONV;
+    static_assert((BM == 64 || BM == 128) && (BN == 64 || BN == 128), "blocks of the split-once ring");
+    static_assert(LOADS % 4 == 0 && NST >= 2 && NST <= 3 && (NCV == 1 || NCV == 2), "shape of the split-once ring");
+};
+
+template <int BM, int BN, int NST, int NCV>
+__device__ __forceinline__ void conv_tile(const GroupMember &d, int64_t i0, int64_t j0, uint8_t *lds) {
+    using G = ConvCfg<BM, BN, NST, NCV>;
+    constexpr int FM = G::FM, FN = G::FN, LPW = G::LPW;
+    const int t = threadIdx.x, lane = t & 63;
+    const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
+    const int wm = wave >> 1, wn = wave & 1;
+    const int L = (int)d.S;
+    const int64_t n = d.n, p = d.p;
+    uint8_t *const raw = lds;
+    uint8_t *const conv = lds + NST * G::RAW;
+
+    const int64_t rows_live = d.m - i0 < BM ? d.m - i0 : BM;
+    const int64_t a_range = rows_live * n * 4;
+    const __amdgpu_buffer_rsrc_t a_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)(d.A + i0 * n), (short)0, (int)(a_range < 0x7FFFFFFF ? a_range : 0x7FFFFFFF), 0x00020000);
+    const float *b_tile = d.B + j0;
+    const int64_t b_total = n * p - j0;                  // elements from b_tile to the end of B
+
+    // Slab s into raw stage s mod NST. A: 16 rows of 64 bytes per load, rows
+    // past m dead. B: 1024 / (4 BN) rows per load; the resource starts at row
+    // k0 and ends with B, so rows past n (and columns past p on the last
+    // row) are out of range and load as zeros.
+    auto issue = [&](int s) {
+        uint8_t *buf = raw + (s % NST) * G::RAW;
+        const int64_t k0 = (int64_t)s * SLAB;
+        const int64_t left = b_total - k0 * p;
+        const __amdgpu_buffer_rsrc_t b_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(b_tile + k0 * p), (short)0,
+            (int)(left * 4 < 0x7FFFFFFF ? (left > 0 ? left * 4 : 0) : 0x7FFFFFFF), 0x00020000);
+#pragma unroll
+        for (int q = 0; q < LPW; ++q) {
+            const int g = wave * LPW + q;
+            if (g < BM / 16) {
+                const int r = 16 * g + (lane >> 2);
+                const int c = (lane & 3) ^ ((lane >> 4) & 3);
+                const int voff = r < rows_live ? (int)(((int64_t)r * n + k0 + 4 * c) * 4) : ring::kDeadVoffset;
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(a_rsrc, (ring::lds_void_t *)(buf + g * 1024), 16, voff,
+                                                         0, 0, 0);
+            } else {
+                constexpr int CPR = BN / 4;                 // 16-byte chunks per B row
+                const int h = g - BM / 16;
+                const int row = h * (1024 / (4 * BN)) + lane / CPR;
+                const int voff = (int)(((int64_t)row * p + 4 * (lane % CPR)) * 4);
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(b_rsrc, (ring::lds_void_t *)(buf + G::RAW_A + h * 1024),
+                                                         16, voff, 0, 0, 0);
+            }
+        }
+    };
+
+    // Split raw slab s into plane set s mod 2; k past n counts as zero.
+    auto convert = [&](int s) {
+        const uint8_t *buf = raw + (s % NST) * G::RAW;
+        uint8_t *cv = conv + (s % NCV) * G::CONV;
+        const int64_t k0 = (int64_t)s * SLAB;
+#pragma unroll
+        for (int i = 0; i < (G::UNITS + 255) / 256; ++i) {
+            const int ub = wave * 64 + 256 * i;     // first unit of this wave: units split per wave
+            if (ub >= G::UNITS) break;
+            const int u = ub + lane;
+            float x[8];
+            int h, dst;
+            const bool is_a = ub < 2 * BM;
+            if (is_a) {
+                h = ub / BM;
+                const int r = u - h * BM;
+                const int sw = (r >> 2) & 3;
+                const float4 v0 = *reinterpret_cast<const float4 *>(buf + r * 64 + (((2 * h) ^ sw) << 4));
+                const float4 v1 = *reinterpret_cast<const float4 *>(buf + r * 64 + (((2 * h + 1) ^ sw) << 4));
+                x[0] = v0.x; x[1] = v0.y; x[2] = v0.z; x[3] = v0.w;
+                x[4] = v1.x; x[5] = v1.y; x[6] = v1.z; x[7] = v1.w;
+                dst = h * BM * 16 + r * 16;
+            } else {
+                h = (ub - 2 * BM) / BN;
+                const int c = u - 2 * BM - h * BN;
+                const uint8_t *bb = buf + G::RAW_A + c * 4;
+#pragma unroll
+                for (int e = 0; e < 8; ++e) x[e] = *reinterpret_cast<const float *>(bb + (8 * h + e) * BN * 4);
+                dst = 2 * G::PL_A + h * BN * 16 + c * 16;
+            }
+            if (k0 + SLAB > n) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+                    if (k0 + 8 * h + e >= n) x[e] = 0.0f;
+            }
+            bf16x8_t hi, lo;
+            split8(x, hi, lo);
+            const int plane = is_a ? G::PL_A : G::PL_B;
+            *reinterpret_cast<bf16x8_t *>(cv + dst) = hi;
+            *reinterpret_cast<bf16x8_t *>(cv + dst + plane) = lo;
+        }
+    };
+
+    const int frow = lane & 31, fhalf = lane >> 5;
+    SplitMode::Frags<FM, FN> f;
+    auto read_frags = [&](int s) {
+        const uint8_t *cv = conv + (s % NCV) * G::CONV;
+#pragma unroll
+        for (int a = 0; a < FM; ++a) {
+            const int off = fhalf * BM * 16 + (wm * G::WM + a * 32 + frow) * 16;
+            f.ah[a] = *reinterpret_cast<const bf16x8_t *>(cv + off);
+            f.al[a] = *reinterpret_cast<const bf16x8_t *>(cv + G::PL_A + off);
+        }
+#pragma unroll
+        for (int b = 0; b < FN; ++b) {
+            const int off = 2 * G::PL_A + fhalf * BN * 16 + (wn * G::WN + b * 32 + frow) * 16;
+            f.bh[b] = *reinterpret_cast<const bf16x8_t *>(cv + off);
+            f.bl[b] = *reinterpret_cast<const bf16x8_t *>(cv + G::PL_B + off);
+        }
+    };
+
+    f32x16_t acc[FM][FN];
+#pragma unroll
+    for (int a = 0; a < FM; ++a)
+#pragma unroll
+        for (int b = 0; b < FN; ++b) acc[a][b] = f32x16_t{};
+
+    auto wait_loads = [&](int slabs) {          // at most `slabs` later slabs of this wave in flight
+        switch (slabs <= 0 ? 0 : slabs >= 2 ? 2 : 1) {
+        case 0: __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(0)); break;
+        case 1: __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(LPW)); break;
+        default: __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(2 * LPW)); break;
+        }
+    };
+    // Barrier that also publishes this wave's plane writes (LDS stores done).
+    auto plane_barrier = [] {
+        __builtin_amdgcn_s_waitcnt(0xC07F);     // lgkmcnt(0); vector-memory and export counts not waited on
+        ring::ring_barrier();
+    };
+
+    if (L > 0) {
+        for (int q = 0; q < NST; ++q)
+            if (q < L) issue(q);
+        wait_loads((NST < L ? NST : L) - 1);
+        ring::ring_barrier();
+        convert(0);
+        for (int s = 0; s < L; ++s) {
+            if (NCV == 2) {
+                // one barrier: planes of s complete, raw slab s + 1 landed,
+                // planes of s - 1 (the set convert(s + 1) writes) read by all
+                if (s + 1 < L) wait_loads((NST - 2 < L - 2 - s) ? NST - 2 : L - 2 - s);
+                plane_barrier();
+                if (s + NST < L) issue(s + NST);  // raw stage s mod NST: split by every wave
+                read_frags(s);
+                if (s + 1 < L) convert(s + 1);
+            } else {
+                // one plane set: a second barrier between reading it and
+                // overwriting it with the next slab
+                plane_barrier();
+                if (s + NST < L) issue(s + NST);
+                read_frags(s);
+                if (s + 1 < L) {
+                    wait_loads((NST - 1 < L - 2 - s) ? NST - 1 : L - 2 - s);
+                    plane_barrier();
+                    convert(s + 1);
+                }
+            }
+            SplitMode::mma<FM, FN>(f, acc);
+        }
+    }
+    __syncthreads();                    // every wave done with both LDS areas before the next tile
+    store_block<FM, FN>(d, i0 + wm * G::WM, j0 + wn * G::WN, acc);
+}
+
+template <int BM, int BN, int NST, int NCV, int OCC>
+__global__ __launch_bounds__(256, OCC) void split_grouped_conv_kernel(const GroupMember *__restrict__ g,
+                                                                    const int32_t *__restrict__ tile_owner,
+                                                                    int64_t total_tiles,
+                                                                    unsigned long long *__restrict__ counter) {
+    using G = ConvCfg<BM, BN, NST, NCV>;
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[G::LDS];
+    // the claimed tile id lives in the last plane set, which no wave writes
+    // before the first barrier of a tile
+    int64_t *s_tile = reinterpret_cast<int64_t *>(lds + NST * G::RAW + (NCV - 1) * G::CONV);
+    for (;;) {
+        __syncthreads();                // nobody still reads the tile id (or the planes)
+        if (threadIdx.x == 0) *s_tile = (int64_t)atomicAdd(counter, 1ull);
+        __syncthreads();
+        const int64_t tile = *s_tile;
+        if (tile >= total_tiles) break;
+        const int k = __builtin_amdgcn_readfirstlane(tile_owner[tile]);
+        const GroupMember &d = g[k];
+        const int64_t local = tile - d.first_tile;
+        const int64_t tm = local / d.tiles_n, tn = local - tm * d.tiles_n;
+        conv_tile<BM, BN, NST, NCV>(d, __builtin_amdgcn_readfirstlane((int)tm) * (int64_t)BM,
+                               __builtin_amdgcn_readfirstlane((int)tn) * (int64_t)BN, lds);
     }
 }
 
@@ -585,16 +810,31 @@ hipError_t launch_split_bf16(const moa_gemm_desc &d, const Plan &plan, void *ws,
 
 namespace {
 __global__ void zero_u64_kernel(unsigned long long *x) { *x = 0ull; }
-constexpr int GB_M = 128, GB_N = 128, GW_M = 64, GW_N = 64, G_NST = 4;   // grouped block shape, ring depth
+constexpr int GB_M = 128, GW_M = 64, GW_N = 64, G_NST = 4;   // largest grouped block rows; raw-ring waves, depth
+
+// Persistent kernels of a grouped launch: block, workgroups per CU, and the
+// relative time of one slab step of a block (measured on 256 x n x 256
+// members), which the static rule weighs slab steps with.
+struct GroupedKernel { int bm, bn, occ; double step_cost; };
+constexpr GroupedKernel kGroupedK[] = {
+    {128, 128, 3, 1.00},   // 0: split once into one plane set, two raw stages
+    {128, 128, 2, 1.25},   // 1: split once, two plane sets, three raw stages
+    {128, 128, 2, 1.25},   // 2: split in registers by every wave that reads a fragment
+    {64, 128, 4, 0.75},    // 3: split once, 64 x 128
+    {128, 64, 4, 0.75},    // 4: split once, 128 x 64
+};
+constexpr int kGroupedVariants = (int)(sizeof(kGroupedK) / sizeof(kGroupedK[0]));
 int64_t align256(int64_t x) { return (x + 255) & ~int64_t(255); }
 
-// Contraction tiles of a member list (independent of the order).
+int64_t member_tiles(const moa_gemm_desc &d, int bm, int bn) {
+    return ((d.m + bm - 1) / bm) * ((d.p + bn - 1) / bn);
+}
+
+// Contraction tiles of a member list under any variant (64 x 64 blocks: at
+// least as many as every block of the table), for sizing the tables.
 GroupedWork grouped_counts(const moa_gemm_desc *const *members, int count) {
-    GroupedWork w{0, 0};
-    for (int k = 0; k < count; ++k) {
-        const moa_gemm_desc &d = *members[k];
-        w.tiles += ((d.m + GB_M - 1) / GB_M) * ((d.p + GB_N - 1) / GB_N);
-    }
+    GroupedWork w{0, 0, 0};
+    for (int k = 0; k < count; ++k) w.tiles += member_tiles(*members[k], 64, 64);
     return w;
 }
 // Member table, then the tile -> member table (int32).
@@ -617,12 +857,37 @@ int64_t split_grouped_workspace_bytes(const moa_gemm_desc *const *members, int c
     return 256 + split_grouped_desc_bytes(members, count);
 }
 
+int split_grouped_variant_count() { return kGroupedVariants; }
+
+// Static rule: the block with the fewest weighted slab steps over the
+// members (ties to the lower variant); variants 1 and 2 are left to the
+// autotuner.
+int split_grouped_default_variant(const moa_gemm_desc *const *members, int count) {
+    int best = 0;
+    double best_cost = 0;
+    for (int v : {0, 3, 4}) {
+        double cost = 0;
+        for (int k = 0; k < count; ++k) {
+            const moa_gemm_desc &d = *members[k];
+            cost += (double)member_tiles(d, kGroupedK[v].bm, kGroupedK[v].bn) * (double)((d.n + SLAB - 1) / SLAB);
+        }
+        cost *= kGroupedK[v].step_cost;
+        if (v == 0 || cost < best_cost) {
+            best = v;
+            best_cost = cost;
+        }
+    }
+    return best;
+}
+
 // Lays out the members (longest k walk first: the tail of the work list holds
-// the cheapest tiles) in `host_staging`; returns the tile count. The device
-// member array is at ws + 256, the claim counter at ws.
+// the cheapest tiles) in `host_staging` for grouped kernel `variant`; returns
+// the tile count. The device member array is at ws + 256, the claim counter
+// at ws.
 GroupedWork split_grouped_layout(const moa_gemm_desc *const *members, int count, void *ws,
-                                 void *host_staging) {
+                                 void *host_staging, int variant) {
     (void)ws;
+    const GroupedKernel gk = kGroupedK[variant];
     std::vector<int> order(count);
     for (int k = 0; k < count; ++k) order[k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
@@ -641,14 +906,14 @@ GroupedWork split_grouped_layout(const moa_gemm_desc *const *members, int count,
         g.m = d.m; g.n = d.n; g.p = d.p;
         g.S = (d.n + SLAB - 1) / SLAB;
         g.first_tile = tiles;
-        g.tiles_n = (int32_t)((d.p + GB_N - 1) / GB_N);
+        g.tiles_n = (int32_t)((d.p + gk.bn - 1) / gk.bn);
         g.accumulate = d.accumulate;
-        const int64_t mt = ((d.m + GB_M - 1) / GB_M) * g.tiles_n;
+        const int64_t mt = ((d.m + gk.bm - 1) / gk.bm) * g.tiles_n;
         for (int64_t t = 0; t < mt; ++t) tile_owner[tiles + t] = q;
         tiles += mt;
         h[q] = g;
     }
-    return {tiles, 0};
+    return {tiles, 0, variant};
 }
 
 // The device part of a grouped launch: reset the claim counter, run the
@@ -662,18 +927,40 @@ hipError_t split_grouped_enqueue(void *ws, int count, const GroupedWork &work, h
     const int32_t *tile_owner = reinterpret_cast<const int32_t *>(
         base + 256 + align256((int64_t)count * (int64_t)sizeof(GroupMember)));
     hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, st, counter);
-    const int64_t grid = std::min<int64_t>(tiles, 2 * kNumCUs);   // two blocks per CU
+    const int v = work.variant;
+    const int64_t grid = std::min<int64_t>(tiles, (int64_t)kGroupedK[v].occ * kNumCUs);   // resident blocks
     TraceScope ts(MOA_K_SPLIT_GROUPED, st);
-    if (grid > 0)
-        hipLaunchKernelGGL((split_grouped_kernel<GB_M, GB_N, GW_M, GW_N, G_NST>), dim3((unsigned)grid), dim3(256),
-                           0, st, dev_members, tile_owner, tiles, counter);
+    if (grid <= 0) return hipGetLastError();
+    const dim3 gr((unsigned)grid), bl(256);
+    switch (v) {
+    case 1:
+        hipLaunchKernelGGL((split_grouped_conv_kernel<128, 128, 3, 2, 2>), gr, bl, 0, st, dev_members, tile_owner,
+                           tiles, counter);
+        break;
+    case 2:
+        hipLaunchKernelGGL((split_grouped_kernel<128, 128, GW_M, GW_N, G_NST>), gr, bl, 0, st, dev_members,
+                           tile_owner, tiles, counter);
+        break;
+    case 3:
+        hipLaunchKernelGGL((split_grouped_conv_kernel<64, 128, 2, 1, 4>), gr, bl, 0, st, dev_members, tile_owner,
+                           tiles, counter);
+        break;
+    case 4:
+        hipLaunchKernelGGL((split_grouped_conv_kernel<128, 64, 2, 1, 4>), gr, bl, 0, st, dev_members, tile_owner,
+                           tiles, counter);
+        break;
+    default:
+        hipLaunchKernelGGL((split_grouped_conv_kernel<128, 128, 2, 1, 3>), gr, bl, 0, st, dev_members, tile_owner,
+                           tiles, counter);
+        break;
+    }
     return hipGetLastError();
 }
 
-hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, void *ws,
+hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, int variant, void *ws,
                                 void *host_staging, hipStream_t st) {
     if (count <= 0) return hipSuccess;
-    const GroupedWork work = split_grouped_layout(members, count, ws, host_staging);
+    const GroupedWork work = split_grouped_layout(members, count, ws, host_staging, variant);
     char *base = static_cast<char *>(ws);
     hipError_t e = hipMemcpyAsync(base + 256, host_staging, (size_t)split_grouped_desc_bytes(members, count),
                                   hipMemcpyHostToDevice, st);

@@ -86,7 +86,8 @@ class moa_req_info(ctypes.Structure):
 
 
 EXPORTS = [
-    "moa_gemm", "moa_gemm_noalloc", "moa_gemm_grouped", "moa_plan_query", "moa_static_block_components",
+    "moa_gemm", "moa_gemm_noalloc", "moa_gemm_grouped", "moa_gemm_grouped_variant", "moa_grouped_plan_query",
+    "moa_autotune_grouped", "moa_plan_query", "moa_static_block_components",
     "moa_split_bf16", "moa_quantise_fp8", "moa_error_norm", "moa_serve_create",
     "moa_serve_submit", "moa_serve_submit_synthetic", "moa_serve_poll", "moa_serve_result", "moa_serve_read",
     "moa_serve_release", "moa_serve_drain", "moa_serve_stats", "moa_serve_destroy", "moa_fill_synthetic",
@@ -123,6 +124,9 @@ def lib():
         "moa_gemm": ([P(moa_gemm_desc), vp], i32),
         "moa_gemm_noalloc": ([P(moa_gemm_desc), vp], i32),
         "moa_gemm_grouped": ([P(moa_gemm_desc), i64, vp], i32),
+        "moa_gemm_grouped_variant": ([P(moa_gemm_desc), i64, i32, vp], i32),
+        "moa_grouped_plan_query": ([P(moa_gemm_desc), i64, P(i32), P(i32), P(i64)], i32),
+        "moa_autotune_grouped": ([P(moa_gemm_desc), i64, i32, vp, P(i32), P(ctypes.c_double)], i32),
         "moa_plan_query": ([P(moa_gemm_desc), P(moa_plan_info)], i32),
         "moa_static_block_components": ([i64, i64, i64], i64),
         "moa_split_bf16": ([vp, i64, i64, vp, vp, vp], i32),
@@ -250,6 +254,33 @@ def moa_gemm_desc_call(desc: moa_gemm_desc, stream=None) -> int:
 def moa_gemm_grouped(descs, stream=None):
     arr = (moa_gemm_desc * len(descs))(*descs)
     _check(lib().moa_gemm_grouped(arr, len(descs), _stream_handle(stream)), "moa_gemm_grouped")
+
+
+MOA_GROUPED_VARIANTS = 5
+
+
+def moa_gemm_grouped_variant(descs, variant: int, stream=None):
+    """moa_gemm_grouped with the persistent split-BF16 kernel forced (-1: planner choice)."""
+    arr = (moa_gemm_desc * len(descs))(*descs)
+    _check(lib().moa_gemm_grouped_variant(arr, len(descs), variant, _stream_handle(stream)),
+           "moa_gemm_grouped_variant")
+
+
+def moa_grouped_plan_query(descs) -> dict:
+    arr = (moa_gemm_desc * len(descs))(*descs)
+    v, t, n = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int64()
+    _check(lib().moa_grouped_plan_query(arr, len(descs), ctypes.byref(v), ctypes.byref(t), ctypes.byref(n)),
+           "moa_grouped_plan_query")
+    return {"variant": v.value, "tuned": t.value, "persistent_members": n.value}
+
+
+def moa_autotune_grouped(descs, reps: int = 3, stream=None):
+    """Times every persistent split-BF16 kernel on this member list; returns (variant, best_ms)."""
+    arr = (moa_gemm_desc * len(descs))(*descs)
+    v, ms = ctypes.c_int32(), ctypes.c_double()
+    _check(lib().moa_autotune_grouped(arr, len(descs), reps, _stream_handle(stream), ctypes.byref(v),
+                                      ctypes.byref(ms)), "moa_autotune_grouped")
+    return v.value, ms.value
 
 
 def moa_plan_query(desc: moa_gemm_desc) -> dict:

@@ -15,7 +15,7 @@ import re
 import pytest
 
 from oracle import oracle as O
-from paper_2306_11148_amd import moa
+from paper_2306_11148_amd import inputs, moa
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 
@@ -331,6 +331,54 @@ def test_grouped_overlap_rejected_before_launch():
     bad = _desc(-1, 4, 4)
     arr = (moa.moa_gemm_desc * 2)(d1, bad)
     assert L.moa_gemm_grouped(arr, 2, None) == moa.MOA_ERR_SHAPE
+
+
+def _members(shapes, flags=0):
+    """Descriptors of distinct, non-overlapping (never touched) arrays."""
+    out = []
+    for k, (m, n, p) in enumerate(shapes):
+        A = 0x100000000 + k * 3 * (1 << 26)
+        out.append(_desc(m, n, p, A=A, B=A + (1 << 26), C=A + 2 * (1 << 26), flags=flags))
+    return out
+
+
+def test_grouped_static_rule_and_group_records(tmp_path):
+    """The persistent split-BF16 kernel of a grouped launch: the static rule
+    takes the block with the fewest weighted slab steps (64-row or 64-column
+    blocks where 128 would be half empty), members with a column-major
+    operand run singly, and an autotuner record for the members' class
+    (count and median m, n, p as ceil(log2)) overrides the rule."""
+    moa.moa_autotune_clear()
+    q = lambda ds: moa.moa_grouped_plan_query(ds)                     # noqa: E731
+    assert q(_members([(128, 300, 128)] * 8))["variant"] == 0          # 64-blocks would double the tiles
+    assert q(_members([(64, 300, 256)] * 8))["variant"] == 3           # 128 rows would be half empty
+    assert q(_members([(256, 300, 64)] * 8))["variant"] == 4
+    c4 = [tuple(int(x) for x in s) for s in inputs.grouped_shapes(512, 32, 2048, seed=4)]
+    assert q(_members(c4)) == {"variant": 0, "tuned": 0, "persistent_members": 512}
+    mixed = _members([(64, 300, 256)] * 4)
+    mixed[1].flags = moa.MOA_FLAG_A_COL
+    assert q(mixed)["persistent_members"] == 3
+    assert q(_members([(64, 300, 256)], flags=moa.MOA_FLAG_B_COL))["variant"] == -1
+    f = tmp_path / "group.txt"
+    f.write_text("1 16 3 6 9 8 2 0.25\n")                             # 8 members, medians 64, 300, 256
+    moa.moa_autotune_load(str(f))
+    assert q(_members([(64, 300, 256)] * 8)) == {"variant": 2, "tuned": 1, "persistent_members": 8}
+    assert q(_members([(64, 300, 256)] * 9))["tuned"] == 0              # 9 members: another class
+    g = tmp_path / "saved.txt"
+    moa.moa_autotune_save(str(g))
+    assert "1 16 3 6 9 8 2" in g.read_text()
+    bad = tmp_path / "bad.txt"
+    bad.write_text("1 16 3 6 9 8 5 0.25\n")                           # no grouped kernel 5
+    with pytest.raises(moa.MoaError):
+        moa.moa_autotune_load(str(bad))
+    moa.moa_autotune_clear()
+    assert q(_members([(64, 300, 256)] * 8))["tuned"] == 0
+    L = moa.lib()
+    ds = _members([(64, 300, 256)] * 2)
+    arr = (moa.moa_gemm_desc * 2)(*ds)
+    for v in (-2, moa.MOA_GROUPED_VARIANTS):
+        assert L.moa_gemm_grouped_variant(arr, 2, v, None) == moa.MOA_ERR_INVALID
+    assert L.moa_autotune_grouped(arr, 2, 0, None, None, None) == moa.MOA_ERR_INVALID
 
 
 def test_serve_argument_errors_before_device():

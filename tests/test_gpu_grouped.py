@@ -61,6 +61,62 @@ def test_grouped_split_bitwise_equals_single(accumulate):
         assert O.rel_err(got, R) <= 1e-5
 
 
+@pytest.mark.parametrize("accumulate", [False, True])
+@pytest.mark.parametrize("variant", range(moa.MOA_GROUPED_VARIANTS))
+def test_every_grouped_kernel_bitwise_equals_single(variant, accumulate):
+    """Each persistent split-BF16 kernel (block shapes 128 x 128, 64 x 128,
+    128 x 64; split once or in registers) gives every member bitwise the
+    single-launch result, on ragged shapes from 1 to 700."""
+    shapes = inputs.grouped_shapes(40, lo=1, hi=700, seed=15)
+    host, dev, descs = make_members(shapes, seed=15, accumulate=accumulate)
+    moa.moa_gemm_grouped_variant(descs, variant)
+    torch.cuda.synchronize()
+    ref = singles(host, "split_bf16", accumulate)
+    for k, ((A, B, C0), (_, _, Ct)) in enumerate(zip(host, dev)):
+        got = Ct.cpu().numpy()
+        assert np.array_equal(got, ref[k]), f"variant {variant} member {k} shape {A.shape} x {B.shape}"
+        R = O.gemm_f64(A.astype(np.float64), B.astype(np.float64),
+                       C0.astype(np.float64) if accumulate else None, accumulate)
+        assert O.rel_err(got, R) <= 1e-5
+
+
+def test_grouped_autotune_record_drives_launches_and_groups():
+    """moa_autotune_grouped times every persistent kernel on the member list
+    and records the fastest for the members' class; moa_gemm_grouped and a
+    prepared group then use it, and results stay bitwise the single-launch
+    ones."""
+    moa.moa_autotune_clear()
+    shapes = inputs.grouped_shapes(24, lo=16, hi=600, seed=16)
+    host, dev, descs = make_members(shapes, seed=16)
+    before = moa.moa_grouped_plan_query(descs)
+    assert before["tuned"] == 0 and before["persistent_members"] == len(descs)
+    v, ms = moa.moa_autotune_grouped(descs, reps=2)
+    assert 0 <= v < moa.MOA_GROUPED_VARIANTS and ms > 0
+    after = moa.moa_grouped_plan_query(descs)
+    assert after == {"variant": v, "tuned": 1, "persistent_members": len(descs)}
+    ref = singles(host, "split_bf16")
+    for _, _, Ct in dev:
+        Ct.fill_(float("nan"))
+    torch.cuda.synchronize()
+    moa.moa_gemm_grouped(descs)
+    torch.cuda.synchronize()
+    for k, (_, _, Ct) in enumerate(dev):
+        assert np.array_equal(Ct.cpu().numpy(), ref[k]), f"member {k}"
+    g = moa.moa_group_create(descs)
+    try:
+        for _ in range(2):
+            for _, _, Ct in dev:
+                Ct.fill_(float("nan"))
+            torch.cuda.synchronize()
+            moa.moa_group_launch(g)
+            torch.cuda.synchronize()
+            for k, (_, _, Ct) in enumerate(dev):
+                assert np.array_equal(Ct.cpu().numpy(), ref[k]), f"replay member {k}"
+    finally:
+        moa.moa_group_destroy(g)
+        moa.moa_autotune_clear()
+
+
 def test_grouped_mixed_paths_bitwise_equals_single():
     shapes = inputs.grouped_shapes(12, lo=5, hi=300, seed=21)
     paths = ["split_bf16", "onf", "fp8", "mfma_f32"] * 3
