@@ -45,6 +45,8 @@ PROFILE_CASES = {
     "onf_f64_256": ("onf", 0, "f64", (256, 256, 256)),
     "fp8_1term": ("fp8", "one", "f32", (8192, 4096, 8192)),
     "fp8_2term": ("fp8", "two", "f32", (8192, 4096, 8192)),
+    # 512 products, m, n, p log-uniform [32, 2048] (seed 4): one grouped launch per step
+    "grouped_c4": ("split_bf16", 0, "f32", None),
 }
 
 
@@ -279,10 +281,13 @@ def cpu_baseline(A, B, C_gpu, n, target_s, onf_rows=None, precision=None):
 
 def grouped_section(torch, moa, inputs, reps=10):
     """512 products, m, n, p log-uniform in [32, 2048] (seed 4), N(0,1) FP32
-    operands drawn on the device from a seeded generator: one grouped launch,
-    the same group prepared once and replayed as a HIP graph, and one launch
-    per product. The roofline of the set is the sum over products of
-    max(3 x 2 m n p / BF16 peak, 4 (m n + n p + m p) bytes / 8 TB/s)."""
+    operands drawn on the device from a seeded generator. The grouped
+    autotuner first times every persistent kernel on the set and records the
+    fastest (the static rule's pick is reported beside it); then one grouped
+    launch, the same group prepared once and replayed as a HIP graph, and one
+    launch per product are timed. The roofline of the set is the sum over
+    products of max(3 x 2 m n p / BF16 peak, 4 (m n + n p + m p) bytes /
+    8 TB/s)."""
     shapes = inputs.grouped_shapes(512, 32, 2048, seed=4)
     gen = torch.Generator(device="cuda").manual_seed(4)
     descs, keep = [], []
@@ -298,7 +303,18 @@ def grouped_section(torch, moa, inputs, reps=10):
     import ctypes
     arr = (moa.moa_gemm_desc * len(descs))(*descs)
     L, st = moa.lib(), torch.cuda.current_stream().cuda_stream
-    group = moa.moa_group_create(descs)
+    moa.moa_autotune_clear()
+    static_variant = moa.moa_grouped_plan_query(descs)["variant"]
+    variant_ms = {}
+    for v in range(moa.MOA_GROUPED_VARIANTS):
+        def run_v(v=v):
+            if L.moa_gemm_grouped_variant(arr, len(descs), v, st) != 0:
+                raise RuntimeError(moa.moa_last_error())
+        run_v()
+        variant_ms[v] = round(timed_loop(run_v, reps, torch)[1] / reps, 4)
+    tuned_variant, tuned_ms = moa.moa_autotune_grouped(descs, reps=reps)
+    plan = moa.moa_grouped_plan_query(descs)
+    group = moa.moa_group_create(descs)          # built with the tuned kernel
 
     def grouped():
         if L.moa_gemm_grouped(arr, len(descs), st) != 0:
@@ -327,6 +343,7 @@ def grouped_section(torch, moa, inputs, reps=10):
         traced = moa.moa_trace_read(reset=True)
     finally:
         moa.moa_group_destroy(group)
+        moa.moa_autotune_clear()
     ms_g, ms_r, ms_s = tot_g / reps, tot_r / reps, tot_s / reps
     n_k, t_k = traced.get("split_grouped", (0, 0.0))
     del keep
@@ -337,6 +354,13 @@ def grouped_section(torch, moa, inputs, reps=10):
             "grouped_tflops": round(flops / ms_g / 1e9, 2), "graph_replay_tflops": round(flops / ms_r / 1e9, 2),
             "per_gemm_tflops": round(flops / ms_s / 1e9, 2),
             "speedup": round(ms_s / best, 3),
+            "persistent_kernel": {"static_rule": static_variant, "autotuned": tuned_variant,
+                                  "used": plan["variant"], "tuned": plan["tuned"],
+                                  "autotune_best_ms": round(tuned_ms, 4),
+                                  "ms_by_kernel": variant_ms,
+                                  "kernels": {0: "128x128 split once, 3/CU", 1: "128x128 split once, 2 plane sets, 2/CU",
+                                              2: "128x128 split in registers, 2/CU", 3: "64x128 split once, 4/CU",
+                                              4: "128x64 split once, 4/CU"}},
             "contraction_kernel_ms": round(t_k / n_k, 4) if n_k else None,
             "roofline": {"bound": "sum over products of max(matrix-core, HBM) time", "ideal_ms": round(roof_ms, 4),
                          "frac": round(roof_ms / best, 4)}}
@@ -722,7 +746,9 @@ def block_sweep(args, torch, moa):
             per, tot = timed_loop(f, reps, torch)
             ms = tot / reps
             e = energy_per_call(f, min(args.energy_seconds, 1.0), ms, energy, torch)
-            print(json.dumps({"block_sweep": "ONF FP64", "N": N, "block": [plan["tile_m"], plan["tile_n"]],
+            print(json.dumps({"block_sweep": "ONF FP64", "N": N, "variant": v,
+                              "staging": "direct-to-LDS ring" if plan["tile_k"] == 8 else "registers",
+                              "block": [plan["tile_m"], plan["tile_n"]],
                               "components": plan["tile_m"] * plan["tile_n"], "ms": round(ms, 4),
                               "tflops": round(2.0 * N ** 3 / ms / 1e9, 3), "energy": e}), flush=True)
         del A, B, C
@@ -772,12 +798,45 @@ def split_variants(args, torch, moa):
             del A, B, C
 
 
+def profile_grouped(args, torch, moa):
+    """--profile-case grouped_c4: the batching workload's grouped launch
+    (planner-chosen persistent kernel), --warmup untimed and --steps timed."""
+    import ctypes
+    from paper_2306_11148_amd import inputs
+    shapes = inputs.grouped_shapes(512, 32, 2048, seed=4)
+    gen = torch.Generator(device="cuda").manual_seed(4)
+    descs, keep = [], []
+    for m, n, p in shapes:
+        A = torch.randn((int(m), int(n)), generator=gen, device="cuda")
+        B = torch.randn((int(n), int(p)), generator=gen, device="cuda")
+        C = torch.empty((int(m), int(p)), device="cuda")
+        keep.append((A, B, C))
+        descs.append(moa.make_desc(A, B, C, path=moa.MOA_PATH_SPLIT_BF16))
+    arr = (moa.moa_gemm_desc * len(descs))(*descs)
+    L, st = moa.lib(), torch.cuda.current_stream().cuda_stream
+
+    def f():
+        if L.moa_gemm_grouped(arr, len(descs), st) != 0:
+            raise RuntimeError(moa.moa_last_error())
+    for _ in range(args.warmup):
+        f()
+    per, tot = timed_loop(f, args.steps, torch)
+    flop = float(sum(2.0 * m * n * p for m, n, p in shapes))
+    print(json.dumps({"profile_case": "grouped_c4", "members": len(descs), "flop": flop,
+                      "plan": moa.moa_grouped_plan_query(descs), "launches": args.steps,
+                      "ms_per_launch": round(tot / args.steps, 4), "per_launch_ms": [round(x, 4) for x in per],
+                      "tflops": round(flop / (tot / args.steps) / 1e9, 2)}), flush=True)
+    del keep
+
+
 def profile_case(args, torch, moa):
     """One path on its workload, --warmup untimed and --steps timed launches
     (HIP events on the launch stream), for counter and trace passes; the
     copy-calibration copy runs last when asked for."""
     import ctypes
     name = args.profile_case
+    if name == "grouped_c4":
+        return profile_grouped(args, torch, moa)
     path, fp8, dt, (m, n, p) = PROFILE_CASES[name]
     dtype = torch.float64 if dt == "f64" else torch.float32
     gen = torch.Generator(device="cuda").manual_seed(n)
