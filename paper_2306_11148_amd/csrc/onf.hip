@@ -345,32 +345,42 @@ __global__ __launch_bounds__(256, 2) void onf64_ring_kernel(const double *__rest
 
     const int64_t rows_live = m - i0 < TM ? m - i0 : TM;
     const int64_t a_range = rows_live * n * 8;
-    const __amdgpu_buffer_rsrc_t a_rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(A + i0 * n), (short)0, (int)(a_range < 0x7FFFFFFF ? a_range : 0x7FFFFFFF), 0x00020000);
     const int64_t b_total = n * p - j0;        // elements from B + j0 to the end of B
     const int64_t S = (n + BK - 1) / BK;
 
-    auto issue = [&](int64_t s) {
-        uint8_t *buf = lds + (s % ONF64_NST) * STAGE;
+    // Both resources start at the slab (A: column k0 of the block's first
+    // row, B: row k0) and end where the live data ends, so each lane's vector
+    // offset is the same for every slab: computed once, in registers no later
+    // instruction overwrites.
+    int voff[LPW];
+#pragma unroll
+    for (int q = 0; q < LPW; ++q) {
+        const int g = wave * LPW + q;                     // wave-uniform
+        if (g < A_BYTES / 1024) {
+            const int r = 16 * g + (lane >> 2);
+            const int c = (lane & 3) ^ ((lane >> 4) & 3);
+            voff[q] = r < rows_live ? (int)(((int64_t)r * n + 2 * c) * 8) : ring::kDeadVoffset;
+        } else {
+            const int h = g - A_BYTES / 1024;              // slab row h: 128 doubles, 2 per lane
+            voff[q] = (int)(((int64_t)h * p + 2 * lane) * 8);
+        }
+    }
+    auto issue_to = [&](uint8_t *buf, int64_t s) {     // buf: stage s mod ONF64_NST
         const int64_t k0 = s * BK;
-        const int64_t left = b_total - k0 * p;
+        const int64_t a_left = a_range - k0 * 8, b_left = (b_total - k0 * p) * 8;
+        const __amdgpu_buffer_rsrc_t a_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(A + i0 * n + k0), (short)0, (int)(a_left > 0 ? a_left : 0), 0x00020000);
         const __amdgpu_buffer_rsrc_t b_rsrc = __builtin_amdgcn_make_buffer_rsrc(
-            (void *)(B + j0 + k0 * p), (short)0, (int)(left * 8 < 0x7FFFFFFF ? left * 8 : 0x7FFFFFFF), 0x00020000);
+            (void *)(B + j0 + k0 * p), (short)0, (int)(b_left < 0x7FFFFFFF ? b_left : 0x7FFFFFFF), 0x00020000);
 #pragma unroll
         for (int q = 0; q < LPW; ++q) {
-            const int g = wave * LPW + q;                 // wave-uniform
-            if (g < A_BYTES / 1024) {
-                const int r = 16 * g + (lane >> 2);
-                const int c = (lane & 3) ^ ((lane >> 4) & 3);
-                const int voff = r < rows_live ? (int)(((int64_t)r * n + k0 + 2 * c) * 8) : ring::kDeadVoffset;
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(a_rsrc, (ring::lds_void_t *)(buf + g * 1024), 16, voff, 0, 0,
-                                                         0);
-            } else {
-                const int h = g - A_BYTES / 1024;          // slab row h: 128 doubles, 2 per lane
-                const int voff = (int)(((int64_t)h * p + 2 * lane) * 8);
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(b_rsrc, (ring::lds_void_t *)(buf + A_BYTES + h * 1024), 16,
-                                                         voff, 0, 0, 0);
-            }
+            const int g = wave * LPW + q;
+            if (g < A_BYTES / 1024)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(a_rsrc, (ring::lds_void_t *)(buf + g * 1024), 16, voff[q], 0,
+                                                         0, 0);
+            else
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(
+                    b_rsrc, (ring::lds_void_t *)(buf + A_BYTES + (g - A_BYTES / 1024) * 1024), 16, voff[q], 0, 0, 0);
         }
     };
 
@@ -430,17 +440,25 @@ __global__ __launch_bounds__(256, 2) void onf64_ring_kernel(const double *__rest
     // Per slab: slab s has landed in every wave (at most slab s + 1 still in
     // flight) and every wave is done with slab s - 1, whose buffer slab
     // s + 2 then takes.
+    // One step: the stage the step's loads fill (slab s + 2) and the stage it
+    // computes (slab s) are disjoint LDS, passed as restrict pointers so that
+    // the compiler sees the reads need not wait for those loads, which are
+    // meant to stay in flight (the explicit wait before the barrier orders
+    // slab s's own loads).
+    auto step = [&](uint8_t *__restrict__ dma, const uint8_t *__restrict__ cur, int64_t s) {
+        if (s + 2 < S) issue_to(dma, s + 2);
+        compute_full(cur);
+    };
     const int64_t full = n / BK;
     if (S > 0) {
-        issue(0);
-        if (S > 1) issue(1);
+        issue_to(lds, 0);
+        if (S > 1) issue_to(lds + STAGE, 1);
     }
     for (int64_t s = 0; s < full; ++s) {
         if (s + 1 < S) __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(LPW));
         else __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(0));
         ring::ring_barrier();
-        if (s + 2 < S) issue(s + 2);
-        compute_full(lds + (s % ONF64_NST) * STAGE);
+        step(lds + ((s + 2) % ONF64_NST) * STAGE, lds + (s % ONF64_NST) * STAGE, s);
     }
     if (full < S) {
         __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(0));

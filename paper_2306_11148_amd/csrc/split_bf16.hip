@@ -502,46 +502,57 @@ __device__ __forceinline__ void conv_tile(const GroupMember &d, int64_t i0, int6
 
     const int64_t rows_live = d.m - i0 < BM ? d.m - i0 : BM;
     const int64_t a_range = rows_live * n * 4;
-    const __amdgpu_buffer_rsrc_t a_rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(d.A + i0 * n), (short)0, (int)(a_range < 0x7FFFFFFF ? a_range : 0x7FFFFFFF), 0x00020000);
+    const float *a_tile = d.A + i0 * n;
     const float *b_tile = d.B + j0;
     const int64_t b_total = n * p - j0;                  // elements from b_tile to the end of B
 
-    // Slab s into raw stage s mod NST. A: 16 rows of 64 bytes per load, rows
-    // past m dead. B: 1024 / (4 BN) rows per load; the resource starts at row
-    // k0 and ends with B, so rows past n (and columns past p on the last
-    // row) are out of range and load as zeros.
-    auto issue = [&](int s) {
-        uint8_t *buf = raw + (s % NST) * G::RAW;
+    // Slab s into raw stage s mod NST. Both resources start at the slab (A:
+    // column k0 of the tile's first row; B: row k0) and end where the live
+    // data ends, so the lanes' vector offsets stay the same for every slab --
+    // computed once here, in registers that no later instruction overwrites
+    // (a register the direct loads still read would make the compiler wait for
+    // every load in flight before reusing it). A: 16 rows of 64 bytes per
+    // load, rows past m dead, k past n in the last live row out of range
+    // (zeros), k past n inside earlier rows reads the next row (masked when
+    // split). B: 1024 / (4 BN) rows per load; rows past n (and columns past p
+    // on the last row) are out of range and load as zeros.
+    int voff[LPW];
+#pragma unroll
+    for (int q = 0; q < LPW; ++q) {
+        const int g = wave * LPW + q;
+        if (g < BM / 16) {
+            const int r = 16 * g + (lane >> 2);
+            const int c = (lane & 3) ^ ((lane >> 4) & 3);
+            voff[q] = r < rows_live ? (int)(((int64_t)r * n + 4 * c) * 4) : ring::kDeadVoffset;
+        } else {
+            constexpr int CPR = BN / 4;                     // 16-byte chunks per B row
+            const int row = (g - BM / 16) * (1024 / (4 * BN)) + lane / CPR;
+            voff[q] = (int)(((int64_t)row * p + 4 * (lane % CPR)) * 4);
+        }
+    }
+    auto issue_to = [&](uint8_t *buf, int s) {       // buf: raw stage s mod NST
         const int64_t k0 = (int64_t)s * SLAB;
-        const int64_t left = b_total - k0 * p;
+        const int64_t a_left = a_range - k0 * 4, b_left = (b_total - k0 * p) * 4;
+        const __amdgpu_buffer_rsrc_t a_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(a_tile + k0), (short)0, (int)(a_left > 0 ? a_left : 0), 0x00020000);
         const __amdgpu_buffer_rsrc_t b_rsrc = __builtin_amdgcn_make_buffer_rsrc(
             (void *)(b_tile + k0 * p), (short)0,
-            (int)(left * 4 < 0x7FFFFFFF ? (left > 0 ? left * 4 : 0) : 0x7FFFFFFF), 0x00020000);
+            (int)(b_left < 0x7FFFFFFF ? (b_left > 0 ? b_left : 0) : 0x7FFFFFFF), 0x00020000);
 #pragma unroll
         for (int q = 0; q < LPW; ++q) {
             const int g = wave * LPW + q;
-            if (g < BM / 16) {
-                const int r = 16 * g + (lane >> 2);
-                const int c = (lane & 3) ^ ((lane >> 4) & 3);
-                const int voff = r < rows_live ? (int)(((int64_t)r * n + k0 + 4 * c) * 4) : ring::kDeadVoffset;
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(a_rsrc, (ring::lds_void_t *)(buf + g * 1024), 16, voff,
+            if (g < BM / 16)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(a_rsrc, (ring::lds_void_t *)(buf + g * 1024), 16, voff[q],
                                                          0, 0, 0);
-            } else {
-                constexpr int CPR = BN / 4;                 // 16-byte chunks per B row
-                const int h = g - BM / 16;
-                const int row = h * (1024 / (4 * BN)) + lane / CPR;
-                const int voff = (int)(((int64_t)row * p + 4 * (lane % CPR)) * 4);
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(b_rsrc, (ring::lds_void_t *)(buf + G::RAW_A + h * 1024),
-                                                         16, voff, 0, 0, 0);
-            }
+            else
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(b_rsrc,
+                                                         (ring::lds_void_t *)(buf + G::RAW_A + (g - BM / 16) * 1024),
+                                                         16, voff[q], 0, 0, 0);
         }
     };
 
-    // Split raw slab s into plane set s mod 2; k past n counts as zero.
-    auto convert = [&](int s) {
-        const uint8_t *buf = raw + (s % NST) * G::RAW;
-        uint8_t *cv = conv + (s % NCV) * G::CONV;
+    // Split raw slab s (in buf) into the plane set cv; k past n counts as zero.
+    auto convert_from = [&](const uint8_t *buf, uint8_t *cv, int s) {
         const int64_t k0 = (int64_t)s * SLAB;
 #pragma unroll
         for (int i = 0; i < (G::UNITS + 255) / 256; ++i) {
@@ -583,8 +594,7 @@ __device__ __forceinline__ void conv_tile(const GroupMember &d, int64_t i0, int6
 
     const int frow = lane & 31, fhalf = lane >> 5;
     SplitMode::Frags<FM, FN> f;
-    auto read_frags = [&](int s) {
-        const uint8_t *cv = conv + (s % NCV) * G::CONV;
+    auto read_frags_from = [&](const uint8_t *cv) {
 #pragma unroll
         for (int a = 0; a < FM; ++a) {
             const int off = fhalf * BM * 16 + (wm * G::WM + a * 32 + frow) * 16;
@@ -618,32 +628,58 @@ __device__ __forceinline__ void conv_tile(const GroupMember &d, int64_t i0, int6
         ring::ring_barrier();
     };
 
-    if (L > 0) {
-        for (int q = 0; q < NST; ++q)
-            if (q < L) issue(q);
+    // One slab step. The stage the step's direct loads fill (dma: raw stage
+    // s mod NST, split by every wave before this step), the stage it splits
+    // (src: slab s + 1) and the plane sets are disjoint LDS, passed as
+    // restrict pointers: that lets the compiler see that reading src or the
+    // planes need not wait for the loads into dma, which are meant to stay in
+    // flight (the explicit waits above order each slab's loads before its
+    // split).
+    auto step1 = [&](uint8_t *__restrict__ dma, const uint8_t *__restrict__ src, uint8_t *__restrict__ planes,
+                     int s) {
+        // one plane set: a second barrier between reading it and overwriting
+        // it with the next slab
+        if (s + NST < L) issue_to(dma, s + NST);
+        read_frags_from(planes);
+        if (s + 1 < L) {
+            wait_loads((NST - 1 < L - 2 - s) ? NST - 1 : L - 2 - s);
+            plane_barrier();
+            convert_from(src, planes, s + 1);
+        }
+    };
+    auto step2 = [&](uint8_t *__restrict__ dma, const uint8_t *__restrict__ src,
+                     const uint8_t *__restrict__ planes_r, uint8_t *__restrict__ planes_w, int s) {
+        // two plane sets: one barrier makes the planes of s complete, raw
+        // slab s + 1 landed and the planes of s - 1 (the set this step
+        // writes) read by every wave
+        if (s + 1 < L) wait_loads((NST - 2 < L - 2 - s) ? NST - 2 : L - 2 - s);
+        plane_barrier();
+        if (s + NST < L) issue_to(dma, s + NST);
+        read_frags_from(planes_r);
+        if (s + 1 < L) convert_from(src, planes_w, s + 1);
+    };
+
+    // Ring fill and the split of slab 0 (stage 0), while the later stages'
+    // loads stay in flight (disjoint: restrict, as in the steps).
+    auto prologue = [&](uint8_t *__restrict__ st0, uint8_t *__restrict__ later, uint8_t *__restrict__ planes) {
+        issue_to(st0, 0);
+        for (int q = 1; q < NST; ++q)
+            if (q < L) issue_to(later + (q - 1) * G::RAW, q);
         wait_loads((NST < L ? NST : L) - 1);
         ring::ring_barrier();
-        convert(0);
+        convert_from(st0, planes, 0);
+    };
+
+    if (L > 0) {
+        prologue(raw, raw + G::RAW, conv);
         for (int s = 0; s < L; ++s) {
+            uint8_t *dma = raw + (s % NST) * G::RAW;
+            const uint8_t *src = raw + ((s + 1) % NST) * G::RAW;
             if (NCV == 2) {
-                // one barrier: planes of s complete, raw slab s + 1 landed,
-                // planes of s - 1 (the set convert(s + 1) writes) read by all
-                if (s + 1 < L) wait_loads((NST - 2 < L - 2 - s) ? NST - 2 : L - 2 - s);
-                plane_barrier();
-                if (s + NST < L) issue(s + NST);  // raw stage s mod NST: split by every wave
-                read_frags(s);
-                if (s + 1 < L) convert(s + 1);
+                step2(dma, src, conv + (s & 1) * G::CONV, conv + ((s + 1) & 1) * G::CONV, s);
             } else {
-                // one plane set: a second barrier between reading it and
-                // overwriting it with the next slab
                 plane_barrier();
-                if (s + NST < L) issue(s + NST);
-                read_frags(s);
-                if (s + 1 < L) {
-                    wait_loads((NST - 1 < L - 2 - s) ? NST - 1 : L - 2 - s);
-                    plane_barrier();
-                    convert(s + 1);
-                }
+                step1(dma, src, conv, s);
             }
             SplitMode::mma<FM, FN>(f, acc);
         }
