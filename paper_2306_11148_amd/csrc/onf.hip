@@ -300,7 +300,7 @@ __global__ __launch_bounds__(256) void onf_kernel(const T *__restrict__ A,
 // per k for 64 FMAs: 2 bytes per FMA, which the LDS delivers at the FP64 FMA
 // rate), where the register-staged kernel's 4 x 8 lane block reads 3; the
 // slabs go from memory straight into LDS (`buffer_load ... lds`, 8 k per
-// slab, three slabs in the ring), so no registers hold them in flight and the
+// slab, four slabs in the ring), so no registers hold them in flight and the
 // 64 accumulator pairs fit two waves per SIMD. Per slab:
 //   A: 128 rows of 64 bytes (8 doubles), 16-byte chunk c of row r at physical
 //      chunk c ^ ((r / 4) mod 4);
@@ -309,7 +309,7 @@ __global__ __launch_bounds__(256) void onf_kernel(const T *__restrict__ A,
 // p are never stored. The k loop is the same ascending fma sequence per
 // element as the register-staged kernel, and the last slab stops at n (no
 // padded steps), so results are bitwise the same.
-constexpr int ONF64_NST = 3;
+constexpr int ONF64_NST = 4;
 
 __global__ __launch_bounds__(256, 2) void onf64_ring_kernel(const double *__restrict__ A, const double *__restrict__ B,
                                                            double *__restrict__ C, int64_t m, int64_t n, int64_t p,
@@ -445,20 +445,23 @@ __global__ __launch_bounds__(256, 2) void onf64_ring_kernel(const double *__rest
     // the compiler sees the reads need not wait for those loads, which are
     // meant to stay in flight (the explicit wait before the barrier orders
     // slab s's own loads).
+    constexpr int NST = ONF64_NST;
+    static_assert(NST >= 3 && NST <= 4, "waits cover up to two later slabs");
     auto step = [&](uint8_t *__restrict__ dma, const uint8_t *__restrict__ cur, int64_t s) {
-        if (s + 2 < S) issue_to(dma, s + 2);
+        if (s + NST - 1 < S) issue_to(dma, s + NST - 1);
         compute_full(cur);
     };
     const int64_t full = n / BK;
-    if (S > 0) {
-        issue_to(lds, 0);
-        if (S > 1) issue_to(lds + STAGE, 1);
-    }
+    for (int q = 0; q < NST - 1; ++q)
+        if (q < S) issue_to(lds + q * STAGE, q);
     for (int64_t s = 0; s < full; ++s) {
-        if (s + 1 < S) __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(LPW));
+        // slab s landed; at most NST - 2 later slabs of this wave in flight
+        const int64_t ahead = S - 1 - s < NST - 2 ? S - 1 - s : NST - 2;
+        if (ahead >= 2) __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(2 * LPW));
+        else if (ahead == 1) __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(LPW));
         else __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(0));
         ring::ring_barrier();
-        step(lds + ((s + 2) % ONF64_NST) * STAGE, lds + (s % ONF64_NST) * STAGE, s);
+        step(lds + ((s + NST - 1) % NST) * STAGE, lds + (s % NST) * STAGE, s);
     }
     if (full < S) {
         __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(0));

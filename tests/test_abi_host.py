@@ -149,7 +149,7 @@ def test_onf_f64_ring_plan():
     q = lambda m, n, p, fl=0: moa.moa_plan_query(_desc(m, n, p, F64, ONF, flags=fl))  # noqa: E731
     big = q(8192, 8192, 8192)
     assert big["variant"] == 4 and (big["tile_m"], big["tile_n"], big["tile_k"]) == (128, 128, 8)
-    assert (big["lane_m"], big["lane_n"]) == (8, 8) and big["lds_bytes"] == 3 * 16384
+    assert (big["lane_m"], big["lane_n"]) == (8, 8) and big["lds_bytes"] == 4 * 16384
     assert q(2048, 2048, 2048)["variant"] == 4                   # 256 blocks
     assert q(2048, 2048, 1920)["variant"] != 4                   # 240 blocks
     assert q(256, 256, 256)["variant"] == 0                      # the static rule's 32 x 32 block
