@@ -129,8 +129,8 @@ class TraceScope {
 hipError_t launch_onf(const moa_gemm_desc &d, const Plan &plan, hipStream_t stream);
 int onf_variant_count(moa_dtype t);
 void onf_variant_shape(moa_dtype t, int v, Plan *p);
-int onf_f64_ring_variant();                  // the FP64 direct-load ring kernel (row-major operands)
-bool onf_f64_ring_fits(int64_t n, int64_t p);
+int onf_ring_variant(moa_dtype t);           // the direct-load ring kernel (row-major operands)
+bool onf_ring_fits(moa_dtype t, int64_t n, int64_t p);
 
 // FP32 matrix cores: variants 0, 1 run the record ring (workspace for the
 // records), mfma_f32_staged_variant() the register-staged kernel (none).

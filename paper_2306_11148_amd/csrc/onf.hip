@@ -295,56 +295,66 @@ __global__ __launch_bounds__(256) void onf_kernel(const T *__restrict__ A,
     }
 }
 
-// FP64 on a direct-load LDS ring: 128 x 128 blocks of C, 8 x 8 elements per
-// lane. A lane reads 2 doubles of LDS per FMA-pair of work (8 of A and 8 of B
-// per k for 64 FMAs: 2 bytes per FMA, which the LDS delivers at the FP64 FMA
-// rate), where the register-staged kernel's 4 x 8 lane block reads 3; the
-// slabs go from memory straight into LDS (`buffer_load ... lds`, 8 k per
-// slab, four slabs in the ring), so no registers hold them in flight and the
-// 64 accumulator pairs fit two waves per SIMD. Per slab:
-//   A: 128 rows of 64 bytes (8 doubles), 16-byte chunk c of row r at physical
-//      chunk c ^ ((r / 4) mod 4);
-//   B: the slab's 8 rows of 128 doubles, one KiB each.
-// Rows past m and slab rows past n read as zeros (buffer ranges); columns past
-// p are never stored. The k loop is the same ascending fma sequence per
-// element as the register-staged kernel, and the last slab stops at n (no
-// padded steps), so results are bitwise the same.
-constexpr int ONF64_NST = 4;
+// ONF on a direct-load LDS ring. A slab is one 64-byte row of A per row of
+// the block (BK = 8 doubles or 16 floats of k) and the matching BK rows of B;
+// the slabs go from memory straight into LDS (`buffer_load ... lds`), so no
+// registers hold them in flight and a lane can keep a large block of C:
+// 128 x 128 blocks, 8 x 8 per lane (8 + 8 elements of LDS per k for 64
+// FMAs: 2 bytes per FMA in FP64, which the LDS delivers at the FP64 FMA rate,
+// 1 byte in FP32; a 16 x 8 FP32 lane block would need more than 256
+// registers). Per slab:
+//   A: TM rows of 64 bytes, 16-byte chunk c of row r at physical chunk
+//      c ^ ((r / 4) mod 4) (conflict-free reads by rows of lanes);
+//   B: the slab's BK rows of TN elements, contiguous.
+// Lane (tr, tc) owns rows tr + TR q of the block and, for each 16-byte chunk
+// g of its columns, elements (g TC + tc) (16 / size) + u. Rows past m and
+// slab rows past n read as zeros (buffer ranges); columns past p are never
+// stored. The k loop is the same ascending fma sequence per element as the
+// register-staged kernel, and the last slab stops at n (no padded steps), so
+// results are bitwise the same.
+constexpr int ONF64_NST = 4, ONF32_NST = 4;
 
-__global__ __launch_bounds__(256, 2) void onf64_ring_kernel(const double *__restrict__ A, const double *__restrict__ B,
-                                                           double *__restrict__ C, int64_t m, int64_t n, int64_t p,
-                                                           int accumulate, int vec_c) {
-    constexpr int TM = 128, TN = 128, BK = 8, R = 8, VJ = 8, TR = 16, TC = 16;
-    constexpr int A_BYTES = TM * BK * 8, B_BYTES = BK * TN * 8, STAGE = A_BYTES + B_BYTES, LPW = 4;
-    static_assert(STAGE / 1024 == 4 * LPW, "four waves, LPW KiB loads each");
-    __shared__ __attribute__((aligned(1024))) uint8_t lds[ONF64_NST * STAGE];
+// N elements of T as one vector register value
+template <typename T, int N> struct ExtVec { typedef T type __attribute__((ext_vector_type(N))); };
+
+template <typename T, int TM, int TN, int R, int VJ, int NST>
+__device__ __forceinline__ void onf_ring_block(const T *__restrict__ A, const T *__restrict__ B, T *__restrict__ C,
+                                               int64_t m, int64_t n, int64_t p, int accumulate, int vec_c,
+                                               uint8_t *lds) {
+    constexpr int ES = (int)sizeof(T), BK = 64 / ES, EPC = 16 / ES;   // k per slab, elements per 16-byte chunk
+    constexpr int TR = TM / R, TC = TN / VJ, GC = VJ / EPC;           // lane rows, lane columns, chunks per lane
+    constexpr int A_BYTES = TM * 64, B_BYTES = BK * TN * ES, STAGE = A_BYTES + B_BYTES;
+    constexpr int LPW = STAGE / 1024 / 4;                                // KiB loads per wave per slab
+    constexpr int RPL = 1024 / (TN * ES), CPR = TN * ES / 16;           // B rows per load, chunks per B row
+    static_assert(TR * TC == 256 && STAGE % 4096 == 0 && VJ % EPC == 0 && RPL >= 1, "shape of the ONF ring");
+    static_assert(NST >= 3 && NST <= 4, "waits cover up to two later slabs");
     const int t = threadIdx.x, lane = t & 63;
     const int wave = __builtin_amdgcn_readfirstlane(t >> 6);
     const int tr = t / TC, tc = t % TC;
     const int64_t i0 = (int64_t)blockIdx.y * TM, j0 = (int64_t)blockIdx.x * TN;
+    auto col = [&](int v) { return (v / EPC * TC + tc) * EPC + v % EPC; };   // lane column v in the block
 
-    // the accumulate form starts from C (lane columns j0 + 32 g + 2 tc + {0, 1})
-    double acc[R][VJ];
+    // the accumulate form starts from C
+    T acc[R][VJ];
 #pragma unroll
     for (int q = 0; q < R; ++q)
 #pragma unroll
-        for (int v = 0; v < VJ; ++v) acc[q][v] = 0.0;
+        for (int v = 0; v < VJ; ++v) acc[q][v] = T(0);
     if (accumulate) {
 #pragma unroll
         for (int q = 0; q < R; ++q) {
             const int64_t i = i0 + tr + TR * q;
             if (i >= m) continue;
-            const double *row = C + i * p + j0 + 2 * tc;
 #pragma unroll
             for (int v = 0; v < VJ; ++v) {
-                const int64_t j = j0 + 32 * (v >> 1) + 2 * tc + (v & 1);
-                if (j < p) acc[q][v] = row[32 * (v >> 1) + (v & 1)];
+                const int64_t j = j0 + col(v);
+                if (j < p) acc[q][v] = C[i * p + j];
             }
         }
     }
 
     const int64_t rows_live = m - i0 < TM ? m - i0 : TM;
-    const int64_t a_range = rows_live * n * 8;
+    const int64_t a_range = rows_live * n * ES;
     const int64_t b_total = n * p - j0;        // elements from B + j0 to the end of B
     const int64_t S = (n + BK - 1) / BK;
 
@@ -359,15 +369,15 @@ __global__ __launch_bounds__(256, 2) void onf64_ring_kernel(const double *__rest
         if (g < A_BYTES / 1024) {
             const int r = 16 * g + (lane >> 2);
             const int c = (lane & 3) ^ ((lane >> 4) & 3);
-            voff[q] = r < rows_live ? (int)(((int64_t)r * n + 2 * c) * 8) : ring::kDeadVoffset;
+            voff[q] = r < rows_live ? (int)(((int64_t)r * n + EPC * c) * ES) : ring::kDeadVoffset;
         } else {
-            const int h = g - A_BYTES / 1024;              // slab row h: 128 doubles, 2 per lane
-            voff[q] = (int)(((int64_t)h * p + 2 * lane) * 8);
+            const int row = (g - A_BYTES / 1024) * RPL + lane / CPR;
+            voff[q] = (int)(((int64_t)row * p + EPC * (lane % CPR)) * ES);
         }
     }
-    auto issue_to = [&](uint8_t *buf, int64_t s) {     // buf: stage s mod ONF64_NST
+    auto issue_to = [&](uint8_t *buf, int64_t s) {     // buf: stage s mod NST
         const int64_t k0 = s * BK;
-        const int64_t a_left = a_range - k0 * 8, b_left = (b_total - k0 * p) * 8;
+        const int64_t a_left = a_range - k0 * ES, b_left = (b_total - k0 * p) * ES;
         const __amdgpu_buffer_rsrc_t a_rsrc = __builtin_amdgcn_make_buffer_rsrc(
             (void *)(A + i0 * n + k0), (short)0, (int)(a_left > 0 ? a_left : 0), 0x00020000);
         const __amdgpu_buffer_rsrc_t b_rsrc = __builtin_amdgcn_make_buffer_rsrc(
@@ -384,31 +394,40 @@ __global__ __launch_bounds__(256, 2) void onf64_ring_kernel(const double *__rest
         }
     };
 
-    // one whole slab (8 k, ascending) from `buf`
+    // two elements of A row r at k, k + 1 (k even)
+    using pair_t = typename ExtVec<T, 2>::type;
+    using chunk_t = typename ExtVec<T, EPC>::type;
+    auto a_pair = [&](const uint8_t *buf, int r, int k) {
+        const int byte = k * ES;
+        return *reinterpret_cast<const pair_t *>(buf + r * 64 + ((((byte >> 4) ^ ((r >> 2) & 3))) << 4) + (byte & 15));
+    };
+    // a lane's VJ elements of B row k
+    auto b_row = [&](const uint8_t *bs, int k, T (&b)[VJ]) {
+#pragma unroll
+        for (int g = 0; g < GC; ++g) {
+            const chunk_t v = *reinterpret_cast<const chunk_t *>(bs + k * TN * ES + (g * TC + tc) * 16);
+#pragma unroll
+            for (int u = 0; u < EPC; ++u) b[g * EPC + u] = v[u];
+        }
+    };
+
+    // one whole slab (BK k, ascending) from `buf`
     auto compute_full = [&](const uint8_t *buf) {
         const uint8_t *bs = buf + A_BYTES;
 #pragma unroll
         for (int kk = 0; kk < BK; kk += 2) {
-            double2 av[R];
+            pair_t av[R];
 #pragma unroll
-            for (int q = 0; q < R; ++q) {
-                const int r = tr + TR * q;
-                av[q] = *reinterpret_cast<const double2 *>(buf + r * 64 + (((kk >> 1) ^ ((r >> 2) & 3)) << 4));
-            }
+            for (int q = 0; q < R; ++q) av[q] = a_pair(buf, tr + TR * q, kk);
 #pragma unroll
             for (int e = 0; e < 2; ++e) {
-                double b[VJ];
-#pragma unroll
-                for (int g = 0; g < VJ / 2; ++g) {
-                    const double2 bv = *reinterpret_cast<const double2 *>(bs + (kk + e) * 1024 + (32 * g + 2 * tc) * 8);
-                    b[2 * g] = bv.x;
-                    b[2 * g + 1] = bv.y;
-                }
+                T b[VJ];
+                b_row(bs, kk + e, b);
 #pragma unroll
                 for (int q = 0; q < R; ++q) {
-                    const double a = e ? av[q].y : av[q].x;
+                    const T a = e ? av[q].y : av[q].x;
 #pragma unroll
-                    for (int v = 0; v < VJ; ++v) acc[q][v] = __builtin_fma(a, b[v], acc[q][v]);
+                    for (int v = 0; v < VJ; ++v) acc[q][v] = fma_t(a, b[v], acc[q][v]);
                 }
             }
         }
@@ -417,40 +436,31 @@ __global__ __launch_bounds__(256, 2) void onf64_ring_kernel(const double *__rest
     auto compute_tail = [&](const uint8_t *buf, int kc) {
         const uint8_t *bs = buf + A_BYTES;
         for (int kk = 0; kk < kc; ++kk) {
-            double a[R], b[VJ];
+            T a[R], b[VJ];
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-                const int r = tr + TR * q;
-                const double2 v2 = *reinterpret_cast<const double2 *>(buf + r * 64 + (((kk >> 1) ^ ((r >> 2) & 3)) << 4));
+                const pair_t v2 = a_pair(buf, tr + TR * q, kk & ~1);
                 a[q] = (kk & 1) ? v2.y : v2.x;
             }
-#pragma unroll
-            for (int g = 0; g < VJ / 2; ++g) {
-                const double2 bv = *reinterpret_cast<const double2 *>(bs + kk * 1024 + (32 * g + 2 * tc) * 8);
-                b[2 * g] = bv.x;
-                b[2 * g + 1] = bv.y;
-            }
+            b_row(bs, kk, b);
 #pragma unroll
             for (int q = 0; q < R; ++q)
 #pragma unroll
-                for (int v = 0; v < VJ; ++v) acc[q][v] = __builtin_fma(a[q], b[v], acc[q][v]);
+                for (int v = 0; v < VJ; ++v) acc[q][v] = fma_t(a[q], b[v], acc[q][v]);
         }
     };
 
-    // Per slab: slab s has landed in every wave (at most slab s + 1 still in
-    // flight) and every wave is done with slab s - 1, whose buffer slab
-    // s + 2 then takes.
-    // One step: the stage the step's loads fill (slab s + 2) and the stage it
-    // computes (slab s) are disjoint LDS, passed as restrict pointers so that
-    // the compiler sees the reads need not wait for those loads, which are
-    // meant to stay in flight (the explicit wait before the barrier orders
-    // slab s's own loads).
-    constexpr int NST = ONF64_NST;
-    static_assert(NST >= 3 && NST <= 4, "waits cover up to two later slabs");
+    // One step: the stage the step's loads fill (slab s + NST - 1) and the
+    // stage it computes (slab s) are disjoint LDS, passed as restrict
+    // pointers so that the compiler sees the reads need not wait for those
+    // loads, which are meant to stay in flight (the explicit wait before the
+    // barrier orders slab s's own loads).
     auto step = [&](uint8_t *__restrict__ dma, const uint8_t *__restrict__ cur, int64_t s) {
         if (s + NST - 1 < S) issue_to(dma, s + NST - 1);
         compute_full(cur);
     };
+    // Per slab: slab s has landed in every wave and every wave is done with
+    // slab s - 1, whose stage slab s + NST - 1 then takes.
     const int64_t full = n / BK;
     for (int q = 0; q < NST - 1; ++q)
         if (q < S) issue_to(lds + q * STAGE, q);
@@ -466,7 +476,7 @@ __global__ __launch_bounds__(256, 2) void onf64_ring_kernel(const double *__rest
     if (full < S) {
         __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(0));
         ring::ring_barrier();
-        compute_tail(lds + (full % ONF64_NST) * STAGE, (int)(n - full * BK));
+        compute_tail(lds + (full % NST) * STAGE, (int)(n - full * BK));
     }
 
 #pragma unroll
@@ -474,25 +484,39 @@ __global__ __launch_bounds__(256, 2) void onf64_ring_kernel(const double *__rest
         const int64_t i = i0 + tr + TR * q;
         if (i >= m) continue;
 #pragma unroll
-        for (int g = 0; g < VJ / 2; ++g) {
-            const int64_t j = j0 + 32 * g + 2 * tc;
-            if (vec_c && j + 2 <= p) {
-                *reinterpret_cast<double2 *>(C + i * p + j) = make_double2(acc[q][2 * g], acc[q][2 * g + 1]);
+        for (int g = 0; g < GC; ++g) {
+            const int64_t j = j0 + (g * TC + tc) * EPC;
+            if (vec_c && j + EPC <= p) {
+                chunk_t v;
+#pragma unroll
+                for (int u = 0; u < EPC; ++u) v[u] = acc[q][g * EPC + u];
+                *reinterpret_cast<chunk_t *>(C + i * p + j) = v;
             } else {
-                if (j < p) C[i * p + j] = acc[q][2 * g];
-                if (j + 1 < p) C[i * p + j + 1] = acc[q][2 * g + 1];
+#pragma unroll
+                for (int u = 0; u < EPC; ++u)
+                    if (j + u < p) C[i * p + j + u] = acc[q][g * EPC + u];
             }
         }
     }
 }
 
-hipError_t launch_onf64_ring(const moa_gemm_desc &d, hipStream_t st) {
-    const double *A = static_cast<const double *>(d.A);
-    const double *B = static_cast<const double *>(d.B);
-    double *C = static_cast<double *>(d.C);
-    const int vec_c = (d.p % 2 == 0) && ((uintptr_t)C % 16 == 0);
-    dim3 grid((unsigned)((d.p + 127) / 128), (unsigned)((d.m + 127) / 128));
-    hipLaunchKernelGGL(onf64_ring_kernel, grid, dim3(256), 0, st, A, B, C, d.m, d.n, d.p, d.accumulate, vec_c);
+template <typename T, int TM, int TN, int R, int VJ, int NST>
+__global__ __launch_bounds__(256, 2) void onf_ring_kernel(const T *__restrict__ A, const T *__restrict__ B,
+                                                         T *__restrict__ C, int64_t m, int64_t n, int64_t p,
+                                                         int accumulate, int vec_c) {
+    __shared__ __attribute__((aligned(1024))) uint8_t lds[NST * (TM * 64 + 64 / sizeof(T) * TN * sizeof(T))];
+    onf_ring_block<T, TM, TN, R, VJ, NST>(A, B, C, m, n, p, accumulate, vec_c, lds);
+}
+
+template <typename T, int TM, int TN, int R, int VJ, int NST>
+hipError_t launch_ring(const moa_gemm_desc &d, hipStream_t st) {
+    const T *A = static_cast<const T *>(d.A);
+    const T *B = static_cast<const T *>(d.B);
+    T *C = static_cast<T *>(d.C);
+    const int vec_c = (d.p % (16 / (int)sizeof(T)) == 0) && ((uintptr_t)C % 16 == 0);
+    dim3 grid((unsigned)((d.p + TN - 1) / TN), (unsigned)((d.m + TM - 1) / TM));
+    hipLaunchKernelGGL((onf_ring_kernel<T, TM, TN, R, VJ, NST>), grid, dim3(256), 0, st, A, B, C, d.m, d.n, d.p,
+                       d.accumulate, vec_c);
     return hipGetLastError();
 }
 
@@ -502,10 +526,12 @@ struct OnfShape { int tm, tn, bk, r, vj; };
 // for the 32 KB vector L1 (three blocks of A, B and C): 1024 FP64 components
 // (32 x 32) and 2048 FP32 components (32 x 64). Larger entries trade LDS for
 // register blocking; the planner picks among them.
-// FP64 entry 4 is the direct-load ring kernel above (row-major operands).
+// The last entry per type is the direct-load ring kernel above (row-major
+// operands).
 constexpr OnfShape kF64[] = {{32, 32, 16, 2, 2}, {64, 64, 16, 4, 4}, {64, 128, 16, 4, 8}, {128, 128, 16, 8, 8},
                              {128, 128, 8, 8, 8}};
-constexpr OnfShape kF32[] = {{32, 64, 16, 2, 4}, {64, 64, 16, 4, 4}, {64, 128, 16, 4, 8}, {128, 128, 16, 8, 8}};
+constexpr OnfShape kF32[] = {{32, 64, 16, 2, 4}, {64, 64, 16, 4, 4}, {64, 128, 16, 4, 8}, {128, 128, 16, 8, 8},
+                             {128, 128, 16, 8, 8}};
 
 template <typename T, int TM, int TN, int BK, int R, int VJ>
 hipError_t launch_one(const moa_gemm_desc &d, hipStream_t st) {
@@ -544,14 +570,17 @@ void onf_variant_shape(moa_dtype t, int v, Plan *p) {
     p->wave_n = s.tn;
     p->threads = 256;
     p->lds_bytes = 2 * (s.tm * (s.bk + 16 / es) + s.bk * s.tn) * es;
-    if (t == MOA_F64 && v == onf_f64_ring_variant()) p->lds_bytes = ONF64_NST * (s.tm + s.tn) * s.bk * es;
+    if (v == onf_ring_variant(t)) p->lds_bytes = (t == MOA_F64 ? ONF64_NST : ONF32_NST) * (s.tm + s.tn) * s.bk * es;
 }
 
-int onf_f64_ring_variant() { return 4; }
+int onf_ring_variant(moa_dtype t) { return onf_variant_count(t) - 1; }
 
-// The ring kernel's 32-bit buffer offsets: 128 rows of n doubles of A, 8 rows
-// of p doubles of B.
-bool onf_f64_ring_fits(int64_t n, int64_t p) { return 130 * n * 8 < 0x7FFFFFFF && 9 * p * 8 < 0x7FFFFFFF; }
+// The ring kernel's 32-bit buffer offsets: 130 rows of n elements of A,
+// BK + 1 rows of p elements of B (BK 8 in FP64, 16 in FP32).
+bool onf_ring_fits(moa_dtype t, int64_t n, int64_t p) {
+    return t == MOA_F64 ? 130 * n * 8 < 0x7FFFFFFF && 9 * p * 8 < 0x7FFFFFFF
+                        : 130 * n * 4 < 0x7FFFFFFF && 17 * p * 4 < 0x7FFFFFFF;
+}
 
 hipError_t launch_onf(const moa_gemm_desc &d, const Plan &plan, hipStream_t st) {
     if (d.dtype == MOA_F64) {
@@ -560,14 +589,15 @@ hipError_t launch_onf(const moa_gemm_desc &d, const Plan &plan, hipStream_t st) 
         case 1: return launch_one<double, 64, 64, 16, 4, 4>(d, st);
         case 2: return launch_one<double, 64, 128, 16, 4, 8>(d, st);
         case 3: return launch_one<double, 128, 128, 16, 8, 8>(d, st);
-        default: return launch_onf64_ring(d, st);
+        default: return launch_ring<double, 128, 128, 8, 8, ONF64_NST>(d, st);
         }
     }
     switch (plan.variant) {
     case 0: return launch_one<float, 32, 64, 16, 2, 4>(d, st);
     case 1: return launch_one<float, 64, 64, 16, 4, 4>(d, st);
     case 2: return launch_one<float, 64, 128, 16, 4, 8>(d, st);
-    default: return launch_one<float, 128, 128, 16, 8, 8>(d, st);
+    case 3: return launch_one<float, 128, 128, 16, 8, 8>(d, st);
+    default: return launch_ring<float, 128, 128, 8, 8, ONF32_NST>(d, st);
     }
 }
 

@@ -206,25 +206,30 @@ moa_status make_plan(const moa_gemm_desc &d_in, Plan *out) {
     case MOA_PATH_ONF: {
         pl.kernel = d.dtype == MOA_F64 ? K_ONF_F64 : K_ONF_F32;
         const int nv = onf_variant_count((moa_dtype)d.dtype);
-        // the FP64 ring kernel reads row-major operands with 32-bit offsets
-        const int ring = d.dtype == MOA_F64 ? onf_f64_ring_variant() : -1;
-        const bool ring_ok = ring >= 0 && !has_col_operand(d) && onf_f64_ring_fits(d.n, d.p);
+        // the ring kernels read row-major operands with 32-bit offsets
+        const int ring = onf_ring_variant((moa_dtype)d.dtype);
+        const bool ring_ok = !has_col_operand(d) && onf_ring_fits((moa_dtype)d.dtype, d.n, d.p);
         int v = 0;
         if (forced >= 0) {
             if (forced >= nv) return fail(MOA_ERR_INVALID, "variant %d out of range (ONF has %d)", forced, nv);
             if (forced == ring && !ring_ok)
-                return fail(MOA_ERR_UNSUPPORTED, "the FP64 ring variant takes row-major operands with n < 2^21");
+                return fail(MOA_ERR_UNSUPPORTED, "the ONF ring variant takes row-major operands whose rows fit "
+                            "32-bit offsets");
             v = forced;
         } else if ((v = tuned_variant(d, pl.path)) >= 0 && (v != ring || ring_ok)) {
             pl.tuned = true;
-        } else if (ring_ok && tiles_for(d.m, d.p, 128, 128) >= kNumCUs) {
+        } else if (ring_ok && [&] {
+                       Plan r;
+                       onf_variant_shape((moa_dtype)d.dtype, ring, &r);
+                       return tiles_for(d.m, d.p, r.tile_m, r.tile_n) >= kNumCUs;
+                   }()) {
             v = ring;
         } else {
             v = 0;
             // register-staged blocks: the largest that still gives every CU a
             // block; FP64 stops at 64 x 128 (its 128 x 128 block needs more
             // registers than two waves per SIMD allow and measured slower)
-            const int top = d.dtype == MOA_F64 ? 2 : nv - 1;
+            const int top = d.dtype == MOA_F64 ? 2 : ring - 1;
             for (int c = top; c >= 0; --c) {
                 Plan t;
                 onf_variant_shape((moa_dtype)d.dtype, c, &t);

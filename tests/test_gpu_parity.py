@@ -96,8 +96,9 @@ def onf_variants(dt):
 @pytest.mark.parametrize("dt", [np.float64, np.float32])
 def test_onf_every_block_size_is_bitwise_the_same(dt, shape):
     """Changing the dimension lift (block sizes) never changes a result:
-    every variant (FP64 also its direct-load ring kernel: whole 8-k slabs,
-    a partial last slab, n < 8), overwrite and accumulate, bitwise the
+    every variant (also the direct-load ring kernels: whole 8-k or 16-k
+    slabs, a partial last slab, n below one slab), overwrite and accumulate,
+    bitwise the
     fma-ordered oracle -- including a zero row of A over a -0 row of C,
     where one padded k step would turn -0 into +0."""
     m, n, p = shape
@@ -109,7 +110,7 @@ def test_onf_every_block_size_is_bitwise_the_same(dt, shape):
     ref = O.gemm_f64_fma(A, B) if dt == np.float64 else O.gemm_f32_fma(A, B)
     ref_acc = O.gemm_f64_fma(A, B, C0, True) if dt == np.float64 else O.gemm_f32_fma(A, B, C0, True)
     count = onf_variants(dt)
-    assert count == (5 if dt == np.float64 else 4)
+    assert count == 5
     for v in range(count):
         fl = moa.MOA_FLAG_VARIANT(v)
         got, got_acc = run(A, B, "onf", flags=fl), run(A, B, "onf", accumulate=True, C0=C0, flags=fl)
