@@ -394,12 +394,10 @@ __device__ __forceinline__ void onf_ring_block(const T *__restrict__ A, const T 
         }
     };
 
-    // two elements of A row r at k, k + 1 (k even)
-    using pair_t = typename ExtVec<T, 2>::type;
+    // the 16-byte chunk of A row r holding k .. k + EPC - 1 (k a multiple of EPC)
     using chunk_t = typename ExtVec<T, EPC>::type;
-    auto a_pair = [&](const uint8_t *buf, int r, int k) {
-        const int byte = k * ES;
-        return *reinterpret_cast<const pair_t *>(buf + r * 64 + ((((byte >> 4) ^ ((r >> 2) & 3))) << 4) + (byte & 15));
+    auto a_chunk = [&](const uint8_t *buf, int r, int k) {
+        return *reinterpret_cast<const chunk_t *>(buf + r * 64 + (((k / EPC) ^ ((r >> 2) & 3)) << 4));
     };
     // a lane's VJ elements of B row k
     auto b_row = [&](const uint8_t *bs, int k, T (&b)[VJ]) {
@@ -415,17 +413,17 @@ __device__ __forceinline__ void onf_ring_block(const T *__restrict__ A, const T 
     auto compute_full = [&](const uint8_t *buf) {
         const uint8_t *bs = buf + A_BYTES;
 #pragma unroll
-        for (int kk = 0; kk < BK; kk += 2) {
-            pair_t av[R];
+        for (int kk = 0; kk < BK; kk += EPC) {
+            chunk_t av[R];
 #pragma unroll
-            for (int q = 0; q < R; ++q) av[q] = a_pair(buf, tr + TR * q, kk);
+            for (int q = 0; q < R; ++q) av[q] = a_chunk(buf, tr + TR * q, kk);
 #pragma unroll
-            for (int e = 0; e < 2; ++e) {
+            for (int e = 0; e < EPC; ++e) {
                 T b[VJ];
                 b_row(bs, kk + e, b);
 #pragma unroll
                 for (int q = 0; q < R; ++q) {
-                    const T a = e ? av[q].y : av[q].x;
+                    const T a = av[q][e];
 #pragma unroll
                     for (int v = 0; v < VJ; ++v) acc[q][v] = fma_t(a, b[v], acc[q][v]);
                 }
@@ -439,8 +437,8 @@ __device__ __forceinline__ void onf_ring_block(const T *__restrict__ A, const T 
             T a[R], b[VJ];
 #pragma unroll
             for (int q = 0; q < R; ++q) {
-                const pair_t v2 = a_pair(buf, tr + TR * q, kk & ~1);
-                a[q] = (kk & 1) ? v2.y : v2.x;
+                const chunk_t c = a_chunk(buf, tr + TR * q, kk - kk % EPC);
+                a[q] = c[kk % EPC];
             }
             b_row(bs, kk, b);
 #pragma unroll
