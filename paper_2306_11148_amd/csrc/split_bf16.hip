@@ -321,50 +321,58 @@ __device__ __forceinline__ void raw_tile(const GroupMember &d, int64_t i0, int64
     const int L = (int)d.S;
     const int64_t n = d.n, p = d.p;
 
-    // A: one resource over the tile's live rows; lane offsets advance by 64
-    // bytes per slab. Rows past m and k past the last live row's end are out
-    // of range (zeros); k past n inside earlier rows reads the next row and is
-    // masked when split.
+    // Both resources start at the slab (A: column k0 of the tile's first row,
+    // B: row k0) and end where the live data ends, so each lane's vector
+    // offset is the same for every slab (computed once, in registers that no
+    // later instruction overwrites). Rows past m and k past the last live
+    // row's end are out of range (zeros); k past n inside earlier rows reads
+    // the next row and is masked when split.
     const int64_t rows_live = d.m - i0 < BM ? d.m - i0 : BM;
     const int64_t a_range = rows_live * n * 4;
-    const __amdgpu_buffer_rsrc_t a_rsrc = __builtin_amdgcn_make_buffer_rsrc(
-        (void *)(d.A + i0 * n), (short)0, (int)(a_range < 0x7FFFFFFF ? a_range : 0x7FFFFFFF), 0x00020000);
+    const float *a_tile = d.A + i0 * n;
     const float *b_tile = d.B + j0;
     const int64_t b_total = n * p - j0;                  // elements from b_tile to the end of B
+    int voff[LPW];
+#pragma unroll
+    for (int q = 0; q < LPW; ++q) {
+        const int g = wave * LPW + q;                    // wave-uniform load index
+        if (g < BM / 16) {
+            const int r = 16 * g + (lane >> 2);
+            const int c = (lane & 3) ^ ((lane >> 4) & 3);
+            voff[q] = r < rows_live ? (int)(((int64_t)r * n + 4 * c) * 4) : ring::kDeadVoffset;
+        } else {
+            const int h = g - BM / 16;                   // pair h: rows h and h + 8 of the slab
+            const int upper = lane >> 5;
+            const int gc = upper ? ((lane & 31) + 8) & 31 : lane & 31;
+            voff[q] = (int)(((int64_t)(h + 8 * upper) * p + 4 * gc) * 4);
+        }
+    }
 
-    auto issue = [&](int s) {
-        uint8_t *buf = lds + (s % NST) * STAGE;
+    auto issue_to = [&](uint8_t *buf, int s) {         // buf: stage s mod NST
         const int64_t k0 = (int64_t)s * SLAB;
+        const int64_t a_left = a_range - k0 * 4, b_left = (b_total - k0 * p) * 4;
+        const __amdgpu_buffer_rsrc_t a_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(a_tile + k0), (short)0, (int)(a_left > 0 ? a_left : 0), 0x00020000);
+        const __amdgpu_buffer_rsrc_t b_rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            (void *)(b_tile + k0 * p), (short)0,
+            (int)(b_left < 0x7FFFFFFF ? (b_left > 0 ? b_left : 0) : 0x7FFFFFFF), 0x00020000);
 #pragma unroll
         for (int q = 0; q < LPW; ++q) {
-            const int g = wave * LPW + q;                // wave-uniform load index
-            if (g < BM / 16) {
-                const int r = 16 * g + (lane >> 2);
-                const int c = (lane & 3) ^ ((lane >> 4) & 3);
-                const int voff = r < rows_live ? (int)(((int64_t)r * n + k0 + 4 * c) * 4) : ring::kDeadVoffset;
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(a_rsrc, (ring::lds_void_t *)(buf + g * 1024), 16, voff,
+            const int g = wave * LPW + q;
+            if (g < BM / 16)
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(a_rsrc, (ring::lds_void_t *)(buf + g * 1024), 16, voff[q],
                                                          0, 0, 0);
-            } else {
-                const int h = g - BM / 16;               // pair h: rows h and h + 8 of the slab
-                const int upper = lane >> 5;
-                const int gc = upper ? ((lane & 31) + 8) & 31 : lane & 31;
-                const int64_t rel = (k0 + h + 8 * upper) * p + 4 * gc;
-                const int64_t left = b_total - k0 * p;   // elements from row k0 on
-                const __amdgpu_buffer_rsrc_t b_rsrc = __builtin_amdgcn_make_buffer_rsrc(
-                    (void *)(b_tile + k0 * p), (short)0,
-                    (int)(left * 4 < 0x7FFFFFFF ? (left > 0 ? left * 4 : 0) : 0x7FFFFFFF), 0x00020000);
-                const int voff = (int)((rel - k0 * p) * 4);
-                __builtin_amdgcn_raw_ptr_buffer_load_lds(b_rsrc, (ring::lds_void_t *)(buf + G::A_BYTES + h * 1024),
-                                                         16, voff, 0, 0, 0);
-            }
+            else
+                __builtin_amdgcn_raw_ptr_buffer_load_lds(b_rsrc,
+                                                         (ring::lds_void_t *)(buf + G::A_BYTES + (g - BM / 16) * 1024),
+                                                         16, voff[q], 0, 0, 0);
         }
     };
 
     const int frow = lane & 31, fhalf = lane >> 5;
     float ra[FM][8], rb[FN][8];
-    // raw fragments of slab s: A rows (8 k of half fhalf), B columns (8 k rows)
-    auto read_raw = [&](int s) {
-        const uint8_t *buf = lds + (s % NST) * STAGE;
+    // raw fragments of a slab (in buf): A rows (8 k of half fhalf), B columns (8 k rows)
+    auto read_raw_from = [&](const uint8_t *buf) {
 #pragma unroll
         for (int a = 0; a < FM; ++a) {
             const int r = wm * WM + a * 32 + frow;
@@ -418,20 +426,26 @@ __device__ __forceinline__ void raw_tile(const GroupMember &d, int64_t i0, int64
     };
     static_assert(NST >= 3 && NST <= 4, "up to two slabs in flight");
 
+    // the loads of a step fill one stage while the fragments of the next
+    // slab are read from another: disjoint LDS, passed as restrict pointers
+    // so that the reads need not wait for those loads
+    auto step = [&](uint8_t *__restrict__ dma, const uint8_t *__restrict__ src, int s) {
+        if (s + NST - 1 < L) issue_to(dma, s + NST - 1);
+        read_raw_from(src);
+    };
     if (L > 0) {
         for (int q = 0; q < NST - 1; ++q)
-            if (q < L) issue(q);
+            if (q < L) issue_to(lds + q * STAGE, q);
         wait_loads(min(NST - 2, L - 1));
         ring::ring_barrier();
-        read_raw(0);
+        read_raw_from(lds);
         convert(0);
         for (int s = 0; s < L; ++s) {
             if (s + 1 < L) {
                 // slab s + 1 landed in every wave; the buffer of slab s - 1 is free
                 wait_loads(min(NST - 3, L - s - 2));
                 ring::ring_barrier();
-                if (s + NST - 1 < L) issue(s + NST - 1);
-                read_raw(s + 1);
+                step(lds + ((s + NST - 1) % NST) * STAGE, lds + ((s + 1) % NST) * STAGE, s);
             }
             SplitMode::mma<FM, FN>(f, acc);
             if (s + 1 < L) convert(s + 1);
