@@ -272,7 +272,7 @@ def cpu_baseline(A, B, C_gpu, n, target_s, onf_rows=None, precision=None):
     if precision is not None:
         pA, pB, p_rows, kept = precision
         Rp = O.gemm_rows_f64(pA.astype(np.float64), pB.astype(np.float64), p_rows)
-        errs["precision"] = {k: O.rel_err(v, Rp) for k, v in kept.items()}
+        errs["precision"] = {k: (O.rel_err(v, Rp), O.max_row_rel_err(v, Rp)) for k, v in kept.items()}
     return {"value": flops / done_t / 1e12, "unit": "TFLOP/s", "cores": threads, "kind": "oracle",
             "sample": f"{len(all_rows)} seeded rows of the {n}^3 FP32 product (inputs widened to "
                       f"FP64), {done_t:.1f} s of oracle time",
@@ -558,7 +558,8 @@ def precision_section(torch, moa, inputs, reps=5):
     C = torch.empty((m, p), device="cuda")
     rows = np.sort(np.random.default_rng(33).choice(m, 48, replace=False))
     out = {"workload": "m=8192 n=4096 p=8192, N(0,1)*10^U(-3,3) per row of A / column of B, seed 3",
-           "error": "normwise vs the FP64 oracle on 48 seeded rows (computed in the CPU leg)"}
+           "error": "normwise and worst row-wise relative error vs the FP64 oracle on 48 seeded "
+                    "rows (computed in the CPU leg)"}
     kept = {}
     paths = [("onf_f32", moa.MOA_PATH_ONF, 0), ("mfma_f32", moa.MOA_PATH_MFMA_F32, 0),
              ("split_bf16", moa.MOA_PATH_SPLIT_BF16, 0), ("fp8_1term", moa.MOA_PATH_FP8_SCALED, moa.MOA_FLAG_FP8_ONE_TERM),
@@ -576,7 +577,7 @@ def precision_section(torch, moa, inputs, reps=5):
         _, tot = timed_loop(f, reps, torch)
         ms = tot / reps
         out[name] = {"ms": round(ms, 4), "tflops": round(2.0 * m * n * p / ms / 1e9, 2),
-                     "normwise_err": None}
+                     "normwise_err": None, "max_row_rel_err": None}
     return out, (A_h, B_h, rows, kept)
 
 
@@ -1006,8 +1007,9 @@ def main():
             progress("CPU check of the sampled served results")
             serving["verified"] = cpu_verify_serving(serving_kept)
         if precision is not None and "precision" in errs:
-            for k, e in errs["precision"].items():
+            for k, (e, er) in errs["precision"].items():
                 precision[k]["normwise_err"] = e
+                precision[k]["max_row_rel_err"] = er
 
     result = {
         "metric": "TFLOP/s + % peak at N=8192 (ONF vs split-BF16 MFMA); p50/p99 GEMM latency",
