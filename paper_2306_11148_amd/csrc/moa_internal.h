@@ -177,6 +177,7 @@ struct GroupedWork {
     int64_t tiles;                      // contraction tiles over all members
     int64_t pack_items;                 // conditioning items over all members
     int variant;                        // persistent kernel
+    int64_t bounds_offset;              // XCD segment bounds, from the start of the member table
 };
 GroupedWork split_grouped_layout(const moa_gemm_desc *const *members, int count, void *workspace,
                                  void *host_staging, int variant);

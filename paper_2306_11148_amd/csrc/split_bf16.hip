@@ -18,6 +18,7 @@
 //    (blocked form of Fig. 2) with three BF16 matrix-core steps per slab and
 //    block pair, FP32 accumulation.
 #include <algorithm>
+#include <cstring>
 #include <vector>
 
 #include "moa_internal.h"
@@ -455,19 +456,38 @@ __device__ __forceinline__ void raw_tile(const GroupMember &d, int64_t i0, int64
     store_block<FM, FN>(d, i0 + wm * WM, j0 + wn * WN, acc);
 }
 
+// Work-list claims, XCD by XCD. The tile list is cut into eight segments of
+// about equal work, one per XCD (workgroups go to the XCDs round-robin by id),
+// each a run of whole members, so that the tiles sharing a member's rows and
+// columns run under one L2. A workgroup claims from its own XCD's segment
+// (counter 4 x, bounds[x] .. bounds[x + 1]) and, once that is drained, from
+// the next XCDs' in turn; `seg` counts the segments it found drained. Called
+// by one thread; -1: nothing left anywhere.
+__device__ __forceinline__ int64_t claim_tile(unsigned long long *ctr, const int64_t *bounds, int &seg) {
+    const int xcd = blockIdx.x & 7;
+    while (seg < 8) {
+        const int x = (xcd + seg) & 7;
+        const int64_t t = bounds[x] + (int64_t)atomicAdd(ctr + 4 * x, 1ull);
+        if (t < bounds[x + 1]) return t;
+        ++seg;
+    }
+    return -1;
+}
+
 template <int BM, int BN, int WM, int WN, int NST>
 __global__ __launch_bounds__(256, 2) void split_grouped_kernel(const GroupMember *__restrict__ g,
                                                                const int32_t *__restrict__ tile_owner,
-                                                               int64_t total_tiles,
+                                                               const int64_t *__restrict__ bounds,
                                                                unsigned long long *__restrict__ counter) {
     __shared__ __attribute__((aligned(1024))) uint8_t lds[RawCfg<BM, BN, WM, WN, NST>::LDS];
     __shared__ int64_t s_tile;
+    int seg = 0;
     for (;;) {
         __syncthreads();                // nobody still reads s_tile
-        if (threadIdx.x == 0) s_tile = (int64_t)atomicAdd(counter, 1ull);
+        if (threadIdx.x == 0) s_tile = claim_tile(counter, bounds, seg);
         __syncthreads();
         const int64_t tile = s_tile;
-        if (tile >= total_tiles) break;
+        if (tile < 0) break;
         const int k = __builtin_amdgcn_readfirstlane(tile_owner[tile]);
         const GroupMember &d = g[k];
         const int64_t local = tile - d.first_tile;
@@ -499,7 +519,7 @@ template <int BM, int BN, int NST, int NCV> struct ConvCfg {
     static constexpr int UNITS = 2 * (BM + BN);                // half rows of A, half columns of B
     static constexpr int LDS = NST * RAW + NCV * CONV;
     static_assert((BM == 64 || BM == 128) && (BN == 64 || BN == 128), "blocks of the split-once ring");
-    static_assert(LOADS % 4 == 0 && NST >= 2 && NST <= 3 && (NCV == 1 || NCV == 2), "shape of the split-once ring");
+    static_assert(LOADS % 4 == 0 && NST >= 2 && NST <= 4 && (NCV == 1 || NCV == 2), "shape of the split-once ring");
 };
 
 template <int BM, int BN, int NST, int NCV>
@@ -594,9 +614,10 @@ __device__ __forceinline__ void conv_tile(const GroupMember &d, int64_t i0, int6
                 dst = 2 * G::PL_A + h * BN * 16 + c * 16;
             }
             if (k0 + SLAB > n) {
+                const int live = (int)(n - k0) - 8 * h;     // live k of this unit's 8 (can be <= 0)
 #pragma unroll
                 for (int e = 0; e < 8; ++e)
-                    if (k0 + 8 * h + e >= n) x[e] = 0.0f;
+                    if (e >= live) x[e] = 0.0f;
             }
             bf16x8_t hi, lo;
             split8(x, hi, lo);
@@ -630,12 +651,14 @@ __device__ __forceinline__ void conv_tile(const GroupMember &d, int64_t i0, int6
         for (int b = 0; b < FN; ++b) acc[a][b] = f32x16_t{};
 
     auto wait_loads = [&](int slabs) {          // at most `slabs` later slabs of this wave in flight
-        switch (slabs <= 0 ? 0 : slabs >= 2 ? 2 : 1) {
+        switch (slabs <= 0 ? 0 : slabs >= 3 ? 3 : slabs) {
         case 0: __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(0)); break;
         case 1: __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(LPW)); break;
-        default: __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(2 * LPW)); break;
+        case 2: __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(2 * LPW)); break;
+        default: __builtin_amdgcn_s_waitcnt(ring::waitcnt_vm(3 * LPW)); break;
         }
     };
+    static_assert(3 * LPW <= 63, "vmcnt counts up to 63 operations");
     // Barrier that also publishes this wave's plane writes (LDS stores done).
     auto plane_barrier = [] {
         __builtin_amdgcn_s_waitcnt(0xC07F);     // lgkmcnt(0); vector-memory and export counts not waited on
@@ -649,12 +672,16 @@ __device__ __forceinline__ void conv_tile(const GroupMember &d, int64_t i0, int6
     // planes need not wait for the loads into dma, which are meant to stay in
     // flight (the explicit waits above order each slab's loads before its
     // split).
+    // The matrix-core steps of slab s are issued as soon as its fragments are
+    // in registers, before the split of slab s + 1, so that they run while
+    // this wave splits.
     auto step1 = [&](uint8_t *__restrict__ dma, const uint8_t *__restrict__ src, uint8_t *__restrict__ planes,
                      int s) {
         // one plane set: a second barrier between reading it and overwriting
         // it with the next slab
         if (s + NST < L) issue_to(dma, s + NST);
         read_frags_from(planes);
+        SplitMode::mma<FM, FN>(f, acc);
         if (s + 1 < L) {
             wait_loads((NST - 1 < L - 2 - s) ? NST - 1 : L - 2 - s);
             plane_barrier();
@@ -670,6 +697,7 @@ __device__ __forceinline__ void conv_tile(const GroupMember &d, int64_t i0, int6
         plane_barrier();
         if (s + NST < L) issue_to(dma, s + NST);
         read_frags_from(planes_r);
+        SplitMode::mma<FM, FN>(f, acc);
         if (s + 1 < L) convert_from(src, planes_w, s + 1);
     };
 
@@ -695,7 +723,6 @@ __device__ __forceinline__ void conv_tile(const GroupMember &d, int64_t i0, int6
                 plane_barrier();
                 step1(dma, src, conv, s);
             }
-            SplitMode::mma<FM, FN>(f, acc);
         }
     }
     __syncthreads();                    // every wave done with both LDS areas before the next tile
@@ -705,19 +732,20 @@ __device__ __forceinline__ void conv_tile(const GroupMember &d, int64_t i0, int6
 template <int BM, int BN, int NST, int NCV, int OCC>
 __global__ __launch_bounds__(256, OCC) void split_grouped_conv_kernel(const GroupMember *__restrict__ g,
                                                                     const int32_t *__restrict__ tile_owner,
-                                                                    int64_t total_tiles,
+                                                                    const int64_t *__restrict__ bounds,
                                                                     unsigned long long *__restrict__ counter) {
     using G = ConvCfg<BM, BN, NST, NCV>;
     __shared__ __attribute__((aligned(1024))) uint8_t lds[G::LDS];
     // the claimed tile id lives in the last plane set, which no wave writes
     // before the first barrier of a tile
     int64_t *s_tile = reinterpret_cast<int64_t *>(lds + NST * G::RAW + (NCV - 1) * G::CONV);
+    int seg = 0;
     for (;;) {
         __syncthreads();                // nobody still reads the tile id (or the planes)
-        if (threadIdx.x == 0) *s_tile = (int64_t)atomicAdd(counter, 1ull);
+        if (threadIdx.x == 0) *s_tile = claim_tile(counter, bounds, seg);
         __syncthreads();
         const int64_t tile = *s_tile;
-        if (tile >= total_tiles) break;
+        if (tile < 0) break;
         const int k = __builtin_amdgcn_readfirstlane(tile_owner[tile]);
         const GroupMember &d = g[k];
         const int64_t local = tile - d.first_tile;
@@ -859,7 +887,9 @@ hipError_t launch_split_bf16(const moa_gemm_desc &d, const Plan &plan, void *ws,
 }
 
 namespace {
-__global__ void zero_u64_kernel(unsigned long long *x) { *x = 0ull; }
+__global__ void zero_counters_kernel(unsigned long long *x) {
+    if (threadIdx.x < 8) x[4 * threadIdx.x] = 0ull;
+}
 constexpr int GB_M = 128, GW_M = 64, GW_N = 64, G_NST = 4;   // largest grouped block rows; raw-ring waves, depth
 
 // Persistent kernels of a grouped launch: block, workgroups per CU, and the
@@ -887,9 +917,13 @@ GroupedWork grouped_counts(const moa_gemm_desc *const *members, int count) {
     for (int k = 0; k < count; ++k) w.tiles += member_tiles(*members[k], 64, 64);
     return w;
 }
-// Member table, then the tile -> member table (int32).
+// Member table, then the tile -> member table (int32), then the nine
+// segment bounds of the XCD claims (int64).
 int64_t table_bytes(int count, const GroupedWork &w) {
-    return align256((int64_t)count * (int64_t)sizeof(GroupMember)) + align256(4 * w.tiles);
+    return align256((int64_t)count * (int64_t)sizeof(GroupMember)) + align256(4 * w.tiles) + 256;
+}
+int64_t bounds_offset(const moa_gemm_desc *const *members, int count) {
+    return table_bytes(count, grouped_counts(members, count)) - 256;
 }
 }  // namespace
 
@@ -930,25 +964,47 @@ int split_grouped_default_variant(const moa_gemm_desc *const *members, int count
     return best;
 }
 
-// Lays out the members (longest k walk first: the tail of the work list holds
-// the cheapest tiles) in `host_staging` for grouped kernel `variant`; returns
-// the tile count. The device member array is at ws + 256, the claim counter
-// at ws.
+// Lays out the members in `host_staging` for grouped kernel `variant`;
+// returns the tile count. Members are dealt, heaviest first (tiles x slab
+// steps), to the lightest of eight XCD segments; inside a segment they run
+// longest k walk first, so each segment's tail holds its cheapest tiles. The
+// device member array is at ws + 256, the claim counters at ws.
 GroupedWork split_grouped_layout(const moa_gemm_desc *const *members, int count, void *ws,
                                  void *host_staging, int variant) {
     (void)ws;
     const GroupedKernel gk = kGroupedK[variant];
+    auto cost = [&](int k) {
+        const moa_gemm_desc &d = *members[k];
+        return (double)member_tiles(d, gk.bm, gk.bn) * (double)((d.n + SLAB - 1) / SLAB);
+    };
+    std::vector<int> heavy(count);
+    for (int k = 0; k < count; ++k) heavy[k] = k;
+    std::stable_sort(heavy.begin(), heavy.end(), [&](int a, int b) { return cost(a) > cost(b); });
+    std::vector<int> seg_of(count);
+    double load[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    for (int k : heavy) {
+        int x = 0;
+        for (int y = 1; y < 8; ++y)
+            if (load[y] < load[x]) x = y;
+        seg_of[k] = x;
+        load[x] += cost(k);
+    }
     std::vector<int> order(count);
     for (int k = 0; k < count; ++k) order[k] = k;
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) {
+        if (seg_of[a] != seg_of[b]) return seg_of[a] < seg_of[b];
         return members[a]->n > members[b]->n;
     });
-    GroupMember *h = static_cast<GroupMember *>(host_staging);
-    int32_t *tile_owner = reinterpret_cast<int32_t *>(static_cast<char *>(host_staging) +
-                                                      align256((int64_t)count * (int64_t)sizeof(GroupMember)));
+    char *base = static_cast<char *>(host_staging);
+    GroupMember *h = reinterpret_cast<GroupMember *>(base);
+    const int64_t owner_off = align256((int64_t)count * (int64_t)sizeof(GroupMember));
+    int32_t *tile_owner = reinterpret_cast<int32_t *>(base + owner_off);
     int64_t tiles = 0;
+    int64_t bounds[9];
+    int next_seg = 0;
     for (int q = 0; q < count; ++q) {
         const moa_gemm_desc &d = *members[order[q]];
+        while (next_seg <= seg_of[order[q]]) bounds[next_seg++] = tiles;
         GroupMember g{};
         g.A = static_cast<const float *>(d.A);
         g.B = static_cast<const float *>(d.B);
@@ -963,7 +1019,10 @@ GroupedWork split_grouped_layout(const moa_gemm_desc *const *members, int count,
         tiles += mt;
         h[q] = g;
     }
-    return {tiles, 0, variant};
+    while (next_seg <= 8) bounds[next_seg++] = tiles;
+    // the bounds sit after the tile table of the largest (64 x 64) tiling
+    std::memcpy(base + bounds_offset(members, count), bounds, sizeof(bounds));
+    return {tiles, 0, variant, bounds_offset(members, count)};
 }
 
 // The device part of a grouped launch: reset the claim counter, run the
@@ -976,7 +1035,8 @@ hipError_t split_grouped_enqueue(void *ws, int count, const GroupedWork &work, h
     const GroupMember *dev_members = reinterpret_cast<const GroupMember *>(base + 256);
     const int32_t *tile_owner = reinterpret_cast<const int32_t *>(
         base + 256 + align256((int64_t)count * (int64_t)sizeof(GroupMember)));
-    hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(1), 0, st, counter);
+    const int64_t *bounds = reinterpret_cast<const int64_t *>(base + 256 + work.bounds_offset);
+    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, st, counter);
     const int v = work.variant;
     const int64_t grid = std::min<int64_t>(tiles, (int64_t)kGroupedK[v].occ * kNumCUs);   // resident blocks
     TraceScope ts(MOA_K_SPLIT_GROUPED, st);
@@ -985,23 +1045,23 @@ hipError_t split_grouped_enqueue(void *ws, int count, const GroupedWork &work, h
     switch (v) {
     case 1:
         hipLaunchKernelGGL((split_grouped_conv_kernel<128, 128, 3, 2, 2>), gr, bl, 0, st, dev_members, tile_owner,
-                           tiles, counter);
+                           bounds, counter);
         break;
     case 2:
         hipLaunchKernelGGL((split_grouped_kernel<128, 128, GW_M, GW_N, G_NST>), gr, bl, 0, st, dev_members,
-                           tile_owner, tiles, counter);
+                           tile_owner, bounds, counter);
         break;
     case 3:
         hipLaunchKernelGGL((split_grouped_conv_kernel<64, 128, 2, 1, 4>), gr, bl, 0, st, dev_members, tile_owner,
-                           tiles, counter);
+                           bounds, counter);
         break;
     case 4:
         hipLaunchKernelGGL((split_grouped_conv_kernel<128, 64, 2, 1, 4>), gr, bl, 0, st, dev_members, tile_owner,
-                           tiles, counter);
+                           bounds, counter);
         break;
     default:
         hipLaunchKernelGGL((split_grouped_conv_kernel<128, 128, 2, 1, 3>), gr, bl, 0, st, dev_members, tile_owner,
-                           tiles, counter);
+                           bounds, counter);
         break;
     }
     return hipGetLastError();

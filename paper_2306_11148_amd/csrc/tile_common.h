@@ -40,11 +40,13 @@ __device__ __forceinline__ void tile_coords(int id, int tiles_m, int tiles_n, in
 // FP32 (hi keeps the leading 8 significant bits of x), so lo is the BF16
 // nearest to the exact residual. Two values per packed 32-bit word.
 // The FP32 value of a BF16 is its 16 bits followed by 16 zero bits, so hi is
-// widened straight from the packed word (one conversion per pair).
+// widened straight from the packed word (one conversion per pair; the low
+// half moves up with a byte permute, which the compiler otherwise turns into
+// a second conversion).
 __device__ __forceinline__ void split_pair(float x0, float x1, uint32_t *hi, uint32_t *lo) {
     const bf16x2_t h = {(__bf16)x0, (__bf16)x1};
     const uint32_t hw = __builtin_bit_cast(uint32_t, h);
-    const float r0 = x0 - __builtin_bit_cast(float, hw << 16);
+    const float r0 = x0 - __builtin_bit_cast(float, __builtin_amdgcn_perm(0u, hw, 0x01000C0Cu));
     const float r1 = x1 - __builtin_bit_cast(float, hw & 0xFFFF0000u);
     const bf16x2_t l = {(__bf16)r0, (__bf16)r1};
     *hi = hw;
