@@ -159,22 +159,38 @@ __global__ __launch_bounds__(256) void mfma_f32_kernel(const float *__restrict__
         __syncthreads();
     }
 
+    // the accumulate form reads a block's 16 values of C before any store
+    auto epilogue = [&](auto acc_form) {
+        constexpr bool ACC = decltype(acc_form)::value;
 #pragma unroll
-    for (int a = 0; a < FM; ++a)
+        for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int b = 0; b < FN; ++b) {
-            const int64_t j = j0 + wn * WN + b * 32 + (lane & 31);
-            if (j >= p) continue;
+            for (int b = 0; b < FN; ++b) {
+                const int64_t j = j0 + wn * WN + b * 32 + (lane & 31);
+                if (j >= p) continue;
+                float old[16];
+                if constexpr (ACC) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t i = i0 + wm * WM + a * 32 + mfma32_row(r, lane);
-                if (i < m) {
-                    float v = acc[a][b][r];
-                    if (accumulate) v += C[i * p + j];
-                    C[i * p + j] = v;
+                    for (int r = 0; r < 16; ++r) {
+                        const int64_t i = i0 + wm * WM + a * 32 + mfma32_row(r, lane);
+                        if (i < m) old[r] = C[i * p + j];
+                    }
+                }
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int64_t i = i0 + wm * WM + a * 32 + mfma32_row(r, lane);
+                    if (i < m) {
+                        float v = acc[a][b][r];
+                        if constexpr (ACC) v += old[r];
+                        C[i * p + j] = v;
+                    }
                 }
             }
-        }
+    };
+    if (accumulate)
+        epilogue(std::true_type{});
+    else
+        epilogue(std::false_type{});
 }
 
 // ------------------------------------------------------------ record ring --

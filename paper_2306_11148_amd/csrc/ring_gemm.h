@@ -27,6 +27,7 @@
 #pragma once
 
 #include <algorithm>
+#include <type_traits>
 
 #include "moa_internal.h"
 #include "tile_common.h"
@@ -273,28 +274,45 @@ __device__ __forceinline__ void tile(const Operands &op, int64_t i0, int64_t j0,
     global_f32 *C = (global_f32 *)op.C;
     const global_i32 *row_exp = (const global_i32 *)op.row_exp;
     const global_i32 *col_exp = (const global_i32 *)op.col_exp;
+    // The accumulate form reads a block's 16 values of C before any store, so
+    // the loads are in flight together; the other forms have no trace of it.
+    auto epilogue = [&](auto acc_form) {
+        constexpr bool ACC = decltype(acc_form)::value;
 #pragma unroll
-    for (int a = 0; a < FM; ++a)
+        for (int a = 0; a < FM; ++a)
 #pragma unroll
-        for (int b = 0; b < FN; ++b) {
-            const int64_t j = j0 + wn * WN + b * 32 + (lane & 31);
-            if (j >= op.p) continue;
-            const int fj = Mode::SCALED && !partial ? col_exp[j] : 0;
+            for (int b = 0; b < FN; ++b) {
+                const int64_t j = j0 + wn * WN + b * 32 + (lane & 31);
+                if (j >= op.p) continue;
+                const int fj = Mode::SCALED && !partial ? col_exp[j] : 0;
+                float old[16];
+                if constexpr (ACC) {
 #pragma unroll
-            for (int r = 0; r < 16; ++r) {
-                const int64_t i = i0 + wm * WM + a * 32 + mfma32_row(r, lane);
-                if (i < op.m) {
-                    float v = acc[a][b][r];
-                    if (partial) {
-                        ((global_f32 *)partial)[i * op.p + j] = v;
-                        continue;
+                    for (int r = 0; r < 16; ++r) {
+                        const int64_t i = i0 + wm * WM + a * 32 + mfma32_row(r, lane);
+                        if (i < op.m) old[r] = C[i * op.p + j];
                     }
-                    if constexpr (Mode::SCALED) v = ldexpf(v, -(row_exp[i] + fj));
-                    if (op.accumulate) v += C[i * op.p + j];
-                    C[i * op.p + j] = v;
+                }
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int64_t i = i0 + wm * WM + a * 32 + mfma32_row(r, lane);
+                    if (i < op.m) {
+                        float v = acc[a][b][r];
+                        if (partial) {
+                            ((global_f32 *)partial)[i * op.p + j] = v;
+                            continue;
+                        }
+                        if constexpr (Mode::SCALED) v = ldexpf(v, -(row_exp[i] + fj));
+                        if constexpr (ACC) v += old[r];
+                        C[i * op.p + j] = v;
+                    }
                 }
             }
-        }
+    };
+    if (op.accumulate && !partial)
+        epilogue(std::true_type{});
+    else
+        epilogue(std::false_type{});
 }
 
 // Tile-id -> block mapping of a single-product launch (XCD-aware bands).

@@ -287,10 +287,12 @@ __device__ __forceinline__ void split8(const float (&x)[8], bf16x8_t &hi, bf16x8
 }
 
 // A wave's FM x FN blocks of 32 x 32 accumulators to C (rows from i0,
-// columns from j0), skipping what lies past m or p.
-template <int FM, int FN>
-__device__ __forceinline__ void store_block(const GroupMember &d, int64_t i0, int64_t j0,
-                                            const f32x16_t (&acc)[FM][FN]) {
+// columns from j0), skipping what lies past m or p. The accumulate form
+// (ACC) reads a block's 16 values of C before any store, so the loads are in
+// flight together; the overwrite form has no trace of it.
+template <bool ACC, int FM, int FN>
+__device__ __forceinline__ void store_blocks(const GroupMember &d, int64_t i0, int64_t j0,
+                                             const f32x16_t (&acc)[FM][FN]) {
     const int lane = threadIdx.x & 63;
     const int64_t p = d.p;
     ring::global_f32 *C = (ring::global_f32 *)d.C;
@@ -300,16 +302,33 @@ __device__ __forceinline__ void store_block(const GroupMember &d, int64_t i0, in
         for (int b = 0; b < FN; ++b) {
             const int64_t j = j0 + b * 32 + (lane & 31);
             if (j >= p) continue;
+            float old[16];
+            if constexpr (ACC) {
+#pragma unroll
+                for (int r = 0; r < 16; ++r) {
+                    const int64_t i = i0 + a * 32 + mfma32_row(r, lane);
+                    if (i < d.m) old[r] = C[i * p + j];
+                }
+            }
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
                 const int64_t i = i0 + a * 32 + mfma32_row(r, lane);
                 if (i < d.m) {
                     float v = acc[a][b][r];
-                    if (d.accumulate) v += C[i * p + j];
+                    if constexpr (ACC) v += old[r];
                     C[i * p + j] = v;
                 }
             }
         }
+}
+
+template <int FM, int FN>
+__device__ __forceinline__ void store_block(const GroupMember &d, int64_t i0, int64_t j0,
+                                            const f32x16_t (&acc)[FM][FN]) {
+    if (d.accumulate)
+        store_blocks<true, FM, FN>(d, i0, j0, acc);
+    else
+        store_blocks<false, FM, FN>(d, i0, j0, acc);
 }
 
 template <int BM, int BN, int WM, int WN, int NST>
