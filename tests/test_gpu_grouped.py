@@ -80,6 +80,24 @@ def test_every_grouped_kernel_bitwise_equals_single(variant, accumulate):
         assert O.rel_err(got, R) <= 1e-5
 
 
+@pytest.mark.parametrize("variant", range(moa.MOA_GROUPED_VARIANTS))
+def test_grouped_claims_with_few_members_and_empty_ones(variant):
+    """Work-list claims by XCD segment: groups of 1, 3, 8 and 9 members (fewer
+    members than segments leave segments empty; one member with m = 0 and one
+    with p = 0 own no tiles) still compute every tile of every member once."""
+    for count in (1, 3, 8, 9):
+        shapes = [tuple(int(x) for x in s) for s in inputs.grouped_shapes(count, lo=1, hi=400, seed=40 + count)]
+        if count >= 8:
+            shapes[2] = (0, shapes[2][1], shapes[2][2])
+            shapes[5] = (shapes[5][0], shapes[5][1], 0)
+        host, dev, descs = make_members(shapes, seed=40 + count)
+        moa.moa_gemm_grouped_variant(descs, variant)
+        torch.cuda.synchronize()
+        ref = singles(host, "split_bf16")
+        for k, (_, _, Ct) in enumerate(dev):
+            assert np.array_equal(Ct.cpu().numpy(), ref[k]), f"variant {variant}, {count} members, member {k}"
+
+
 def test_grouped_autotune_record_drives_launches_and_groups():
     """moa_autotune_grouped times every persistent kernel on the member list
     and records the fastest for the members' class; moa_gemm_grouped and a
