@@ -312,7 +312,11 @@ __global__ __launch_bounds__(256) void onf_kernel(const T *__restrict__ A,
 // stored. The k loop is the same ascending fma sequence per element as the
 // register-staged kernel, and the last slab stops at n (no padded steps), so
 // results are bitwise the same.
-constexpr int ONF64_NST = 4, ONF32_NST = 4;
+// Ring depth and workgroups per CU: FP32 three 16 KiB stages and three
+// workgroups per CU (the kernel fits 128 VGPRs), FP64 four stages and two
+// (its 64 FP64 accumulators per lane would spill at three).
+constexpr int ONF64_NST = 4, ONF32_NST = 3;
+template <typename T> constexpr int ring_occupancy() { return sizeof(T) == 4 ? 3 : 2; }
 
 // N elements of T as one vector register value
 template <typename T, int N> struct ExtVec { typedef T type __attribute__((ext_vector_type(N))); };
@@ -499,7 +503,7 @@ __device__ __forceinline__ void onf_ring_block(const T *__restrict__ A, const T 
 }
 
 template <typename T, int TM, int TN, int R, int VJ, int NST>
-__global__ __launch_bounds__(256, 2) void onf_ring_kernel(const T *__restrict__ A, const T *__restrict__ B,
+__global__ __launch_bounds__(256, ring_occupancy<T>()) void onf_ring_kernel(const T *__restrict__ A, const T *__restrict__ B,
                                                          T *__restrict__ C, int64_t m, int64_t n, int64_t p,
                                                          int accumulate, int vec_c) {
     __shared__ __attribute__((aligned(1024))) uint8_t lds[NST * (TM * 64 + 64 / sizeof(T) * TN * sizeof(T))];

@@ -167,14 +167,14 @@ def test_onf_f64_ring_plan():
 
 def test_onf_f32_ring_plan():
     """FP32 products likewise: the direct-load ring kernel (variant 4, 16-k
-    slabs, 128 x 128 blocks of 8 x 8 per lane, four-stage ring) once every
+    slabs, 128 x 128 blocks of 8 x 8 per lane, three-stage ring) once every
     CU gets a block and the operands are row-major; else the largest
     register-staged block that still gives every CU one."""
     F32, ONF = moa.MOA_F32, moa.MOA_PATH_ONF
     q = lambda m, n, p, fl=0: moa.moa_plan_query(_desc(m, n, p, F32, ONF, flags=fl))  # noqa: E731
     big = q(8192, 8192, 8192)
     assert big["variant"] == 4 and (big["tile_m"], big["tile_n"], big["tile_k"]) == (128, 128, 16)
-    assert (big["lane_m"], big["lane_n"]) == (8, 8) and big["lds_bytes"] == 4 * 16384
+    assert (big["lane_m"], big["lane_n"]) == (8, 8) and big["lds_bytes"] == 3 * 16384
     assert q(2048, 2048, 2048)["variant"] == 4                   # 256 blocks
     assert q(2048, 2048, 1920)["variant"] == 2                   # 240 blocks of 128 x 128: 64 x 128
     assert q(8192, 8192, 8192, moa.MOA_FLAG_A_COL)["variant"] == 3
