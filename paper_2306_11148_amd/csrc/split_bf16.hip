@@ -693,14 +693,20 @@ __device__ __forceinline__ void conv_tile(const GroupMember &d, int64_t i0, int6
     // split).
     // The matrix-core steps of slab s are issued as soon as its fragments are
     // in registers, before the split of slab s + 1, so that they run while
-    // this wave splits.
+    // this wave splits; the wave issues them at raised priority, so that the
+    // other workgroups' split work does not hold them back.
+    auto mma_step = [&] {
+        __builtin_amdgcn_s_setprio(1);
+        SplitMode::mma<FM, FN>(f, acc);
+        __builtin_amdgcn_s_setprio(0);
+    };
     auto step1 = [&](uint8_t *__restrict__ dma, const uint8_t *__restrict__ src, uint8_t *__restrict__ planes,
                      int s) {
         // one plane set: a second barrier between reading it and overwriting
         // it with the next slab
         if (s + NST < L) issue_to(dma, s + NST);
         read_frags_from(planes);
-        SplitMode::mma<FM, FN>(f, acc);
+        mma_step();
         if (s + 1 < L) {
             wait_loads((NST - 1 < L - 2 - s) ? NST - 1 : L - 2 - s);
             plane_barrier();
@@ -716,7 +722,7 @@ __device__ __forceinline__ void conv_tile(const GroupMember &d, int64_t i0, int6
         plane_barrier();
         if (s + NST < L) issue_to(dma, s + NST);
         read_frags_from(planes_r);
-        SplitMode::mma<FM, FN>(f, acc);
+        mma_step();
         if (s + 1 < L) convert_from(src, planes_w, s + 1);
     };
 
