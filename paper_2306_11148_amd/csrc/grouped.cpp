@@ -5,8 +5,10 @@
 // shared tile list; scaled-FP8 members likewise, one sequence per term count.
 // Members on the ONF and FP32 matrix-core paths run as single launches, in
 // order, on the same stream. The member tables of the persistent launches
-// travel to the device through pinned staging buffers that are recycled once
-// the stream has consumed them.
+// are written to pinned, coherent staging buffers, mapped into the device's
+// address space, that are recycled once the stream has consumed them: the split-BF16
+// launch reads its table from there with a small kernel, the FP8 launches
+// copy theirs.
 #include <algorithm>
 #include <mutex>
 #include <vector>
@@ -18,6 +20,7 @@ namespace {
 
 struct Staging {
     void *ptr = nullptr;
+    void *dev = nullptr;                // ptr in the device's address space (null: not mapped)
     size_t bytes = 0;
     hipEvent_t done = nullptr;
 };
@@ -38,8 +41,12 @@ moa_status staging_acquire(size_t bytes, Staging *out) {
     }
     Staging s;
     s.bytes = bytes < 4096 ? 4096 : bytes;
-    hipError_t e = hipHostMalloc(&s.ptr, s.bytes, hipHostMallocDefault);
+    hipError_t e = hipHostMalloc(&s.ptr, s.bytes, hipHostMallocMapped | hipHostMallocCoherent);
     if (e != hipSuccess) return fail(MOA_ERR_NOMEM, "pinned staging of %zu bytes: %s", s.bytes, hipGetErrorString(e));
+    if (hipHostGetDevicePointer(&s.dev, s.ptr, 0) != hipSuccess) {
+        s.dev = nullptr;
+        (void)hipGetLastError();        // not mapped: the table goes up by a copy
+    }
     e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
     if (e != hipSuccess) {
         (void)hipHostFree(s.ptr);
@@ -127,7 +134,7 @@ moa_status run_list(const std::vector<const moa_gemm_desc *> &list, int64_t desc
         if (!arena) scratch_free(ws, stream);
         return s;
     }
-    const hipError_t e = launch(list.data(), cnt, ws, st.ptr);
+    const hipError_t e = launch(list.data(), cnt, ws, st.ptr, st.dev);
     staging_release(st, stream);
     if (!arena) scratch_free(ws, stream);
     if (e != hipSuccess) return hip_fail(e, "grouped launch");
@@ -192,15 +199,15 @@ moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t st
     }
     moa_status s = run_list(
         pt.split, split_grouped_desc_bytes(pt.split.data(), (int)pt.split.size()), split_grouped_workspace_bytes,
-        [&](const moa_gemm_desc *const *m, int c, void *ws, void *host) {
-            return launch_split_grouped(m, c, sv, ws, host, stream);
+        [&](const moa_gemm_desc *const *m, int c, void *ws, void *host, void *host_dev) {
+            return launch_split_grouped(m, c, sv, ws, host, host_dev, stream);
         },
         stream, arena);
     for (int two = 0; two < 2 && s == MOA_OK; ++two)
         s = run_list(
             pt.fp8[two], fp8_grouped_desc_bytes((int)pt.fp8[two].size()),
             [&](const moa_gemm_desc *const *m, int c) { return fp8_grouped_workspace_bytes(m, c, two != 0); },
-            [&](const moa_gemm_desc *const *m, int c, void *ws, void *host) {
+            [&](const moa_gemm_desc *const *m, int c, void *ws, void *host, void *) {
                 return launch_fp8_grouped(m, c, two != 0, ws, host, stream);
             },
             stream, arena);

@@ -157,8 +157,10 @@ int64_t split_grouped_workspace_bytes(const moa_gemm_desc *const *members, int c
 // (else it runs as a single launch).
 bool split_grouped_fits(const moa_gemm_desc &d);
 int64_t split_grouped_desc_bytes(const moa_gemm_desc *const *members, int count);
+// `host_staging_dev`: the staging buffer's address in the device's address
+// space (null: the table goes up by a copy instead of being read in place).
 hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, int variant, void *workspace,
-                                void *host_staging, hipStream_t stream);
+                                void *host_staging, const void *host_staging_dev, hipStream_t stream);
 // Persistent split-BF16 kernels of a grouped launch (blocks 128 x 128 split
 // once with three or two blocks per CU, 128 x 128 split in registers,
 // 64 x 128, 128 x 64), the static rule's choice among them, and the choice a
@@ -177,7 +179,7 @@ struct GroupedWork {
     int64_t tiles;                      // contraction tiles over all members
     int64_t pack_items;                 // conditioning items over all members
     int variant;                        // persistent kernel
-    int64_t bounds_offset;              // XCD segment bounds, from the start of the member table
+    int64_t table_used;                 // bytes of the member table the launch reads (a prefix)
 };
 GroupedWork split_grouped_layout(const moa_gemm_desc *const *members, int count, void *workspace,
                                  void *host_staging, int variant);

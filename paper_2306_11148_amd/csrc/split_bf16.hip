@@ -942,14 +942,11 @@ GroupedWork grouped_counts(const moa_gemm_desc *const *members, int count) {
     for (int k = 0; k < count; ++k) w.tiles += member_tiles(*members[k], 64, 64);
     return w;
 }
-// Member table, then the tile -> member table (int32), then the nine
-// segment bounds of the XCD claims (int64).
-int64_t table_bytes(int count, const GroupedWork &w) {
-    return align256((int64_t)count * (int64_t)sizeof(GroupMember)) + align256(4 * w.tiles) + 256;
-}
-int64_t bounds_offset(const moa_gemm_desc *const *members, int count) {
-    return table_bytes(count, grouped_counts(members, count)) - 256;
-}
+// Member table, then the nine segment bounds of the XCD claims (int64, 256
+// bytes), then the tile -> member table (int32): the part a launch uses is
+// one prefix of the table.
+int64_t members_bytes(int count) { return align256((int64_t)count * (int64_t)sizeof(GroupMember)); }
+int64_t table_bytes(int count, const GroupedWork &w) { return members_bytes(count) + 256 + align256(4 * w.tiles); }
 }  // namespace
 
 // The raw ring addresses a tile's rows of A with 32-bit offsets (128 rows of
@@ -1022,8 +1019,7 @@ GroupedWork split_grouped_layout(const moa_gemm_desc *const *members, int count,
     });
     char *base = static_cast<char *>(host_staging);
     GroupMember *h = reinterpret_cast<GroupMember *>(base);
-    const int64_t owner_off = align256((int64_t)count * (int64_t)sizeof(GroupMember));
-    int32_t *tile_owner = reinterpret_cast<int32_t *>(base + owner_off);
+    int32_t *tile_owner = reinterpret_cast<int32_t *>(base + members_bytes(count) + 256);
     int64_t tiles = 0;
     int64_t bounds[9];
     int next_seg = 0;
@@ -1045,23 +1041,20 @@ GroupedWork split_grouped_layout(const moa_gemm_desc *const *members, int count,
         h[q] = g;
     }
     while (next_seg <= 8) bounds[next_seg++] = tiles;
-    // the bounds sit after the tile table of the largest (64 x 64) tiling
-    std::memcpy(base + bounds_offset(members, count), bounds, sizeof(bounds));
-    return {tiles, 0, variant, bounds_offset(members, count)};
+    std::memcpy(base + members_bytes(count), bounds, sizeof(bounds));
+    return {tiles, 0, variant, members_bytes(count) + 256 + 4 * tiles};
 }
 
-// The device part of a grouped launch: reset the claim counter, run the
-// persistent contraction. Contains no allocation, copy or memset, so it can
-// be captured in a graph and replayed.
-hipError_t split_grouped_enqueue(void *ws, int count, const GroupedWork &work, hipStream_t st) {
+namespace {
+// The persistent contraction of a grouped launch whose member table and
+// cleared claim counters are in place.
+hipError_t launch_persistent(void *ws, int count, const GroupedWork &work, hipStream_t st) {
     const int64_t tiles = work.tiles;
     char *base = static_cast<char *>(ws);
     unsigned long long *counter = reinterpret_cast<unsigned long long *>(base);
     const GroupMember *dev_members = reinterpret_cast<const GroupMember *>(base + 256);
-    const int32_t *tile_owner = reinterpret_cast<const int32_t *>(
-        base + 256 + align256((int64_t)count * (int64_t)sizeof(GroupMember)));
-    const int64_t *bounds = reinterpret_cast<const int64_t *>(base + 256 + work.bounds_offset);
-    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, st, counter);
+    const int64_t *bounds = reinterpret_cast<const int64_t *>(base + 256 + members_bytes(count));
+    const int32_t *tile_owner = reinterpret_cast<const int32_t *>(base + 256 + members_bytes(count) + 256);
     const int v = work.variant;
     const int64_t grid = std::min<int64_t>(tiles, (int64_t)kGroupedK[v].occ * kNumCUs);   // resident blocks
     TraceScope ts(MOA_K_SPLIT_GROUPED, st);
@@ -1092,15 +1085,43 @@ hipError_t split_grouped_enqueue(void *ws, int count, const GroupedWork &work, h
     return hipGetLastError();
 }
 
+// Uploads the used prefix of a member table (n16 16-byte words) straight from
+// pinned host memory mapped into the device's address space, and clears the
+// claim counters: one small kernel in place of a copy-engine transfer, whose
+// hand-offs to and from the compute queue cost more than the copy.
+__global__ __launch_bounds__(256) void stage_table_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                          int64_t n16, unsigned long long *__restrict__ counters) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+    if (blockIdx.x == 0 && threadIdx.x < 8) counters[4 * threadIdx.x] = 0ull;
+}
+}  // namespace
+
+// The device part of a grouped launch whose member table is already on the
+// device: clear the claim counters, run the persistent contraction. Contains
+// no allocation, copy or memset, so it can be captured in a graph and
+// replayed.
+hipError_t split_grouped_enqueue(void *ws, int count, const GroupedWork &work, hipStream_t st) {
+    hipLaunchKernelGGL(zero_counters_kernel, dim3(1), dim3(64), 0, st, static_cast<unsigned long long *>(ws));
+    return launch_persistent(ws, count, work, st);
+}
+
 hipError_t launch_split_grouped(const moa_gemm_desc *const *members, int count, int variant, void *ws,
-                                void *host_staging, hipStream_t st) {
+                                void *host_staging, const void *host_staging_dev, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     const GroupedWork work = split_grouped_layout(members, count, ws, host_staging, variant);
     char *base = static_cast<char *>(ws);
-    hipError_t e = hipMemcpyAsync(base + 256, host_staging, (size_t)split_grouped_desc_bytes(members, count),
-                                  hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return e;
-    return split_grouped_enqueue(ws, count, work, st);
+    if (!host_staging_dev) {
+        hipError_t e = hipMemcpyAsync(base + 256, host_staging, (size_t)work.table_used, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return e;
+        return split_grouped_enqueue(ws, count, work, st);
+    }
+    const int64_t n16 = (work.table_used + 15) / 16;
+    const int64_t blocks = std::min<int64_t>((n16 + 255) / 256, 64);
+    hipLaunchKernelGGL(stage_table_kernel, dim3((unsigned)blocks), dim3(256), 0, st,
+                       static_cast<const uint4 *>(host_staging_dev), reinterpret_cast<uint4 *>(base + 256), n16,
+                       reinterpret_cast<unsigned long long *>(base));
+    return launch_persistent(ws, count, work, st);
 }
 
 hipError_t launch_split_only(const float *X, int64_t count, uint16_t *hi, uint16_t *lo,
