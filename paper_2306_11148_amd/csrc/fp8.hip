@@ -779,13 +779,32 @@ hipError_t fp8_grouped_enqueue(void *ws, int count, bool two, const Fp8GroupWork
     return hipGetLastError();
 }
 
+namespace {
+// The member table straight from pinned host memory mapped into the device's
+// address space (n16 16-byte words): a kernel in place of a copy-engine
+// transfer and its hand-offs to and from the compute queue.
+__global__ __launch_bounds__(256) void table_from_host_kernel(const uint4 *__restrict__ src, uint4 *__restrict__ dst,
+                                                              int64_t n16) {
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += stride) dst[i] = src[i];
+}
+}  // namespace
+
 hipError_t launch_fp8_grouped(const moa_gemm_desc *const *members, int count, bool two, void *ws,
-                              void *host_staging, hipStream_t st) {
+                              void *host_staging, const void *host_staging_dev, hipStream_t st) {
     if (count <= 0) return hipSuccess;
     const Fp8GroupWork w = fp8_grouped_layout(members, count, two, ws, host_staging);
-    hipError_t e = hipMemcpyAsync(static_cast<char *>(ws) + w.table_offset, host_staging,
-                                  (size_t)fp8_grouped_desc_bytes(count), hipMemcpyHostToDevice, st);
-    if (e != hipSuccess) return e;
+    char *table = static_cast<char *>(ws) + w.table_offset;
+    const int64_t bytes = fp8_grouped_desc_bytes(count);
+    if (host_staging_dev) {
+        const int64_t n16 = (bytes + 15) / 16;
+        hipLaunchKernelGGL(table_from_host_kernel, dim3((unsigned)std::min<int64_t>((n16 + 255) / 256, 64)),
+                           dim3(256), 0, st, static_cast<const uint4 *>(host_staging_dev),
+                           reinterpret_cast<uint4 *>(table), n16);
+    } else {
+        hipError_t e = hipMemcpyAsync(table, host_staging, (size_t)bytes, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return e;
+    }
     return fp8_grouped_enqueue(ws, count, two, w, st);
 }
 

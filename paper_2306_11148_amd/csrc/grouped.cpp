@@ -6,9 +6,8 @@
 // Members on the ONF and FP32 matrix-core paths run as single launches, in
 // order, on the same stream. The member tables of the persistent launches
 // are written to pinned, coherent staging buffers, mapped into the device's
-// address space, that are recycled once the stream has consumed them: the split-BF16
-// launch reads its table from there with a small kernel, the FP8 launches
-// copy theirs.
+// address space, that are recycled once the stream has consumed them; each
+// launch reads its table from there with a small kernel.
 #include <algorithm>
 #include <mutex>
 #include <vector>
@@ -40,7 +39,7 @@ moa_status staging_acquire(size_t bytes, Staging *out) {
         }
     }
     Staging s;
-    s.bytes = bytes < 4096 ? 4096 : bytes;
+    s.bytes = bytes < 4096 ? 4096 : (bytes + 255) / 256 * 256;   // whole 16-byte words for the table kernels
     hipError_t e = hipHostMalloc(&s.ptr, s.bytes, hipHostMallocMapped | hipHostMallocCoherent);
     if (e != hipSuccess) return fail(MOA_ERR_NOMEM, "pinned staging of %zu bytes: %s", s.bytes, hipGetErrorString(e));
     if (hipHostGetDevicePointer(&s.dev, s.ptr, 0) != hipSuccess) {
@@ -207,8 +206,8 @@ moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t st
         s = run_list(
             pt.fp8[two], fp8_grouped_desc_bytes((int)pt.fp8[two].size()),
             [&](const moa_gemm_desc *const *m, int c) { return fp8_grouped_workspace_bytes(m, c, two != 0); },
-            [&](const moa_gemm_desc *const *m, int c, void *ws, void *host, void *) {
-                return launch_fp8_grouped(m, c, two != 0, ws, host, stream);
+            [&](const moa_gemm_desc *const *m, int c, void *ws, void *host, void *host_dev) {
+                return launch_fp8_grouped(m, c, two != 0, ws, host, host_dev, stream);
             },
             stream, arena);
     return s;

@@ -208,7 +208,7 @@ Fp8GroupWork fp8_grouped_layout(const moa_gemm_desc *const *members, int count, 
 hipError_t fp8_grouped_enqueue(void *workspace, int count, bool two_term, const Fp8GroupWork &work,
                                hipStream_t stream);
 hipError_t launch_fp8_grouped(const moa_gemm_desc *const *members, int count, bool two_term, void *workspace,
-                              void *host_staging, hipStream_t stream);
+                              void *host_staging, const void *host_staging_dev, hipStream_t stream);
 
 hipError_t launch_split_only(const float *X, int64_t count, uint16_t *hi, uint16_t *lo,
                              hipStream_t stream);
