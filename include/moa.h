@@ -232,7 +232,7 @@ moa_status moa_gemm_grouped(const moa_gemm_desc *descs, int64_t count,
  *   3  64 x 128 blocks, split once, four per CU;
  *   4  128 x 64 blocks, split once, four per CU.
  * moa_gemm_grouped and moa_group_create use the autotuner's record for the
- * members' class if there is one, else the static rule: the block among 0, 3
+ * members' class if there is one, else the static rule: the block among 2, 3
  * and 4 with the fewest slab steps over the members, weighted by the
  * measured time of one slab step of that block. moa_gemm_grouped_variant runs
  * moa_gemm_grouped with `variant` forced (-1: that choice); MOA_ERR_INVALID

@@ -369,11 +369,11 @@ def test_grouped_static_rule_and_group_records(tmp_path):
     (count and median m, n, p as ceil(log2)) overrides the rule."""
     moa.moa_autotune_clear()
     q = lambda ds: moa.moa_grouped_plan_query(ds)                     # noqa: E731
-    assert q(_members([(128, 300, 128)] * 8))["variant"] == 0          # 64-blocks would double the tiles
+    assert q(_members([(128, 300, 128)] * 8))["variant"] == 2          # 64-blocks would double the tiles
     assert q(_members([(64, 300, 256)] * 8))["variant"] == 3           # 128 rows would be half empty
     assert q(_members([(256, 300, 64)] * 8))["variant"] == 4
     c4 = [tuple(int(x) for x in s) for s in inputs.grouped_shapes(512, 32, 2048, seed=4)]
-    assert q(_members(c4)) == {"variant": 0, "tuned": 0, "persistent_members": 512}
+    assert q(_members(c4)) == {"variant": 2, "tuned": 0, "persistent_members": 512}
     mixed = _members([(64, 300, 256)] * 4)
     mixed[1].flags = moa.MOA_FLAG_A_COL
     assert q(mixed)["persistent_members"] == 3
