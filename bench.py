@@ -92,6 +92,8 @@ def parse():
     ap.add_argument("--profile-case", type=str, default=None, choices=sorted(PROFILE_CASES),
                     help="launch one path on its workload --warmup + --steps times and print the per-launch "
                          "times (the program rocprofv3 counter passes run)")
+    ap.add_argument("--grouped-variant", type=int, default=-1,
+                    help="with --profile-case grouped_c4: force this persistent kernel (-1: the planner's)")
     return ap.parse_args()
 
 
@@ -801,7 +803,8 @@ def split_variants(args, torch, moa):
 
 def profile_grouped(args, torch, moa):
     """--profile-case grouped_c4: the batching workload's grouped launch
-    (planner-chosen persistent kernel), --warmup untimed and --steps timed."""
+    (the planner's persistent kernel, or --grouped-variant's), --warmup
+    untimed and --steps timed."""
     import ctypes
     from paper_2306_11148_amd import inputs
     shapes = inputs.grouped_shapes(512, 32, 2048, seed=4)
@@ -817,14 +820,15 @@ def profile_grouped(args, torch, moa):
     L, st = moa.lib(), torch.cuda.current_stream().cuda_stream
 
     def f():
-        if L.moa_gemm_grouped(arr, len(descs), st) != 0:
+        if L.moa_gemm_grouped_variant(arr, len(descs), args.grouped_variant, st) != 0:
             raise RuntimeError(moa.moa_last_error())
     for _ in range(args.warmup):
         f()
     per, tot = timed_loop(f, args.steps, torch)
     flop = float(sum(2.0 * m * n * p for m, n, p in shapes))
     print(json.dumps({"profile_case": "grouped_c4", "members": len(descs), "flop": flop,
-                      "plan": moa.moa_grouped_plan_query(descs), "launches": args.steps,
+                      "plan": moa.moa_grouped_plan_query(descs), "forced_variant": args.grouped_variant,
+                      "launches": args.steps,
                       "ms_per_launch": round(tot / args.steps, 4), "per_launch_ms": [round(x, 4) for x in per],
                       "tflops": round(flop / (tot / args.steps) / 1e9, 2)}), flush=True)
     del keep
