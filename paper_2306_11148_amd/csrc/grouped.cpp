@@ -146,13 +146,13 @@ struct Partition {
     std::vector<const moa_gemm_desc *> single, split, fp8[2];
 };
 
-Partition partition(const moa_gemm_desc *descs, int64_t count) {
+Partition partition(const moa_gemm_desc *descs, int64_t count, const char *split_k = nullptr) {
     Partition pt;
     for (int64_t g = 0; g < count; ++g) {
         const moa_gemm_desc &d = descs[g];
         if (d.m == 0 || d.p == 0) continue;
         const moa_path path = resolve_path(d);
-        if (has_col_operand(d) || plans_split_k(d))   // the persistent launches take
+        if (has_col_operand(d) || (split_k ? split_k[g] != 0 : plans_split_k(d)))   // the persistent launches take
             pt.single.push_back(&d);                  // row-major, unsplit members
         else if (path == MOA_PATH_SPLIT_BF16 && split_grouped_fits(d))
             pt.split.push_back(&d);
@@ -179,8 +179,8 @@ int64_t grouped_scratch_bytes(const moa_gemm_desc *descs, int64_t count) {
 }
 
 moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t stream, ScratchArena *arena,
-                       int split_variant) {
-    const Partition pt = partition(descs, count);
+                       int split_variant, const char *split_k) {
+    const Partition pt = partition(descs, count, split_k);
     const int sv = pt.split.empty() ? 0 : split_grouped_choose(pt.split.data(), (int)pt.split.size(), split_variant,
                                                                nullptr);
     for (const moa_gemm_desc *d : pt.single) {
@@ -219,14 +219,20 @@ using namespace moa;
 
 namespace {
 
-moa_status check_grouped_args(const moa_gemm_desc *descs, int64_t count) {
+// Validates every member and plans it once; `split_k` (optional) receives
+// whether each member's plan splits k.
+moa_status check_grouped_args(const moa_gemm_desc *descs, int64_t count, std::vector<char> *split_k = nullptr) {
     if (count < 0) return fail(MOA_ERR_INVALID, "negative count");
     if (count > 0 && !descs) return fail(MOA_ERR_INVALID, "null descriptor array");
+    if (split_k) split_k->assign((size_t)count, 0);
     for (int64_t g = 0; g < count; ++g) {
         moa_status s = validate(descs[g], true);
         if (s != MOA_OK) return s;
         Plan pl;
-        if (descs[g].m > 0 && descs[g].p > 0 && (s = make_plan(descs[g], &pl)) != MOA_OK) return s;
+        if (descs[g].m > 0 && descs[g].p > 0) {
+            if ((s = make_plan(descs[g], &pl)) != MOA_OK) return s;
+            if (split_k) (*split_k)[(size_t)g] = pl.split_k > 1 ? 1 : 0;
+        }
     }
     return check_group_overlap(descs, count);
 }
@@ -242,9 +248,10 @@ extern "C" moa_status moa_gemm_grouped_variant(const moa_gemm_desc *descs, int64
     try {
         if (variant < -1 || variant >= split_grouped_variant_count())
             return fail(MOA_ERR_INVALID, "grouped variant %d out of range", (int)variant);
-        moa_status s = check_grouped_args(descs, count);
+        std::vector<char> split_k;
+        moa_status s = check_grouped_args(descs, count, &split_k);
         if (s != MOA_OK) return s;
-        return run_grouped(descs, count, static_cast<hipStream_t>(stream), nullptr, variant);
+        return run_grouped(descs, count, static_cast<hipStream_t>(stream), nullptr, variant, split_k.data());
     } catch (...) {
         return fail(MOA_ERR_DEVICE, "internal error");
     }
@@ -253,9 +260,10 @@ extern "C" moa_status moa_gemm_grouped_variant(const moa_gemm_desc *descs, int64
 extern "C" moa_status moa_grouped_plan_query(const moa_gemm_desc *descs, int64_t count, int32_t *variant,
                                              int32_t *tuned, int64_t *persistent_members) {
     try {
-        moa_status s = check_grouped_args(descs, count);
+        std::vector<char> split_k;
+        moa_status s = check_grouped_args(descs, count, &split_k);
         if (s != MOA_OK) return s;
-        const Partition pt = partition(descs, count);
+        const Partition pt = partition(descs, count, split_k.data());
         bool t = false;
         const int v = pt.split.empty() ? -1 : split_grouped_choose(pt.split.data(), (int)pt.split.size(), -1, &t);
         if (variant) *variant = v;
@@ -271,9 +279,10 @@ extern "C" moa_status moa_autotune_grouped(const moa_gemm_desc *descs, int64_t c
                                            int32_t *chosen, double *best_ms) {
     try {
         if (reps < 1) return fail(MOA_ERR_INVALID, "reps must be >= 1");
-        moa_status s = check_grouped_args(descs, count);
+        std::vector<char> split_k;
+        moa_status s = check_grouped_args(descs, count, &split_k);
         if (s != MOA_OK) return s;
-        const Partition pt = partition(descs, count);
+        const Partition pt = partition(descs, count, split_k.data());
         if (pt.split.empty()) return fail(MOA_ERR_UNSUPPORTED, "no member runs in the persistent split-BF16 launch");
         hipStream_t st = static_cast<hipStream_t>(stream);
         hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -286,9 +295,9 @@ extern "C" moa_status moa_autotune_grouped(const moa_gemm_desc *descs, int64_t c
         int best = -1;
         double best_t = 0;
         for (int v = 0; v < split_grouped_variant_count() && s == MOA_OK; ++v) {
-            s = run_grouped(descs, count, st, nullptr, v);                     // warm-up
+            s = run_grouped(descs, count, st, nullptr, v, split_k.data());     // warm-up
             if (s == MOA_OK && (e = hipEventRecord(e0, st)) != hipSuccess) s = hip_fail(e, "autotune timing");
-            for (int r = 0; r < reps && s == MOA_OK; ++r) s = run_grouped(descs, count, st, nullptr, v);
+            for (int r = 0; r < reps && s == MOA_OK; ++r) s = run_grouped(descs, count, st, nullptr, v, split_k.data());
             if (s == MOA_OK && (e = hipEventRecord(e1, st)) != hipSuccess) s = hip_fail(e, "autotune timing");
             if (s == MOA_OK && (e = hipEventSynchronize(e1)) != hipSuccess) s = hip_fail(e, "autotune timing");
             float ms = 0;

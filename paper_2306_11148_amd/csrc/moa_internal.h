@@ -239,8 +239,10 @@ struct ScratchArena {
     int64_t size = 0;
     int64_t used = 0;
 };
+// `split_k` (optional): per member, whether its plan splits k (as the caller
+// already planned it), so that members are not planned twice.
 moa_status run_grouped(const moa_gemm_desc *descs, int64_t count, hipStream_t stream,
-                       ScratchArena *arena = nullptr, int split_variant = -1);
+                       ScratchArena *arena = nullptr, int split_variant = -1, const char *split_k = nullptr);
 // Bytes of scratch run_grouped takes from an arena for these members.
 int64_t grouped_scratch_bytes(const moa_gemm_desc *descs, int64_t count);
 // Scratch bytes of one product under its plan (0 for empty products).
