@@ -80,6 +80,8 @@ def parse():
                          "one JSON line per rate")
     ap.add_argument("--serve-window", type=int, default=0,
                     help="with --serve-rates: the server's batching window in microseconds (0: none)")
+    ap.add_argument("--serve-max-group", type=int, default=64,
+                    help="with --serve-rates: the most requests the server puts in one grouped launch")
     ap.add_argument("--no-grouped", action="store_true")
     ap.add_argument("--no-precision", action="store_true")
     ap.add_argument("--split-variants", type=str, default=None,
@@ -370,7 +372,8 @@ def grouped_section(torch, moa, inputs, reps=10):
                          "frac": round(roof_ms / best, 4)}}
 
 
-def serving_section(torch, moa, inputs, rate, seconds, max_requests, seed=5, verify_share=0.01, window_us=0):
+def serving_section(torch, moa, inputs, rate, seconds, max_requests, seed=5, verify_share=0.01, window_us=0,
+                    max_group=64):
     """Open-loop Poisson arrivals at `rate` req/s: min(rate * seconds,
     max_requests) synthetic requests, m, p log-uniform [64, 4096], n
     log-uniform [64, 8192], 70% split-BF16 / 30% two-term FP8. Each request is
@@ -391,7 +394,8 @@ def serving_section(torch, moa, inputs, rate, seconds, max_requests, seed=5, ver
     path_of = lambda q: "split_bf16" if split[q] else "fp8"   # noqa: E731
     budget = 200 << 30
     reserve = 16 << 30       # taken at creation: no allocation while requests run
-    srv = moa.moa_serve_create(budget, slots=4, max_group=16, batch_window_us=window_us, pool_reserve_bytes=reserve)
+    srv = moa.moa_serve_create(budget, slots=4, max_group=max_group, batch_window_us=window_us,
+                               pool_reserve_bytes=reserve)
     kept, infos, sched_ns = {}, [None] * count, [0] * count
     try:
         # untimed warm-up: the first shapes once through the server (code
@@ -449,14 +453,15 @@ def serving_section(torch, moa, inputs, rate, seconds, max_requests, seed=5, ver
     span = (max(i["t_done_ns"] for i in infos) - sched_ns[0]) / 1e9
     bad = sum(1 for i in infos if i["status"] != 0)
     groups = np.array([i["group_size"] for i in infos])
-    out = {"rate_req_per_s": rate, "batch_window_us": window_us, "requests": count, "seconds": round(span, 3),
+    out = {"rate_req_per_s": rate, "batch_window_us": window_us, "max_group": max_group, "requests": count,
+           "seconds": round(span, 3),
            "latency_ms": {"p50": round(float(np.percentile(body, 50)), 3),
                           "p99": round(float(np.percentile(body, 99)), 3),
                           "mean": round(float(body.mean()), 3)},
            "tflops": round(flops / span / 1e12, 2), "failed": bad,
            "mean_group_size": round(float(groups.mean()), 2),
            "mix": "70% split-BF16 / 30% two-term FP8, synthetic requests (operands drawn on the device "
-                  "at admission), HBM budget 200 GB, 4 slots, groups <= 16",
+                  "at admission), HBM budget 200 GB, 4 slots, groups <= " + str(max_group),
            "first_5pct_discarded": skip,
            "device_memory": {"budget_bytes": budget, "pool_reserve_bytes": reserve,
                              "peak_pool_bytes": stats["peak_pool_bytes"],
@@ -911,7 +916,7 @@ def main():
             progress(f"serving loop at {rate:.0f} req/s: up to {args.serve_seconds:.1f} s or "
                      f"{args.serve_requests} requests")
             res, kept = serving_section(torch, moa, inputs, rate, args.serve_seconds, args.serve_requests,
-                                        window_us=args.serve_window)
+                                        window_us=args.serve_window, max_group=args.serve_max_group)
             res["verified"] = cpu_verify_serving(kept)
             print(json.dumps({"serving_sweep": res}), flush=True)
         return
