@@ -41,11 +41,17 @@ moa_status staging_acquire(size_t bytes, Staging *out) {
     Staging s;
     s.bytes = bytes < 4096 ? 4096 : (bytes + 255) / 256 * 256;   // whole 16-byte words for the table kernels
     hipError_t e = hipHostMalloc(&s.ptr, s.bytes, hipHostMallocMapped | hipHostMallocCoherent);
-    if (e != hipSuccess) return fail(MOA_ERR_NOMEM, "pinned staging of %zu bytes: %s", s.bytes, hipGetErrorString(e));
-    if (hipHostGetDevicePointer(&s.dev, s.ptr, 0) != hipSuccess) {
+    if (e == hipSuccess) {
+        if (hipHostGetDevicePointer(&s.dev, s.ptr, 0) != hipSuccess) {
+            s.dev = nullptr;            // not mapped: the table goes up by a copy
+            (void)hipGetLastError();
+        }
+    } else {                            // no coherent mapping: plain pinned memory and a copy
+        (void)hipGetLastError();
         s.dev = nullptr;
-        (void)hipGetLastError();        // not mapped: the table goes up by a copy
+        e = hipHostMalloc(&s.ptr, s.bytes, hipHostMallocDefault);
     }
+    if (e != hipSuccess) return fail(MOA_ERR_NOMEM, "pinned staging of %zu bytes: %s", s.bytes, hipGetErrorString(e));
     e = hipEventCreateWithFlags(&s.done, hipEventDisableTiming);
     if (e != hipSuccess) {
         (void)hipHostFree(s.ptr);
